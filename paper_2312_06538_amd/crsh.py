@@ -1,0 +1,178 @@
+"""ctypes binding of libcrsh.so: the C-ABI of ``include/crsh.h`` under the same
+names.  Argument marshalling only -- every step runs in the HIP kernels.
+
+Device memory comes from torch tensors (``tensor.data_ptr()``) and streams
+from ``torch.cuda.current_stream().cuda_stream``; nothing here computes.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcrsh.so")
+
+MAX_LEVELS = 16
+MAX_LIGHTS = 4
+MAX_BUNDLE = 32
+MAX_MERGE = 16
+
+OK, ERR_INVALID, ERR_CAPACITY, ERR_HIP = 0, 1, 2, 3
+OVERFLOW_RAYS, OVERFLOW_NODES, OVERFLOW_PAIRS = 1, 2, 4
+RAY_SHADOW, RAY_REFLECT, RAY_REFRACT = 1, 2, 4
+
+vp = C.c_void_p
+
+
+class CrshError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"crsh status {status}: {msg}")
+        self.status = status
+
+
+class Meta(C.Structure):
+    _fields_ = [("n_rays", C.c_uint32), ("n_levels", C.c_uint32),
+                ("level_off", C.c_uint32 * MAX_LEVELS), ("level_cnt", C.c_uint32 * MAX_LEVELS),
+                ("status", C.c_uint32), ("reserved", C.c_uint32),
+                ("pairs", C.c_uint64 * MAX_LEVELS), ("hits", C.c_uint64 * MAX_LEVELS),
+                ("tests", C.c_uint64 * MAX_LEVELS),
+                ("mesh_tests", C.c_uint64), ("mesh_hits", C.c_uint64), ("final_tests", C.c_uint64),
+                ("rays_required", C.c_uint64), ("nodes_required", C.c_uint64)]
+
+
+class Gbuf(C.Structure):
+    _fields_ = [("px", vp), ("py", vp), ("pz", vp), ("nx", vp), ("ny", vp), ("nz", vp), ("mat", vp),
+                ("w", C.c_int32), ("h", C.c_int32)]
+
+
+class Raygen(C.Structure):
+    _fields_ = [("n_lights", C.c_int32), ("lights", (C.c_float * 3) * MAX_LIGHTS), ("eye", C.c_float * 3),
+                ("mat_flags", vp), ("mat_ior", vp), ("n_mats", C.c_int32), ("ray_types", C.c_uint32),
+                ("eps_off", C.c_float), ("eps_shadow", C.c_float),
+                ("lo", C.c_float * 3), ("inv_ext", C.c_float * 3)]
+
+
+class Rays(C.Structure):
+    _fields_ = [("ox", vp), ("oy", vp), ("oz", vp), ("dx", vp), ("dy", vp), ("dz", vp), ("tmax", vp),
+                ("pix", vp), ("capacity", C.c_uint32)]
+
+
+class Nodes(C.Structure):
+    _fields_ = [(k, vp) for k in ("cx", "cy", "cz", "r", "ax", "ay", "az", "c", "s", "tan", "sec")] + \
+               [("capacity", C.c_uint32)]
+
+
+class Scene(C.Structure):
+    _fields_ = [("v", vp * 9), ("m", C.c_uint32), ("mesh_first", vp), ("mesh_count", vp), ("msph", vp),
+                ("n_mesh", C.c_uint32)]
+
+
+class Pairs(C.Structure):
+    _fields_ = [("tri", vp), ("node", vp), ("capacity", C.c_uint64)]
+
+
+class Hits(C.Structure):
+    _fields_ = [("tkey", vp), ("tri", vp), ("t", vp), ("u", vp), ("v", vp), ("capacity", C.c_uint32)]
+
+
+PairTable = Pairs * MAX_LEVELS
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it was not built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2312_06538_amd/build.py "
+                               "(the CRSH path runs only in its HIP kernels)")
+        # torch ships its own HIP runtime under the same soname; load it first so
+        # that libcrsh.so binds to that one runtime (one set of streams and memory)
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        L.crsh_last_error.restype = C.c_char_p
+        L.crsh_last_error.argtypes = []
+        L.crsh_workspace_size.restype = C.c_size_t
+        L.crsh_workspace_size.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64]
+        L.crsh_meta_reset.restype = st
+        L.crsh_meta_reset.argtypes = [vp, vp]
+        L.crsh_read_meta.restype = st
+        L.crsh_read_meta.argtypes = [vp, C.POINTER(Meta), vp]
+        L.crsh_hash.restype = st
+        L.crsh_hash.argtypes = [C.POINTER(Gbuf), C.POINTER(Raygen), C.POINTER(Rays), vp, vp, vp, vp,
+                                C.c_size_t, vp]
+        L.crsh_sort.restype = st
+        L.crsh_sort.argtypes = [vp, vp, vp, vp, C.c_uint32, vp, vp, C.c_size_t, vp]
+        L.crsh_build.restype = st
+        L.crsh_build.argtypes = [C.POINTER(Rays), vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Nodes),
+                                 C.POINTER(Rays), vp, vp]
+        L.crsh_traverse.restype = st
+        L.crsh_traverse.argtypes = [C.POINTER(Nodes), C.POINTER(Scene), C.c_uint32, C.c_uint32, C.c_int32,
+                                    C.c_int32, PairTable, vp, vp, C.c_size_t, vp]
+        L.crsh_hits_reset.restype = st
+        L.crsh_hits_reset.argtypes = [C.POINTER(Hits), vp]
+        L.crsh_profile_next.restype = st
+        L.crsh_profile_next.argtypes = [C.c_char_p, C.c_int32, vp, vp]
+        L.crsh_closest_hit.restype = st
+        L.crsh_closest_hit.argtypes = [C.POINTER(Rays), vp, C.c_int32, C.POINTER(Pairs), C.POINTER(Scene),
+                                       C.c_float, C.POINTER(Hits), vp, vp, C.c_size_t, vp]
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return lib().crsh_last_error().decode()
+
+
+def _check(status, allow_capacity=False):
+    if status == OK or (allow_capacity and status == ERR_CAPACITY):
+        return status
+    raise CrshError(status, last_error())
+
+
+def crsh_workspace_size(max_rays, max_tris, max_meshes, max_nodes, max_pairs):
+    return int(lib().crsh_workspace_size(max_rays, max_tris, max_meshes, max_nodes, max_pairs))
+
+
+def crsh_meta_reset(meta, stream):
+    return _check(lib().crsh_meta_reset(meta, stream))
+
+
+def crsh_read_meta(meta, stream, allow_capacity=True):
+    out = Meta()
+    st = lib().crsh_read_meta(meta, C.byref(out), stream)
+    _check(st, allow_capacity=allow_capacity)
+    return out, st
+
+
+def crsh_hash(gbuf, raygen, rays, keys, ids, meta, ws, ws_bytes, stream):
+    return _check(lib().crsh_hash(C.byref(gbuf), C.byref(raygen), C.byref(rays), keys, ids, meta, ws, ws_bytes,
+                                  stream))
+
+
+def crsh_sort(keys_in, ids_in, keys_out, ids_out, capacity, meta, ws, ws_bytes, stream):
+    return _check(lib().crsh_sort(keys_in, ids_in, keys_out, ids_out, capacity, meta, ws, ws_bytes, stream))
+
+
+def crsh_build(rays, sorted_ids, bundle, merge, levels, nodes, sorted_rays, meta, stream):
+    return _check(lib().crsh_build(C.byref(rays), sorted_ids, bundle, merge, levels, C.byref(nodes),
+                                   C.byref(sorted_rays), meta, stream))
+
+
+def crsh_traverse(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, stream):
+    return _check(lib().crsh_traverse(C.byref(nodes), C.byref(scene), tri_begin, tri_end, bundle, merge, pairs,
+                                      meta, ws, ws_bytes, stream))
+
+
+def crsh_hits_reset(hits, stream):
+    return _check(lib().crsh_hits_reset(C.byref(hits), stream))
+
+
+def crsh_closest_hit(sorted_rays, sorted_ids, bundle, level1, scene, t_min, hits, meta, ws, ws_bytes, stream):
+    return _check(lib().crsh_closest_hit(C.byref(sorted_rays), sorted_ids, bundle, C.byref(level1),
+                                         C.byref(scene), t_min, C.byref(hits), meta, ws, ws_bytes, stream))
+
+
+def crsh_profile_next(kernel, occurrence, start_event, stop_event):
+    """Arm the one-shot timer; events are hipEvent_t handles (torch.cuda.Event.cuda_event)."""
+    return _check(lib().crsh_profile_next(kernel.encode(), occurrence, start_event, stop_event))

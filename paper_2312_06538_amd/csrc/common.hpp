@@ -1,0 +1,184 @@
+// Shared device helpers of the CRSH HIP library (gfx950, wave64).
+//
+// Floating point: every kernel is compiled with -ffp-contract=off and
+// correctly rounded float32 division and square root, so each written
+// operation rounds once (IEEE binary32, nearest-even) and sums of three terms
+// are evaluated as (a + b) + c.  That fixed order is what makes keys, nodes
+// and pairs reproducible bit for bit by any other conforming implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "crsh.h"
+
+namespace crsh {
+
+constexpr int WAVE = 64;
+
+// ------------------------------------------------------------------ float3
+struct f3 {
+    float x, y, z;
+};
+
+__device__ __forceinline__ f3 mk(float x, float y, float z)
+{
+    f3 r;
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    return r;
+}
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ f3 operator*(f3 a, float s) { return mk(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ f3 operator/(f3 a, float s) { return mk(a.x / s, a.y / s, a.z / s); }
+__device__ __forceinline__ f3 operator-(f3 a) { return mk(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b)
+{
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float len(f3 a) { return sqrtf(dot(a, a)); }
+__device__ __forceinline__ float fmax2(float a, float b) { return a > b ? a : b; }
+
+// Conservativeness margins (see the hierarchy build): spheres grow by
+// SPHERE_PAD * (r + max|c|) per union, cones by CONE_PAD radians per change.
+// Bisectors of sums shorter than BISECT_MIN are too inaccurate: full cone.
+constexpr float SPHERE_PAD = 0x1p-20f;
+constexpr float CONE_PAD = 0x1p-16f;
+constexpr float BISECT_MIN = 0.25f;
+constexpr float INSIDE_MARGIN = 0x1p-20f;
+constexpr float NEAR_PARALLEL = 0x1p-10f;
+constexpr float DET_EPS = 1e-12f;
+
+// --------------------------------------------------------------- wave ops
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ uint32_t rank_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// inclusive prefix sum over the 64 lanes of a wave
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T o = __shfl_up(v, d, WAVE);
+        if (l >= (uint32_t)d) v += o;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// Exclusive block scan of one value per thread; returns the exclusive prefix
+// and the block total.  scratch: NWAVES entries of LDS.
+template <typename T, int NWAVES>
+__device__ __forceinline__ T block_excl_scan(T v, T *scratch, T &total)
+{
+    const uint32_t l = lane_id();
+    const uint32_t w = threadIdx.x / WAVE;
+    T inc = wave_incl_scan(v);
+    if (l == WAVE - 1) scratch[w] = inc;
+    __syncthreads();
+    T before = 0;
+    T tot = 0;
+#pragma unroll
+    for (int i = 0; i < NWAVES; ++i) {
+        T s = scratch[i];
+        if ((uint32_t)i < w) before += s;
+        tot += s;
+    }
+    total = tot;
+    __syncthreads();
+    return before + inc - v;
+}
+
+// ------------------------------------------------ decoupled look-back scan
+// Tiles publish their own count first (flag 1), then the inclusive prefix
+// once known (flag 2); a tile walks back over its predecessors until it meets
+// an inclusive prefix.  Tiles take their index from an atomic counter in
+// launch order, so every tile waited on has already started and publishes
+// its count without waiting itself: the walk always ends.
+constexpr uint64_t LB_AGG = 1ull << 62;
+constexpr uint64_t LB_INC = 2ull << 62;
+constexpr uint64_t LB_MASK = (1ull << 62) - 1;
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by one thread of the tile; returns the exclusive prefix of `count`.
+__device__ __forceinline__ uint64_t lookback(uint64_t *flags, uint32_t tile, uint64_t count)
+{
+    if (tile == 0) {
+        lb_store(&flags[0], LB_INC | count);
+        return 0;
+    }
+    lb_store(&flags[tile], LB_AGG | count);
+    uint64_t excl = 0;
+    int64_t j = (int64_t)tile - 1;
+    while (j >= 0) {
+        uint64_t f = lb_load(&flags[j]);
+        if ((f & ~LB_MASK) == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += f & LB_MASK;
+        if ((f & ~LB_MASK) == LB_INC) break;
+        --j;
+    }
+    lb_store(&flags[tile], LB_INC | (excl + count));
+    return excl;
+}
+
+// ------------------------------------------------------------- workspace
+// Every stage carves its scratch from the start of the caller's workspace;
+// these are the byte counts each stage needs.
+constexpr uint32_t SORT_TILE = 4096;      // keys per sort tile
+constexpr uint32_t SORT_PASSES = 4;       // 8-bit digits of a 32-bit key
+constexpr uint32_t HASH_BLOCK = 256;      // pixels per hash block
+constexpr uint32_t LEVEL_TILE = 256;      // parent pairs per traversal tile
+
+__host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t sort_ws_bytes(uint32_t cap);
+size_t hash_ws_bytes(uint64_t pixels);
+size_t trav_ws_bytes(uint32_t m, uint64_t top_items, uint64_t max_pairs);
+size_t hit_ws_bytes(uint32_t m);
+
+// launch helpers
+void set_error(const char *fmt, ...);
+crsh_status hip_check(hipError_t e, const char *what);
+
+// One-shot kernel timer (crsh_profile_next): prof_begin returns true when
+// this launch is the armed one and has recorded the start event.
+bool prof_begin(const char *kernel, hipStream_t s);
+void prof_end(bool armed, hipStream_t s);
+
+struct prof_scope {
+    bool on;
+    hipStream_t s;
+    prof_scope(const char *k, hipStream_t st) : on(prof_begin(k, st)), s(st) {}
+    ~prof_scope() { prof_end(on, s); }
+};
+
+}  // namespace crsh

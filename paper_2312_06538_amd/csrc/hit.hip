@@ -1,0 +1,232 @@
+// Stage 5: final intersection tests and closest hit (Sec. 3.3.8).
+//
+// k_hit_prep   triangles repacked as 3 x float4 (v0, e1 = v1 - v0,
+//              e2 = v2 - v0): one 48-byte fetch per test instead of nine
+//              scattered loads; e1, e2 are the same single roundings the
+//              test would make.
+// k_hit        persistent waves over the level-1 pairs; a group of G lanes
+//              (G = bundle rounded up to a power of two) takes one pair, one
+//              lane per ray of its leaf, so a leaf's rays are read
+//              contiguously from the sorted ray arrays.  A hit lowers the
+//              ray's 64-bit (t bits, triangle) key with an atomic minimum:
+//              positive floats order like their bit patterns, so the minimum
+//              is the closest hit with ties to the lower triangle id.
+// k_hit_final  one thread per sorted ray: decode the key, recompute u, v with
+//              the same test, write the result at the ray id.
+#include "common.hpp"
+
+namespace crsh {
+
+__global__ void k_hit_prep(const float *__restrict__ v0x, const float *__restrict__ v0y,
+                           const float *__restrict__ v0z, const float *__restrict__ v1x,
+                           const float *__restrict__ v1y, const float *__restrict__ v1z,
+                           const float *__restrict__ v2x, const float *__restrict__ v2y,
+                           const float *__restrict__ v2z, uint32_t m, float4 *tri)
+{
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x) {
+        float ax = v0x[t], ay = v0y[t], az = v0z[t];
+        float e1x = v1x[t] - ax, e1y = v1y[t] - ay, e1z = v1z[t] - az;
+        float e2x = v2x[t] - ax, e2y = v2y[t] - ay, e2z = v2z[t] - az;
+        tri[3 * t + 0] = make_float4(ax, ay, az, e1x);
+        tri[3 * t + 1] = make_float4(e1y, e1z, e2x, e2y);
+        tri[3 * t + 2] = make_float4(e2z, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+struct tri_t {
+    f3 v0, e1, e2;
+};
+
+__device__ __forceinline__ tri_t load_tri(const float4 *__restrict__ tri, uint32_t t)
+{
+    float4 a = tri[3 * t + 0];
+    float4 b = tri[3 * t + 1];
+    float4 c = tri[3 * t + 2];
+    tri_t r;
+    r.v0 = mk(a.x, a.y, a.z);
+    r.e1 = mk(a.w, b.x, b.y);
+    r.e2 = mk(b.z, b.w, c.x);
+    return r;
+}
+
+// Two-sided Moller-Trumbore, accepted for t_min < t < tmax.
+__device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float tmax, const tri_t &tr, float &tt,
+                                                float &uu, float &vv)
+{
+    f3 p = cross(D, tr.e2);
+    float det = dot(tr.e1, p);
+    if (!(fabsf(det) >= DET_EPS)) return false;
+    float inv = 1.0f / det;
+    f3 T = O - tr.v0;
+    float u = dot(T, p) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) return false;
+    f3 q = cross(T, tr.e1);
+    float v = dot(D, q) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
+    float t = dot(tr.e2, q) * inv;
+    if (!(t > t_min && t < tmax)) return false;
+    tt = t;
+    uu = u;
+    vv = v;
+    return true;
+}
+
+struct sorted_rays {
+    const float *ox, *oy, *oz, *dx, *dy, *dz, *tmax;
+};
+
+__global__ __launch_bounds__(256) void k_hit(sorted_rays R, const float4 *__restrict__ tri,
+                                             const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
+                                             uint64_t cap1, uint32_t B, uint32_t log2G, float t_min,
+                                             unsigned long long *tkey, crsh_meta *meta, uint32_t ray_cap, uint32_t m)
+{
+    __shared__ uint64_t s_red[256 / WAVE];
+    const uint32_t n = min(meta->n_rays, ray_cap);
+    uint64_t np = meta->n_levels ? meta->pairs[0] : 0;
+    np = np < cap1 ? np : cap1;
+    const uint32_t l = lane_id();
+    const uint32_t G = 1u << log2G;
+    const uint32_t slot = l >> log2G;        // pair slot of this lane in the wave
+    const uint32_t j = l & (G - 1);          // ray of the leaf
+    const uint32_t per_wave = WAVE >> log2G;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
+    uint64_t tests = 0;
+    for (uint64_t q0 = wave * per_wave; q0 < np; q0 += nwaves * per_wave) {
+        const uint64_t q = q0 + slot;
+        if (q >= np || j >= B) continue;
+        const uint32_t t = ptri[q];
+        const uint32_t s = pnode[q] * B + j;
+        if (s >= n || t >= m) continue;
+        ++tests;
+        const tri_t tr = load_tri(tri, t);
+        const f3 O = mk(R.ox[s], R.oy[s], R.oz[s]);
+        const f3 D = mk(R.dx[s], R.dy[s], R.dz[s]);
+        float th, uh, vh;
+        if (moller_trumbore(O, D, t_min, R.tmax[s], tr, th, uh, vh)) {
+            unsigned long long key = ((unsigned long long)__float_as_uint(th) << 32) | t;
+            atomicMin(&tkey[s], key);
+        }
+    }
+    tests = wave_sum(tests);
+    if (l == 0) s_red[threadIdx.x / WAVE] = tests;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t tot = 0;
+        for (int i = 0; i < 256 / WAVE; ++i) tot += s_red[i];
+        if (tot) atomicAdd((unsigned long long *)&meta->final_tests, (unsigned long long)tot);
+    }
+}
+
+struct hit_out {
+    int32_t *tri;
+    float *t, *u, *v;
+};
+
+__global__ void k_hit_final(sorted_rays R, const float4 *__restrict__ tri, const uint32_t *__restrict__ sorted_ids,
+                            float t_min, const unsigned long long *tkey, hit_out out, const crsh_meta *meta,
+                            uint32_t ray_cap, uint32_t m)
+{
+    const uint32_t n = min(meta->n_rays, ray_cap);
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+        const unsigned long long key = tkey[s];
+        const uint32_t id = sorted_ids[s];
+        if (id >= ray_cap) continue;    // ids come from the sort: never taken
+        int32_t best = -1;
+        float th = 0.0f, uh = 0.0f, vh = 0.0f;
+        if (key != ~0ull && (uint32_t)(key & 0xFFFFFFFFull) < m) {
+            const uint32_t t = (uint32_t)(key & 0xFFFFFFFFull);
+            const f3 O = mk(R.ox[s], R.oy[s], R.oz[s]);
+            const f3 D = mk(R.dx[s], R.dy[s], R.dz[s]);
+            if (moller_trumbore(O, D, t_min, R.tmax[s], load_tri(tri, t), th, uh, vh)) {
+                best = (int32_t)t;
+            } else {                     // cannot happen: same inputs, same operations
+                best = (int32_t)t;
+                th = __uint_as_float((uint32_t)(key >> 32));
+            }
+        }
+        out.tri[id] = best;
+        out.t[id] = th;
+        out.u[id] = uh;
+        out.v[id] = vh;
+    }
+}
+
+__global__ void k_tkey_fill(unsigned long long *tkey, uint32_t n)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) tkey[i] = ~0ull;
+}
+
+}  // namespace crsh
+
+using namespace crsh;
+
+extern "C" crsh_status crsh_hits_reset(crsh_hits *hits, hipStream_t stream)
+{
+    if (!hits || !hits->tkey) {
+        set_error("crsh_hits_reset: NULL argument");
+        return CRSH_ERR_INVALID;
+    }
+    uint32_t g = std::min<uint32_t>((hits->capacity + 255) / 256, 4096);
+    if (g == 0) g = 1;
+    k_tkey_fill<<<g, 256, 0, stream>>>(hits->tkey, hits->capacity);
+    return hip_check(hipGetLastError(), "crsh_hits_reset launch");
+}
+
+extern "C" crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
+                                        const crsh_pairs *level1, const crsh_scene *scene, float t_min,
+                                        crsh_hits *hits, crsh_meta *meta, void *ws, size_t ws_bytes,
+                                        hipStream_t stream)
+{
+    if (!sorted || !sorted_ids || !level1 || !scene || !hits || !meta || !ws) {
+        set_error("crsh_closest_hit: NULL argument");
+        return CRSH_ERR_INVALID;
+    }
+    if (bundle < 1 || bundle > CRSH_MAX_BUNDLE) {
+        set_error("crsh_closest_hit: bundle must be in [1, %d]", CRSH_MAX_BUNDLE);
+        return CRSH_ERR_INVALID;
+    }
+    if (!sorted->ox || !sorted->oy || !sorted->oz || !sorted->dx || !sorted->dy || !sorted->dz ||
+        !sorted->tmax || !hits->tkey || !hits->tri || !hits->t || !hits->u || !hits->v ||
+        (level1->capacity && (!level1->tri || !level1->node))) {
+        set_error("crsh_closest_hit: incomplete arrays");
+        return CRSH_ERR_INVALID;
+    }
+    for (int k = 0; k < 9; ++k)
+        if (!scene->v[k] && scene->m) {
+            set_error("crsh_closest_hit: missing vertex array");
+            return CRSH_ERR_INVALID;
+        }
+    if (hits->capacity < sorted->capacity) {
+        set_error("crsh_closest_hit: hit capacity below the ray capacity");
+        return CRSH_ERR_INVALID;
+    }
+    if (ws_bytes < hit_ws_bytes(scene->m)) {
+        set_error("crsh_closest_hit: workspace too small (%zu < %zu)", ws_bytes, hit_ws_bytes(scene->m));
+        return CRSH_ERR_INVALID;
+    }
+    float4 *tri = (float4 *)ws;
+    const float *const *v = scene->v;
+    if (scene->m) {
+        uint32_t g = std::min<uint32_t>((scene->m + 255) / 256, 2048);
+        k_hit_prep<<<g, 256, 0, stream>>>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], scene->m, tri);
+    }
+    uint32_t log2G = 0;
+    while ((1u << log2G) < (uint32_t)bundle) ++log2G;
+    sorted_rays R{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
+    if (level1->capacity)
+        {
+            prof_scope ps("k_hit", stream);
+            k_hit<<<2048, 256, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity, (uint32_t)bundle,
+                                        log2G, t_min, hits->tkey, meta, sorted->capacity, scene->m);
+        }
+    uint32_t g = std::min<uint32_t>((sorted->capacity + 255) / 256, 4096);
+    if (g == 0) g = 1;
+    hit_out o{hits->tri, hits->t, hits->u, hits->v};
+    {
+        prof_scope ps("k_hit_final", stream);
+        k_hit_final<<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta, sorted->capacity,
+                                           scene->m);
+    }
+    return hip_check(hipGetLastError(), "crsh_closest_hit launch");
+}

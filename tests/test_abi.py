@@ -1,0 +1,117 @@
+"""The C-ABI library without a GPU: it loads, exports every entry point that
+include/crsh.h declares, its ctypes mirrors match the C layouts, and
+argument errors are reported on the host before anything is launched."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2312_06538_amd import crsh as X
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "crsh.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(crsh_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = X.lib()
+    names = declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.check_output(["nm", "-D", "--defined-only", X.LIB_PATH]).decode()
+    exported = set(re.findall(r" T (crsh_\w+)", out))
+    assert set(names) <= exported
+
+
+LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "crsh.h"
+#define S(t) printf(#t " %zu\n", sizeof(t));
+#define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
+int main(void) {
+  S(crsh_meta) O(crsh_meta, status) O(crsh_meta, pairs) O(crsh_meta, hits) O(crsh_meta, tests)
+  O(crsh_meta, final_tests) O(crsh_meta, nodes_required)
+  S(crsh_gbuf) O(crsh_gbuf, mat) O(crsh_gbuf, w)
+  S(crsh_raygen) O(crsh_raygen, mat_flags) O(crsh_raygen, ray_types) O(crsh_raygen, inv_ext)
+  S(crsh_rays) O(crsh_rays, pix) O(crsh_rays, capacity)
+  S(crsh_nodes) O(crsh_nodes, sec) O(crsh_nodes, capacity)
+  S(crsh_scene) O(crsh_scene, m) O(crsh_scene, msph) O(crsh_scene, n_mesh)
+  S(crsh_pairs) O(crsh_pairs, capacity)
+  S(crsh_hits) O(crsh_hits, v) O(crsh_hits, capacity)
+  return 0;
+}
+"""
+
+
+def test_ctypes_layouts_match_header(tmp_path):
+    c = tmp_path / "layout.c"
+    c.write_text(LAYOUT_C)
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", "/opt/rocm/include", str(c), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    mirror = {"crsh_meta": X.Meta, "crsh_gbuf": X.Gbuf, "crsh_raygen": X.Raygen, "crsh_rays": X.Rays,
+              "crsh_nodes": X.Nodes, "crsh_scene": X.Scene, "crsh_pairs": X.Pairs, "crsh_hits": X.Hits}
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(mirror[t], f).offset == int(val), key
+        else:
+            assert ctypes.sizeof(mirror[key]) == int(val), key
+
+
+def test_invalid_arguments_are_rejected_on_the_host():
+    L = X.lib()
+    assert L.crsh_meta_reset(None, None) == X.ERR_INVALID
+    assert "NULL" in X.last_error()
+    r = X.Rays(*([1] * 8), 100)
+    n = X.Nodes(*([1] * 11), 100)
+    # bundle 0 / merge 1 / levels 0
+    for B, F, lv in ((0, 4, 4), (8, 1, 4), (8, 4, 0), (33, 4, 4), (8, 17, 4), (8, 4, 17)):
+        st = L.crsh_build(ctypes.byref(r), 1, B, F, lv, ctypes.byref(n), ctypes.byref(r), 1, None)
+        assert st == X.ERR_INVALID, (B, F, lv)
+    assert "bundle" in X.last_error()
+    # sort: aliasing, oversized capacity, small workspace
+    assert L.crsh_sort(8, 16, 8, 24, 10, 1, 1, 1 << 30, None) == X.ERR_INVALID
+    assert L.crsh_sort(8, 16, 32, 24, 1 << 30, 1, 1, 1 << 40, None) == X.ERR_INVALID
+    assert L.crsh_sort(8, 16, 32, 24, 1000, 1, 1, 10, None) == X.ERR_INVALID
+    assert "workspace" in X.last_error()
+    # hash: empty primary-hit buffer
+    g = X.Gbuf(*([1] * 7), 0, 4)
+    rg = X.Raygen()
+    assert L.crsh_hash(ctypes.byref(g), ctypes.byref(rg), ctypes.byref(r), 1, 1, 1, 1, 1 << 20, None) == \
+        X.ERR_INVALID
+    # traverse: triangle batch outside the scene
+    sc = X.Scene((X.vp * 9)(*([1] * 9)), 10, 1, 1, 1, 1)
+    pt = X.PairTable()
+    pt[0] = X.Pairs(1, 1, 10)
+    assert L.crsh_traverse(ctypes.byref(n), ctypes.byref(sc), 5, 11, 8, 4, pt, 1, 1, 1 << 30, None) == \
+        X.ERR_INVALID
+    assert "batch" in X.last_error()
+    # closest hit: bundle out of range
+    h = X.Hits(1, 1, 1, 1, 1, 100)
+    assert L.crsh_closest_hit(ctypes.byref(r), 1, 0, ctypes.byref(pt[0]), ctypes.byref(sc), ctypes.c_float(1e-4),
+                              ctypes.byref(h), 1, 1, 1 << 30, None) == X.ERR_INVALID
+    assert L.crsh_profile_next(None, 0, 1, 1) == X.ERR_INVALID
+
+
+def test_workspace_size_covers_every_stage():
+    a = X.crsh_workspace_size(1 << 20, 1000, 10, 1 << 16, 1 << 20)
+    b = X.crsh_workspace_size(1 << 21, 1000, 10, 1 << 16, 1 << 20)
+    assert b > a > (1 << 20) * 8
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(X, "_lib", None)
+    monkeypatch.setattr(X, "LIB_PATH", "/nonexistent/libcrsh.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        X.lib()

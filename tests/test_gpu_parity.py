@@ -1,0 +1,232 @@
+"""GPU parity: every HIP stage against the oracle, through the C-ABI.
+
+Bar: bit-exact keys, ids, rays, sorted order, node arrays and pair levels
+(in order), exact counters, exact closest-hit triangle ids; t, u, v within
+1e-5 relative (they come out bit-equal, since both sides do the same
+binary32 operations).  Sizes: the 128x128 shadow workload, and reduced
+versions of the 1024x1024 and 1920x1080 workloads that span many tiles and
+leave ragged tails.
+"""
+import numpy as np
+import pytest
+
+from conftest import small, oracle_run, workload
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["c1", "c2s", "c3s"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_06538_amd import crsh
+    crsh.lib()
+
+
+def _gu():
+    import gpu_util
+    return gpu_util
+
+
+def _same(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return a.shape == b.shape and np.array_equal(a.view(np.uint32) if a.dtype == np.float32 else a,
+                                                 b.view(np.uint32) if b.dtype == np.float32 else b)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_hash_bit_exact(name):
+    base, kw = small(name)
+    print(f"[hash] {name}", flush=True)
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)["hash"]
+    g = _gu().gpu_hash(wl)
+    assert g["status"] == 0
+    assert g["n"] == o["n"]
+    assert _same(g["keys"], o["keys"])
+    assert _same(g["ids"], o["ids"])
+    for k in O.RAY_FIELDS:
+        assert _same(g["rays"][k], o["rays"][k]), k
+    assert _same(g["rays"]["pix"], o["rays"]["pix"])
+
+
+@pytest.mark.parametrize("n,span", [(0, 7), (1, 7), (4095, 1 << 32), (4096, 3), (4097, 1 << 20),
+                                    (50000, 1 << 32), (123457, 97), (300001, 1 << 16)])
+def test_sort_bit_exact(n, span):
+    print(f"[sort] n={n} span={span}", flush=True)
+    rng = np.random.default_rng(n + span % 1000)
+    keys = rng.integers(0, span, size=n, dtype=np.uint64).astype(np.uint32)
+    ids = np.arange(n, dtype=np.uint32)
+    ok, oi = O.sort_rays(keys, ids)
+    gk, gi = _gu().gpu_sort(keys, ids, capacity=n + 1000)
+    assert _same(gk, ok) and _same(gi, oi)
+
+
+def test_sort_digit_skipping_and_values():
+    gu = _gu()
+    rng = np.random.default_rng(5)
+    # every key equal: all passes skipped, plain copy
+    keys = np.full(10000, 0xDEADBEEF, np.uint32)
+    ids = rng.permutation(10000).astype(np.uint32)
+    gk, gi = gu.gpu_sort(keys, ids)
+    assert _same(gi, ids) and _same(gk, keys)
+    # only the top byte varies: three passes skipped
+    keys = (rng.integers(0, 256, 20000).astype(np.uint32) << 24) | 0x00123456
+    ok, oi = O.sort_rays(keys, ids[:0].tolist() or np.arange(20000, dtype=np.uint32))
+    gk, gi = gu.gpu_sort(keys, np.arange(20000, dtype=np.uint32))
+    assert _same(gk, ok) and _same(gi, oi)
+    # arbitrary values travel with their keys, equal keys keep input order
+    keys = rng.integers(0, 40, 30000).astype(np.uint32)
+    vals = rng.permutation(30000).astype(np.uint32)
+    ok, oi = O.sort_rays(keys, vals)
+    gk, gi = gu.gpu_sort(keys, vals)
+    assert _same(gk, ok) and _same(gi, oi)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_sort_of_workload_keys(name):
+    base, kw = small(name)
+    o = oracle_run(base, **kw)
+    gk, gi = _gu().gpu_sort(o["hash"]["keys"], o["hash"]["ids"])
+    assert _same(gk, o["sorted_keys"]) and _same(gi, o["sorted_ids"])
+
+
+def _check_tree(g, o):
+    assert g["n_levels"] == o["n_levels"]
+    assert _same(g["level_cnt"], o["level_cnt"])
+    assert _same(g["level_off"], o["level_off"])
+    for k in O.NODE_FIELDS:
+        assert _same(g["nodes"][k], o["nodes"][k]), k
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_build_bit_exact(name):
+    base, kw = small(name)
+    print(f"[build] {name}", flush=True)
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    g = _gu().gpu_build(o["hash"]["rays"], o["sorted_ids"], wl.B, wl.F, wl.n)
+    _check_tree(g, o["tree"])
+    sid = o["sorted_ids"].astype(np.int64)
+    for k in O.RAY_FIELDS:
+        assert _same(g["sorted"][k], o["hash"]["rays"][k][sid]), k
+
+
+@pytest.mark.parametrize("B,F,n", [(1, 2, 3), (4, 2, 6), (5, 7, 4), (8, 8, 2), (32, 3, 3), (16, 16, 2),
+                                   (16, 4, 1)])
+def test_build_shapes(B, F, n):
+    base, kw = small("c2s")
+    print(f"[build-shape] B={B} F={F} n={n}", flush=True)
+    o = oracle_run(base, **kw)
+    ot = O.build_tree(o["hash"]["rays"], o["sorted_ids"], B, F, n)
+    g = _gu().gpu_build(o["hash"]["rays"], o["sorted_ids"], B, F, n)
+    _check_tree(g, ot)
+
+
+def test_build_empty_and_tiny():
+    gu = _gu()
+    r = {k: np.zeros(3, np.float32) for k in O.RAY_FIELDS}
+    r["dz"][:] = 1.0
+    r["pix"] = np.zeros(3, np.uint32)
+    g = gu.gpu_build(r, np.arange(3, dtype=np.uint32), 8, 4, 4, n_rays=0)
+    assert g["n_levels"] == 0
+    g = gu.gpu_build(r, np.arange(3, dtype=np.uint32), 8, 4, 4, n_rays=3)
+    o = O.build_tree(r, np.arange(3, dtype=np.uint32), 8, 4, 4)
+    _check_tree(g, o)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_traverse_bit_exact(name):
+    base, kw = small(name)
+    print(f"[traverse] {name}", flush=True)
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    cap = max(len(t) for t, _ in o["trav"]["pairs"].values()) + 4096
+    g = _gu().gpu_traverse(o["tree"], wl.scene, wl.B, wl.F, capacity=cap)
+    assert g["status"] == 0
+    tr = o["trav"]
+    for lv in tr["pairs"]:
+        assert _same(g["pairs"][lv][0], tr["pairs"][lv][0]), lv
+        assert _same(g["pairs"][lv][1], tr["pairs"][lv][1]), lv
+        assert g["tests"][lv] == tr["tests"][lv]
+        assert g["hits"][lv] == tr["hits"][lv]
+    assert g["mesh_tests"] == tr["mesh_tests"]
+    assert g["mesh_hits"] == tr["mesh_hits"]
+
+
+def test_traverse_triangle_batches():
+    base, kw = small("c2s")
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    m = wl.scene.m
+    cuts = [(0, 777), (777, m // 2), (m // 2, m)]
+    g = _gu().gpu_traverse(o["tree"], wl.scene, wl.B, wl.F, batches=cuts, capacity=1 << 22)
+    for run, (b, e) in zip(g["runs"], cuts):
+        ot = O.traverse(o["tree"], wl.scene, b, e)
+        for lv in ot["pairs"]:
+            assert _same(run["pairs"][lv][0], ot["pairs"][lv][0])
+            assert _same(run["pairs"][lv][1], ot["pairs"][lv][1])
+    # counters sum over batches
+    for lv in o["trav"]["tests"]:
+        assert g["tests"][lv] == o["trav"]["tests"][lv]
+        assert g["hits"][lv] == o["trav"]["hits"][lv]
+
+
+def test_traverse_capacity_overflow_reports_required_size():
+    base, kw = small("c1")
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    need = max(len(t) for t, _ in o["trav"]["pairs"].values())
+    g = _gu().gpu_traverse(o["tree"], wl.scene, wl.B, wl.F, capacity=need // 3)
+    assert g["status"] == 2    # CRSH_ERR_CAPACITY
+    top = o["tree"]["n_levels"]
+    assert g["meta"].pairs[top - 1] == len(o["trav"]["pairs"][top][0])
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_closest_hit_matches_oracle(name):
+    base, kw = small(name)
+    print(f"[hit] {name}", flush=True)
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    g, m = _gu().gpu_closest_hit(o["hash"]["rays"], o["sorted_ids"], wl.B, o["trav"]["pairs"][1], wl.scene,
+                                 wl.t_min)
+    assert np.array_equal(g[0], o["hits"][0])
+    for a, b in zip(g[1:], o["hits"][1:]):
+        assert np.allclose(a, b, rtol=1e-5, atol=0)
+    assert int(m.final_tests) == o["trav"]["final_tests"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_pipeline_end_to_end(name):
+    base, kw = small(name)
+    print(f"[pipeline] {name}", flush=True)
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    g = _gu().run_pipeline(wl, pair_capacity=1 << 16)
+    assert g["n"] == o["hash"]["n"]
+    assert _same(g["keys"], o["hash"]["keys"])
+    assert _same(g["sorted_ids"], o["sorted_ids"])
+    _check_tree(g, o["tree"])
+    for lv, (t, n) in o["trav"]["pairs"].items():
+        assert _same(g["pairs"][lv][0], t) and _same(g["pairs"][lv][1], n)
+    assert g["final_tests"] == o["trav"]["final_tests"]
+    assert np.array_equal(g["hit"][0], o["hits"][0])
+    for a, b in zip(g["hit"][1:], o["hits"][1:]):
+        assert np.allclose(a, b, rtol=1e-5, atol=0)
+
+
+def test_pipeline_is_deterministic():
+    base, kw = small("c2s")
+    wl = workload(base, **kw)
+    a = _gu().run_pipeline(wl, pair_capacity=1 << 22)
+    b = _gu().run_pipeline(wl, pair_capacity=1 << 22)
+    for lv in a["pairs"]:
+        assert _same(a["pairs"][lv][0], b["pairs"][lv][0]) and _same(a["pairs"][lv][1], b["pairs"][lv][1])
+    for x, y in zip(a["hit"], b["hit"]):
+        assert _same(x, y)
