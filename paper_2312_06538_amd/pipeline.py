@@ -141,9 +141,11 @@ def read_meta(bf, stream=None):
     return m, st
 
 
-def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=4):
-    """Run a frame; if a pair level overflowed, regrow the pair arrays to what
-    the device reported and run again.  Returns (buffers, meta)."""
+def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12):
+    """Run a frame; if a pair level overflowed, regrow the pair arrays and run
+    again.  An overflowing level truncates the levels below it, so their
+    reported sizes are lower bounds: grow to at least twice the capacity.
+    Returns (buffers, meta)."""
     for _ in range(max_tries):
         run_frame(fr, bf, stream, tri_batches)
         m, st = read_meta(bf, stream)
@@ -152,7 +154,8 @@ def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=4
         if m.status & ~X.OVERFLOW_PAIRS:
             raise X.CrshError(st, X.last_error())
         need = max(int(m.pairs[k]) for k in range(X.MAX_LEVELS))
-        bf = Buffers(fr, int(need * grow) + 1024, keep_levels=bf.keep_levels)
+        cap = max(int(need * grow) + 1024, 2 * bf.pair_capacity)
+        bf = Buffers(fr, cap, keep_levels=bf.keep_levels)
     raise X.CrshError(X.ERR_CAPACITY, "pair capacity still too small after regrowing")
 
 

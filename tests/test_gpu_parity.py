@@ -165,7 +165,7 @@ def test_traverse_triangle_batches():
     o = oracle_run(base, **kw)
     m = wl.scene.m
     cuts = [(0, 777), (777, m // 2), (m // 2, m)]
-    g = _gu().gpu_traverse(o["tree"], wl.scene, wl.B, wl.F, batches=cuts, capacity=1 << 22)
+    g = _gu().gpu_traverse(o["tree"], wl.scene, wl.B, wl.F, batches=cuts, capacity=1 << 24)
     for run, (b, e) in zip(g["runs"], cuts):
         ot = O.traverse(o["tree"], wl.scene, b, e)
         for lv in ot["pairs"]:
