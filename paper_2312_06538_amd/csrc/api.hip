@@ -50,6 +50,19 @@ void prof_end(bool armed, hipStream_t s)
     g_prof.armed = false;
 }
 
+uint32_t resident_grid(const void *f, int threads, uint64_t want)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, threads, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    uint64_t g = (uint64_t)per_cu * (uint64_t)cus;
+    if (want < g) g = want;
+    return g ? (uint32_t)g : 1u;
+}
+
 size_t sort_ws_bytes(uint32_t cap)
 {
     size_t tiles = (cap + SORT_TILE - 1) / SORT_TILE;
@@ -64,13 +77,17 @@ size_t hash_ws_bytes(uint64_t pixels)
     return align256(((pixels + HASH_BLOCK - 1) / HASH_BLOCK + 1) * 4);
 }
 
-size_t trav_ws_bytes(uint32_t m, uint64_t top_items, uint64_t max_pairs)
+size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t max_pairs)
 {
-    uint64_t tiles = (max_pairs + LEVEL_TILE - 1) / LEVEL_TILE;
-    uint64_t flags = std::max<uint64_t>(tiles, top_items) + 1;
-    return align256((size_t)m * 16)                        // triangle spheres
-           + align256(64 * 8)                              // tile counters
-           + align256(flags * 8);                          // look-back words
+    uint64_t level_tiles = (max_pairs + LEVEL_TILE - 1) / LEVEL_TILE;
+    uint64_t items = std::max<uint64_t>(top_items, level_tiles) + 1;
+    return align256((size_t)m * 16)                            // triangle spheres
+           + align256((size_t)node_cap * 16) * 2               // packed nodes
+           + align256((size_t)node_cap * 4)
+           + align256(items * 4) + align256(items * 8)         // counts, offsets
+           + align256(level_tiles * LEVEL_THREADS * 4 + 4)     // pass masks
+           + align256((items / SCAN_TILE_ITEMS + 2) * 8)       // scan look-back words
+           + align256(4);                                      // scan tile counter
 }
 
 size_t hit_ws_bytes(uint32_t m) { return align256((size_t)m * 48); }
@@ -92,7 +109,7 @@ extern "C" size_t crsh_workspace_size(uint32_t max_rays, uint32_t max_tris, uint
 {
     size_t a = sort_ws_bytes(max_rays);
     size_t b = hash_ws_bytes(max_rays);
-    size_t c = trav_ws_bytes(max_tris, (uint64_t)max_nodes * max_meshes, max_pairs);
+    size_t c = trav_ws_bytes(max_tris, max_nodes, (uint64_t)max_nodes * max_meshes, max_pairs);
     size_t d = hit_ws_bytes(max_tris);
     return std::max(std::max(a, b), std::max(c, d));
 }

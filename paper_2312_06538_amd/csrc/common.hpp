@@ -126,6 +126,40 @@ __device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Called by a whole wave (all 64 lanes); returns the exclusive prefix of
+// `count` to every lane.  The wave reads 64 predecessors' words at once
+// (lane i looks at tile - 1 - i), so a walk over many tiles that have only
+// published their own count costs one round trip per 64 tiles.
+__device__ __forceinline__ uint64_t lookback_wave(uint64_t *flags, uint32_t tile, uint64_t count)
+{
+    const uint32_t l = lane_id();
+    if (tile == 0) {
+        if (l == 0) lb_store(&flags[0], LB_INC | count);
+        return 0;
+    }
+    if (l == 0) lb_store(&flags[tile], LB_AGG | count);
+    uint64_t excl = 0;
+    int64_t top = (int64_t)tile - 1;
+    for (;;) {
+        const int64_t idx = top - (int64_t)l;
+        const uint64_t f = idx >= 0 ? lb_load(&flags[idx]) : LB_INC;   // before tile 0: prefix 0
+        const uint64_t kind = f & ~LB_MASK;
+        const uint64_t inc = ballot(kind == LB_INC);
+        const uint64_t none = ballot(kind == 0);
+        const uint32_t first = inc ? (uint32_t)__builtin_ctzll(inc) : 64u;
+        const uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+        if (none & upto) {                 // a tile we need has not published yet
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += wave_sum((uint64_t)(l <= first ? (f & LB_MASK) : 0ull));
+        if (first < 64) break;
+        top -= WAVE;
+    }
+    if (l == 0) lb_store(&flags[tile], LB_INC | (excl + count));
+    return excl;
+}
+
 // Called by one thread of the tile; returns the exclusive prefix of `count`.
 __device__ __forceinline__ uint64_t lookback(uint64_t *flags, uint32_t tile, uint64_t count)
 {
@@ -156,18 +190,25 @@ __device__ __forceinline__ uint64_t lookback(uint64_t *flags, uint32_t tile, uin
 constexpr uint32_t SORT_TILE = 4096;      // keys per sort tile
 constexpr uint32_t SORT_PASSES = 4;       // 8-bit digits of a 32-bit key
 constexpr uint32_t HASH_BLOCK = 256;      // pixels per hash block
-constexpr uint32_t LEVEL_TILE = 256;      // parent pairs per traversal tile
+constexpr uint32_t LEVEL_THREADS = 256;   // threads of a traversal tile
+constexpr uint32_t LEVEL_PPT = 2;         // parent pairs per thread
+constexpr uint32_t LEVEL_TILE = LEVEL_THREADS * LEVEL_PPT;   // parent pairs per tile
+constexpr uint32_t SCAN_TILE_ITEMS = 4096;                 // counts per scan tile
 
 __host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t sort_ws_bytes(uint32_t cap);
 size_t hash_ws_bytes(uint64_t pixels);
-size_t trav_ws_bytes(uint32_t m, uint64_t top_items, uint64_t max_pairs);
+size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t max_pairs);
 size_t hit_ws_bytes(uint32_t m);
 
 // launch helpers
 void set_error(const char *fmt, ...);
 crsh_status hip_check(hipError_t e, const char *what);
+
+// Largest grid of `threads`-thread blocks of kernel f that the current device
+// keeps resident at once (occupancy x compute units), capped at `want`.
+uint32_t resident_grid(const void *f, int threads, uint64_t want);
 
 // One-shot kernel timer (crsh_profile_next): prof_begin returns true when
 // this launch is the armed one and has recorded the start event.

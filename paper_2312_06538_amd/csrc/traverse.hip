@@ -1,18 +1,16 @@
 // Stage 4: hierarchy traversal (Sec. 3.3.7, Eq. 9).
 //
-// k_tri_sph    bounding sphere of every triangle (centroid, farthest vertex).
-// k_top        persistent waves; one (top node, mesh) item per wave in item
-//              order: mesh-sphere test, then the mesh's triangles (in the
-//              current triangle batch) against the node, 64 per step.  The
-//              item's survivors are counted, its offset found by decoupled
-//              look-back over items, and the survivors written in triangle
-//              order.
-// k_level      persistent 256-thread blocks; one parent pair per thread, its
-//              F children tested in order; block scan + look-back over tiles
-//              give every survivor its place, so the child level comes out
-//              trimmed (Fig. 4) and in (parent pair, child) order.
-// Both orders equal a sequential traversal's, so each pair level is
-// deterministic.
+// Every level is produced in three launches with no wait between blocks:
+//   count  each work item (top level: one (top node, mesh) pair per wave;
+//          lower levels: a tile of 512 parent pairs, 2 per thread, every
+//          child unrolled) runs its Eq. 9 tests and records how many pass
+//          (lower levels also keep each thread's pass mask);
+//   scan   exclusive scan of the counts -> output offset of every item;
+//   emit   each item writes its survivors at its offset, in (parent pair,
+//          child) order -- at the top level (node, mesh, triangle) order.
+// The pair arrays therefore come out trimmed (Fig. 4) and in the order of a
+// sequential traversal, so they are deterministic.  Work is spread with
+// grid-stride loops; nothing depends on which blocks are resident.
 #include "common.hpp"
 
 namespace crsh {
@@ -27,10 +25,20 @@ struct pair_levels {
 struct node_arrays {
     const float *cx, *cy, *cz, *r, *ax, *ay, *az, *c, *tan, *sec;
 };
-struct trav_ctl {
-    uint32_t top_ctr;
-    uint32_t lvl_ctr[CRSH_MAX_LEVELS];
+
+// per-level scratch carved from the workspace
+struct trav_scratch {
+    uint32_t *cnt;         // survivors per work item
+    uint64_t *off;         // exclusive offsets of the work items
+    uint32_t *mask;        // pass masks of the lower-level count pass
+    uint64_t *scan_flags;  // look-back words of the scan
+    uint32_t *scan_ctr;    // tile counter of the scan
 };
+
+constexpr uint32_t SCAN_THREADS = 256;
+constexpr uint32_t SCAN_ITEMS = 16;
+constexpr uint32_t SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+static_assert(SCAN_TILE == SCAN_TILE_ITEMS, "workspace sizing");
 
 __global__ void k_tri_sph(const float *__restrict__ v0x, const float *__restrict__ v0y,
                           const float *__restrict__ v0z, const float *__restrict__ v1x,
@@ -51,151 +59,281 @@ __global__ void k_tri_sph(const float *__restrict__ v0x, const float *__restrict
     }
 }
 
-// Eq. 9 with H the projection of P on the node axis: |P-H| = |(P-C) x a|,
-// |C-H| = |(P-C).a|; pass iff |P-H|^2 <= (|C-H| tan + (d + r) sec)^2.
-struct node_t {
-    f3 C, a;
-    float r, c, tan, sec;
-};
-
-__device__ __forceinline__ node_t load_node(const node_arrays &nd, uint32_t i)
+// Traversal copy of the nodes: (cx, cy, cz, r), (ax, ay, az, tan) and sec,
+// with sec = -1 marking a cone of 90 degrees or more (c <= 0 gives no
+// positive sec, c > 0 always does), so one test reads 36 bytes in 3 loads.
+// Also clears the per-call pair counts.
+__global__ void k_node_pack(node_arrays nd, crsh_meta *meta, float4 *na, float4 *nb, float *ns)
 {
-    node_t n;
-    n.C = mk(nd.cx[i], nd.cy[i], nd.cz[i]);
-    n.r = nd.r[i];
-    n.a = mk(nd.ax[i], nd.ay[i], nd.az[i]);
-    n.c = nd.c[i];
-    n.tan = nd.tan[i];
-    n.sec = nd.sec[i];
-    return n;
+    const uint32_t nl = meta->n_levels;
+    const uint32_t total = nl ? meta->level_off[nl - 1] + meta->level_cnt[nl - 1] : 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        na[i] = make_float4(nd.cx[i], nd.cy[i], nd.cz[i], nd.r[i]);
+        nb[i] = make_float4(nd.ax[i], nd.ay[i], nd.az[i], nd.tan[i]);
+        ns[i] = nd.c[i] > 0.0f ? nd.sec[i] : -1.0f;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < CRSH_MAX_LEVELS) meta->pairs[threadIdx.x] = 0;
 }
 
-__device__ __forceinline__ bool node_meets(const node_t &n, f3 P, float d)
+// Eq. 9 with H the projection of P on the node axis: |P-H| = |(P-C) x a|,
+// |C-H| = |(P-C).a|; pass iff |P-H|^2 <= (|C-H| tan + (d + r) sec)^2.
+__device__ __forceinline__ bool packed_meets(float4 A, float4 Bv, float sec, f3 P, float d)
 {
-    if (!(n.c > 0.0f)) return true;
-    f3 v = P - n.C;
-    float t = dot(v, n.a);
-    f3 w = cross(v, n.a);
+    if (!(sec > 0.0f)) return true;
+    f3 v = P - mk(A.x, A.y, A.z);
+    f3 a = mk(Bv.x, Bv.y, Bv.z);
+    float t = dot(v, a);
+    f3 w = cross(v, a);
     float lhs2 = dot(w, w);
-    float rhs = fabsf(t) * n.tan + (d + n.r) * n.sec;
+    float rhs = fabsf(t) * Bv.w + (d + A.w) * sec;
     return lhs2 <= rhs * rhs;
 }
 
-// Zero the look-back words that the next traversal kernel will use.
-__global__ void k_trav_prep(uint64_t *flags, trav_ctl *ctl, crsh_meta *meta, int32_t parent_level,
-                            uint32_t n_mesh, pair_levels P, int32_t first)
+// number of work items of a level: top level (parent_level 0) = top nodes x
+// meshes, lower levels = tiles of LEVEL_TILE parent pairs
+__device__ __forceinline__ uint64_t level_items(const crsh_meta *meta, int32_t parent_level, uint32_t n_mesh,
+                                                const pair_levels &P)
 {
     const uint32_t nl = meta->n_levels;
-    uint64_t need = 0;
-    if (parent_level == 0) {
-        if (nl > 0) need = (uint64_t)meta->level_cnt[nl - 1] * n_mesh;
-    } else if ((uint32_t)parent_level <= nl && parent_level >= 2) {
-        uint64_t nin = meta->pairs[parent_level - 1];
-        uint64_t cap = P.p[parent_level - 1].cap;
-        nin = nin < cap ? nin : cap;
-        need = (nin + LEVEL_TILE - 1) / LEVEL_TILE;
-    }
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < need;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        flags[i] = 0;
-    if (first && blockIdx.x == 0 && threadIdx.x < CRSH_MAX_LEVELS) {
-        meta->pairs[threadIdx.x] = 0;
-        ctl->lvl_ctr[threadIdx.x] = 0;
-        if (threadIdx.x == 0) ctl->top_ctr = 0;
+    if (parent_level == 0) return nl ? (uint64_t)meta->level_cnt[nl - 1] * n_mesh : 0;
+    if ((uint32_t)parent_level > nl || parent_level < 2) return 0;
+    uint64_t nin = meta->pairs[parent_level - 1];
+    const uint64_t cap = P.p[parent_level - 1].cap;
+    nin = nin < cap ? nin : cap;
+    return (nin + LEVEL_TILE - 1) / LEVEL_TILE;
+}
+
+__device__ __forceinline__ void clear_scan(const trav_scratch &S, uint64_t items)
+{
+    const uint64_t nt = (items + SCAN_TILE - 1) / SCAN_TILE;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = gid; i < nt; i += (uint64_t)gridDim.x * blockDim.x) S.scan_flags[i] = 0;
+    if (gid == 0) *S.scan_ctr = 0;
+}
+
+// ------------------------------------------------------------- top level
+__device__ __forceinline__ void top_item(uint32_t item, uint32_t n_mesh, uint32_t off, const float4 *na,
+                                         const float4 *nb, const float *ns, const float *msph,
+                                         const uint32_t *mesh_first, const uint32_t *mesh_count,
+                                         uint32_t tri_begin, uint32_t tri_end, float4 &A, float4 &Bv, float &S,
+                                         uint32_t &i, uint32_t &b, uint32_t &e, bool &pass)
+{
+    i = item / n_mesh;
+    const uint32_t m = item - i * n_mesh;
+    A = na[off + i];
+    Bv = nb[off + i];
+    S = ns[off + i];
+    pass = packed_meets(A, Bv, S, mk(msph[4 * m], msph[4 * m + 1], msph[4 * m + 2]), msph[4 * m + 3]);
+    b = e = 0;
+    if (pass) {
+        b = max(mesh_first[m], tri_begin);
+        e = min(mesh_first[m] + mesh_count[m], tri_end);
+        if (e < b) e = b;
     }
 }
 
-__global__ __launch_bounds__(WAVE) void k_top(node_arrays nd, const float4 *__restrict__ tsph,
-                                              const uint32_t *__restrict__ mesh_first,
-                                              const uint32_t *__restrict__ mesh_count,
-                                              const float *__restrict__ msph, uint32_t n_mesh, uint32_t tri_begin,
-                                              uint32_t tri_end, pair_levels P, uint64_t *flags, trav_ctl *ctl,
-                                              crsh_meta *meta)
+__global__ __launch_bounds__(256) void k_top_count(const float4 *__restrict__ na, const float4 *__restrict__ nb,
+                                                   const float *__restrict__ ns, const float4 *__restrict__ tsph,
+                                                   const uint32_t *__restrict__ mesh_first,
+                                                   const uint32_t *__restrict__ mesh_count,
+                                                   const float *__restrict__ msph, uint32_t n_mesh,
+                                                   uint32_t tri_begin, uint32_t tri_end, pair_levels P,
+                                                   trav_scratch S, crsh_meta *meta)
+{
+    __shared__ uint64_t s_red[3][256 / WAVE];
+    const uint32_t nl = meta->n_levels;
+    if (nl == 0) return;
+    const uint32_t top = nl - 1;
+    const uint64_t n_items = level_items(meta, 0, n_mesh, P);
+    clear_scan(S, n_items);
+    const uint32_t off = meta->level_off[top];
+    const uint32_t l = lane_id();
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
+    uint64_t tests = 0, mhits = 0, items = 0;
+    for (uint64_t it = wave; it < n_items; it += nwaves) {
+        float4 A, Bv;
+        float Sg;
+        uint32_t i, b, e;
+        bool pass;
+        top_item((uint32_t)it, n_mesh, off, na, nb, ns, msph, mesh_first, mesh_count, tri_begin, tri_end, A, Bv,
+                 Sg, i, b, e, pass);
+        ++items;
+        mhits += pass ? 1 : 0;
+        tests += e - b;
+        uint32_t cnt = 0;
+        for (uint32_t t0 = b; t0 < e; t0 += WAVE) {
+            const uint32_t t = t0 + l;
+            bool ok = false;
+            if (t < e) {
+                const float4 s = tsph[t];
+                ok = packed_meets(A, Bv, Sg, mk(s.x, s.y, s.z), s.w);
+            }
+            cnt += (uint32_t)__popcll(ballot(ok));
+        }
+        if (l == 0) S.cnt[it] = cnt;
+    }
+    if (l == 0) {
+        s_red[0][threadIdx.x / WAVE] = tests;
+        s_red[1][threadIdx.x / WAVE] = mhits;
+        s_red[2][threadIdx.x / WAVE] = items;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0, bq = 0, c = 0;
+        for (int w = 0; w < 256 / WAVE; ++w) {
+            a += s_red[0][w];
+            bq += s_red[1][w];
+            c += s_red[2][w];
+        }
+        if (a) atomicAdd((unsigned long long *)&meta->tests[top], (unsigned long long)a);
+        if (bq) atomicAdd((unsigned long long *)&meta->mesh_hits, (unsigned long long)bq);
+        if (c) atomicAdd((unsigned long long *)&meta->mesh_tests, (unsigned long long)c);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na, const float4 *__restrict__ nb,
+                                                  const float *__restrict__ ns, const float4 *__restrict__ tsph,
+                                                  const uint32_t *__restrict__ mesh_first,
+                                                  const uint32_t *__restrict__ mesh_count,
+                                                  const float *__restrict__ msph, uint32_t n_mesh,
+                                                  uint32_t tri_begin, uint32_t tri_end, pair_levels P,
+                                                  trav_scratch S, const crsh_meta *meta)
 {
     const uint32_t nl = meta->n_levels;
     if (nl == 0) return;
     const uint32_t top = nl - 1;
-    const uint32_t ntop = meta->level_cnt[top];
-    const uint32_t off = meta->level_off[top];
-    const uint64_t n_items = (uint64_t)ntop * n_mesh;
     const pairs_dev out = P.p[top];
+    if (out.tri == nullptr) return;
+    const uint64_t n_items = level_items(meta, 0, n_mesh, P);
+    const uint32_t off = meta->level_off[top];
     const uint32_t l = lane_id();
-    if (out.tri == nullptr) {       // no storage for this many levels
-        if (blockIdx.x == 0 && l == 0) atomicOr(&meta->status, CRSH_OVERFLOW_PAIRS);
-        return;
-    }
-    uint64_t tests = 0, mhits = 0, items = 0;
-    for (;;) {
-        uint32_t item = 0;
-        if (l == 0) item = atomicAdd(&ctl->top_ctr, 1u);
-        item = __shfl(item, 0, WAVE);
-        if (item >= n_items) break;
-        ++items;
-        const uint32_t i = item / n_mesh;
-        const uint32_t m = item - i * n_mesh;
-        const node_t node = load_node(nd, off + i);
-        const bool pass = node_meets(node, mk(msph[4 * m], msph[4 * m + 1], msph[4 * m + 2]), msph[4 * m + 3]);
-        uint32_t b = 0, e = 0;
-        if (pass) {
-            ++mhits;
-            b = max(mesh_first[m], tri_begin);
-            e = min(mesh_first[m] + mesh_count[m], tri_end);
-            if (e < b) e = b;
-            tests += e - b;
-        }
-        uint32_t cnt = 0;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
+    for (uint64_t it = wave; it < n_items; it += nwaves) {
+        if (S.cnt[it] == 0) continue;
+        float4 A, Bv;
+        float Sg;
+        uint32_t i, b, e;
+        bool pass;
+        top_item((uint32_t)it, n_mesh, off, na, nb, ns, msph, mesh_first, mesh_count, tri_begin, tri_end, A, Bv,
+                 Sg, i, b, e, pass);
+        uint64_t pos = S.off[it];
         for (uint32_t t0 = b; t0 < e; t0 += WAVE) {
-            uint32_t t = t0 + l;
+            const uint32_t t = t0 + l;
             bool ok = false;
             if (t < e) {
-                float4 s = tsph[t];
-                ok = node_meets(node, mk(s.x, s.y, s.z), s.w);
+                const float4 s = tsph[t];
+                ok = packed_meets(A, Bv, Sg, mk(s.x, s.y, s.z), s.w);
             }
-            cnt += (uint32_t)__popcll(ballot(ok));
-        }
-        uint64_t excl = 0;
-        if (l == 0) excl = lookback(flags, item, cnt);
-        excl = __shfl(excl, 0, WAVE);
-        uint64_t pos = excl;
-        if (cnt) {
-            for (uint32_t t0 = b; t0 < e; t0 += WAVE) {
-                uint32_t t = t0 + l;
-                bool ok = false;
-                if (t < e) {
-                    float4 s = tsph[t];
-                    ok = node_meets(node, mk(s.x, s.y, s.z), s.w);
-                }
-                uint64_t mask = ballot(ok);
-                uint64_t at = pos + rank_below(mask);
-                if (ok && at < out.cap) {
-                    out.tri[at] = t;
-                    out.node[at] = i;
-                }
-                pos += (uint32_t)__popcll(mask);
+            const uint64_t mask = ballot(ok);
+            const uint64_t at = pos + rank_below(mask);
+            if (ok && at < out.cap) {
+                out.tri[at] = t;
+                out.node[at] = i;
             }
+            pos += (uint32_t)__popcll(mask);
         }
-        if (item == n_items - 1 && l == 0) {
-            uint64_t total = excl + cnt;
-            meta->pairs[top] = total;
-            atomicAdd((unsigned long long *)&meta->hits[top], (unsigned long long)total);
-            if (total > out.cap) atomicOr(&meta->status, CRSH_OVERFLOW_PAIRS);
-        }
-    }
-    if (l == 0) {
-        if (tests) atomicAdd((unsigned long long *)&meta->tests[top], (unsigned long long)tests);
-        if (mhits) atomicAdd((unsigned long long *)&meta->mesh_hits, (unsigned long long)mhits);
-        if (items) atomicAdd((unsigned long long *)&meta->mesh_tests, (unsigned long long)items);
     }
 }
 
-__global__ __launch_bounds__(LEVEL_TILE) void k_level(int32_t parent_level, uint32_t F, node_arrays nd,
-                                                      const float4 *__restrict__ tsph, uint32_t m, pair_levels P,
-                                                      uint64_t *flags, trav_ctl *ctl, crsh_meta *meta)
+// ----------------------------------------------------------- lower levels
+template <int NF, int PPT>
+__device__ __forceinline__ uint32_t level_tile_mask(uint64_t q0, uint64_t nin, const pairs_dev &in, uint32_t F,
+                                                    uint32_t nk, uint32_t offk, const float4 *__restrict__ na,
+                                                    const float4 *__restrict__ nb, const float *__restrict__ ns,
+                                                    const float4 *__restrict__ tsph, uint32_t m, uint32_t *tri,
+                                                    uint32_t *par, uint64_t &tests)
 {
-    __shared__ uint32_t s_tile;
-    __shared__ uint64_t s_excl;
-    __shared__ uint32_t s_scan[LEVEL_TILE / WAVE];
-    __shared__ uint64_t s_red[LEVEL_TILE / WAVE];
+    float4 sp[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const bool ok = q0 + k < nin;
+        tri[k] = ok ? in.tri[q0 + k] : 0u;
+        par[k] = ok ? in.node[q0 + k] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) sp[k] = tsph[tri[k] < m ? tri[k] : 0u];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        float4 A[NF], Bv[NF];
+        float Sg[NF];
+        bool ok[NF];
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            const uint32_t ch = par[k] * F + (uint32_t)j;
+            ok[j] = par[k] != 0xFFFFFFFFu && (uint32_t)j < F && ch < nk;
+            const uint32_t g = offk + (ok[j] ? ch : 0u);
+            A[j] = na[g];
+            Bv[j] = nb[g];
+            Sg[j] = ns[g];
+        }
+        const f3 Pc = mk(sp[k].x, sp[k].y, sp[k].z);
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            if (!ok[j]) continue;
+            ++tests;
+            if (packed_meets(A[j], Bv[j], Sg[j], Pc, sp[k].w)) mask |= 1u << (k * NF + j);
+        }
+    }
+    return mask;
+}
+
+template <int NF, int PPT>
+__global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_level, uint32_t F,
+                                                               const float4 *__restrict__ na,
+                                                               const float4 *__restrict__ nb,
+                                                               const float *__restrict__ ns,
+                                                               const float4 *__restrict__ tsph, uint32_t m,
+                                                               pair_levels P, trav_scratch S, crsh_meta *meta)
+{
+    static_assert(NF * PPT <= 32, "one bit per child test");
+    static_assert(LEVEL_THREADS * PPT == LEVEL_TILE, "tile size");
+    __shared__ uint32_t s_red32[LEVEL_THREADS / WAVE];
+    __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
+    const uint32_t nl = meta->n_levels;
+    if ((uint32_t)parent_level > nl) return;
+    const uint64_t ntiles = level_items(meta, parent_level, 0, P);
+    clear_scan(S, ntiles);                  // the scan that follows reads these
+    const pairs_dev in = P.p[parent_level - 1];
+    if (in.tri == nullptr || P.p[parent_level - 2].tri == nullptr) return;
+    uint64_t nin = meta->pairs[parent_level - 1];
+    nin = nin < in.cap ? nin : in.cap;
+    const uint32_t nk = meta->level_cnt[parent_level - 2];
+    const uint32_t offk = meta->level_off[parent_level - 2];
+    uint64_t tests = 0;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint32_t tri[PPT], par[PPT];
+        const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
+        const uint32_t mask =
+            level_tile_mask<NF, PPT>(q0, nin, in, F, nk, offk, na, nb, ns, tsph, m, tri, par, tests);
+        S.mask[tile * LEVEL_THREADS + threadIdx.x] = mask;
+        const uint32_t c = wave_sum((uint32_t)__popc(mask));
+        if (lane_id() == 0) s_red32[threadIdx.x / WAVE] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < LEVEL_THREADS / WAVE; ++w) t += s_red32[w];
+            S.cnt[tile] = t;
+        }
+        __syncthreads();
+    }
+    tests = wave_sum(tests);
+    if (lane_id() == 0) s_red[threadIdx.x / WAVE] = tests;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t tt = 0;
+        for (int w = 0; w < LEVEL_THREADS / WAVE; ++w) tt += s_red[w];
+        if (tt) atomicAdd((unsigned long long *)&meta->tests[parent_level - 2], (unsigned long long)tt);
+    }
+}
+
+template <int NF, int PPT>
+__global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_level, uint32_t F, pair_levels P,
+                                                              trav_scratch S, const crsh_meta *meta)
+{
+    __shared__ uint32_t s_scan[LEVEL_THREADS / WAVE];
     const uint32_t nl = meta->n_levels;
     if ((uint32_t)parent_level > nl) return;
     const pairs_dev in = P.p[parent_level - 1];
@@ -204,59 +342,88 @@ __global__ __launch_bounds__(LEVEL_TILE) void k_level(int32_t parent_level, uint
     uint64_t nin = meta->pairs[parent_level - 1];
     nin = nin < in.cap ? nin : in.cap;
     const uint64_t ntiles = (nin + LEVEL_TILE - 1) / LEVEL_TILE;
-    const uint32_t nk = meta->level_cnt[parent_level - 2];
-    const uint32_t offk = meta->level_off[parent_level - 2];
-    uint64_t tests = 0;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(&ctl->lvl_ctr[parent_level - 1], 1u);
-        __syncthreads();
-        const uint32_t tile = s_tile;
-        if (tile >= ntiles) break;
-        const uint64_t q = (uint64_t)tile * LEVEL_TILE + threadIdx.x;
-        uint32_t mask = 0, tri = 0, p = 0;
-        if (q < nin) {
-            tri = in.tri[q];
-            p = in.node[q];
-            const float4 s = tsph[tri < m ? tri : 0];
-            const f3 Pc = mk(s.x, s.y, s.z);
-            for (uint32_t j = 0; j < F; ++j) {
-                const uint32_t ch = p * F + j;
-                if (ch >= nk) break;
-                ++tests;
-                if (node_meets(load_node(nd, offk + ch), Pc, s.w)) mask |= 1u << j;
-            }
-        }
-        const uint32_t c = (uint32_t)__popc(mask);
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (S.cnt[tile] == 0) continue;          // uniform over the block
+        const uint32_t mask = S.mask[tile * LEVEL_THREADS + threadIdx.x];
         uint32_t total;
-        const uint32_t ex = block_excl_scan<uint32_t, LEVEL_TILE / WAVE>(c, s_scan, total);
-        if (threadIdx.x == 0) s_excl = lookback(flags, tile, total);
-        __syncthreads();
-        uint64_t at = s_excl + ex;
-        while (mask) {
-            const uint32_t j = (uint32_t)__builtin_ctz(mask);
-            mask &= mask - 1;
-            if (at < out.cap) {
-                out.tri[at] = tri;
-                out.node[at] = p * F + j;
+        const uint32_t ex = block_excl_scan<uint32_t, LEVEL_THREADS / WAVE>((uint32_t)__popc(mask), s_scan, total);
+        if (!mask) continue;
+        const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
+        uint32_t tri[PPT], par[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const bool ok = ((mask >> (k * NF)) & ((1u << NF) - 1u)) != 0u;
+            tri[k] = ok ? in.tri[q0 + k] : 0u;
+            par[k] = ok ? in.node[q0 + k] : 0u;
+        }
+        uint64_t at = S.off[tile] + ex;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+            for (int j = 0; j < NF; ++j) {
+                if (!((mask >> (k * NF + j)) & 1u)) continue;
+                if (at < out.cap) {
+                    out.tri[at] = tri[k];
+                    out.node[at] = par[k] * F + (uint32_t)j;
+                }
+                ++at;
             }
-            ++at;
         }
-        if (tile == ntiles - 1 && threadIdx.x == 0) {
-            const uint64_t all = s_excl + total;
-            meta->pairs[parent_level - 2] = all;
-            atomicAdd((unsigned long long *)&meta->hits[parent_level - 2], (unsigned long long)all);
-            if (all > out.cap) atomicOr(&meta->status, CRSH_OVERFLOW_PAIRS);
-        }
-        __syncthreads();
     }
-    tests = wave_sum(tests);
-    if (lane_id() == 0) s_red[threadIdx.x / WAVE] = tests;
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive scan of the item counts into 64-bit offsets; the total becomes
+// the pair count of the output level.  Tiles take their index from an atomic
+// counter in launch order, so every tile waited on in the look-back has
+// started and publishes its sum without waiting: the look-back always ends.
+// There are few tiles (SCAN_TILE items each).
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_items(int32_t parent_level, uint32_t n_mesh, pair_levels P,
+                                                             trav_scratch S, crsh_meta *meta)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_excl;
+    __shared__ uint64_t s_scan[SCAN_THREADS / WAVE];
+    const uint32_t nl = meta->n_levels;
+    if (nl == 0) return;
+    const uint64_t n = level_items(meta, parent_level, n_mesh, P);
+    const uint32_t out_level = parent_level == 0 ? nl - 1 : (uint32_t)parent_level - 2;
+    const uint64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (threadIdx.x == 0) s_tile = atomicAdd(S.scan_ctr, 1u);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t t = 0;
-        for (int i = 0; i < LEVEL_TILE / WAVE; ++i) t += s_red[i];
-        if (t) atomicAdd((unsigned long long *)&meta->tests[parent_level - 2], (unsigned long long)t);
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) return;
+    const uint64_t base = (uint64_t)tile * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint64_t v[SCAN_ITEMS];
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_ITEMS; ++k) {
+        v[k] = base + k < n ? S.cnt[base + k] : 0u;
+        sum += v[k];
     }
+    uint64_t total;
+    const uint64_t ex = block_excl_scan<uint64_t, SCAN_THREADS / WAVE>(sum, s_scan, total);
+    if (threadIdx.x < WAVE) {
+        const uint64_t e = lookback_wave(S.scan_flags, tile, total);
+        if (threadIdx.x == 0) s_excl = e;
+    }
+    __syncthreads();
+    uint64_t run = s_excl + ex;
+#pragma unroll
+    for (uint32_t k = 0; k < SCAN_ITEMS; ++k) {
+        if (base + k < n) S.off[base + k] = run;
+        run += v[k];
+    }
+    if (tile == ntiles - 1 && threadIdx.x == SCAN_THREADS - 1) {
+        meta->pairs[out_level] = run;
+        atomicAdd((unsigned long long *)&meta->hits[out_level], (unsigned long long)run);
+        if (run > P.p[out_level].cap) atomicOr(&meta->status, CRSH_OVERFLOW_PAIRS);
+    }
+}
+
+__global__ void k_no_storage(crsh_meta *meta, uint32_t levels_given)
+{
+    if (meta->n_levels > levels_given) atomicOr(&meta->status, CRSH_OVERFLOW_PAIRS);
 }
 
 }  // namespace crsh
@@ -300,20 +467,38 @@ extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *
         set_error("crsh_traverse: no pair storage");
         return CRSH_ERR_INVALID;
     }
-    size_t need = trav_ws_bytes(scene->m, (uint64_t)nodes->capacity * scene->n_mesh, max_pairs);
+    const uint64_t top_items = (uint64_t)nodes->capacity * scene->n_mesh;
+    size_t need = trav_ws_bytes(scene->m, nodes->capacity, top_items, max_pairs);
     if (ws_bytes < need) {
         set_error("crsh_traverse: workspace too small (%zu < %zu)", ws_bytes, need);
         return CRSH_ERR_INVALID;
     }
+    const uint64_t level_tiles = (max_pairs + LEVEL_TILE - 1) / LEVEL_TILE;
+    const uint64_t items = std::max(top_items, level_tiles) + 1;
     char *w = (char *)ws;
     float4 *tsph = (float4 *)w;
     w += align256((size_t)scene->m * 16);
-    trav_ctl *ctl = (trav_ctl *)w;
-    w += align256(64 * 8);
-    uint64_t *flags = (uint64_t *)w;
+    float4 *na = (float4 *)w;
+    w += align256((size_t)nodes->capacity * 16);
+    float4 *nb = (float4 *)w;
+    w += align256((size_t)nodes->capacity * 16);
+    float *ns = (float *)w;
+    w += align256((size_t)nodes->capacity * 4);
+    trav_scratch S;
+    S.cnt = (uint32_t *)w;
+    w += align256(items * 4);
+    S.off = (uint64_t *)w;
+    w += align256(items * 8);
+    S.mask = (uint32_t *)w;
+    w += align256(level_tiles * LEVEL_THREADS * 4 + 4);
+    S.scan_flags = (uint64_t *)w;
+    w += align256((items / SCAN_TILE + 2) * 8);
+    S.scan_ctr = (uint32_t *)w;
 
     node_arrays nd{nodes->cx, nodes->cy, nodes->cz, nodes->r, nodes->ax, nodes->ay, nodes->az,
                    nodes->c, nodes->tan, nodes->sec};
+    int nf = 2;
+    while (nf < merge) nf *= 2;
     pair_levels P;
     for (int k = 0; k < CRSH_MAX_LEVELS; ++k) {
         P.p[k].tri = k < levels ? pairs[k].tri : nullptr;
@@ -326,19 +511,49 @@ extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *
         k_tri_sph<<<g, 256, 0, stream>>>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], tri_begin,
                                          tri_end, tsph);
     }
-    k_trav_prep<<<1024, 256, 0, stream>>>(flags, ctl, meta, 0, scene->n_mesh, P, 1);
     {
-        prof_scope ps("k_top", stream);
-        k_top<<<2048, WAVE, 0, stream>>>(nd, tsph, scene->mesh_first, scene->mesh_count, scene->msph, scene->n_mesh,
-                                     tri_begin, tri_end, P, flags, ctl, meta);
+        uint32_t g = std::min<uint32_t>((nodes->capacity + 255) / 256, 2048);
+        k_node_pack<<<g, 256, 0, stream>>>(nd, meta, na, nb, ns);
+    }
+    k_no_storage<<<1, 1, 0, stream>>>(meta, (uint32_t)levels);
+    const uint32_t scan_grid = (uint32_t)std::min<uint64_t>((items + SCAN_TILE - 1) / SCAN_TILE, 1u << 20);
+    {
+        uint32_t g = (uint32_t)std::min<uint64_t>((top_items + 3) / 4, 2048);
+        if (g == 0) g = 1;
+        {
+            prof_scope ps("k_top_count", stream);
+            k_top_count<<<g, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first, scene->mesh_count, scene->msph,
+                                               scene->n_mesh, tri_begin, tri_end, P, S, meta);
+        }
+        k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(0, scene->n_mesh, P, S, meta);
+        {
+            prof_scope ps("k_top_emit", stream);
+            k_top_emit<<<g, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first, scene->mesh_count, scene->msph,
+                                              scene->n_mesh, tri_begin, tri_end, P, S, meta);
+        }
     }
     for (int L = levels; L >= 2; --L) {
-        uint64_t tiles = (pairs[L - 1].capacity + LEVEL_TILE - 1) / LEVEL_TILE;
-        uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 2048);
-        k_trav_prep<<<1024, 256, 0, stream>>>(flags, ctl, meta, L, scene->n_mesh, P, 0);
+        const uint64_t tiles = (pairs[L - 1].capacity + LEVEL_TILE - 1) / LEVEL_TILE;
+        uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096);
+        const uint32_t Fu = (uint32_t)merge;
         {
             prof_scope ps("k_level", stream);
-            k_level<<<g, LEVEL_TILE, 0, stream>>>(L, (uint32_t)merge, nd, tsph, scene->m, P, flags, ctl, meta);
+            switch (nf) {
+            case 2: k_level_count<2, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, meta); break;
+            case 4: k_level_count<4, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, meta); break;
+            case 8: k_level_count<8, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, meta); break;
+            default: k_level_count<16, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, meta); break;
+            }
+        }
+        k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta);
+        {
+            prof_scope ps("k_level_emit", stream);
+            switch (nf) {
+            case 2: k_level_emit<2, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta); break;
+            case 4: k_level_emit<4, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta); break;
+            case 8: k_level_emit<8, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta); break;
+            default: k_level_emit<16, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta); break;
+            }
         }
     }
     return hip_check(hipGetLastError(), "crsh_traverse launch");
