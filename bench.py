@@ -101,10 +101,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--workload", default="refl_1024", choices=["shadow_128", "refl_1024", "mixed_1080p", "adjoint_512"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-top", type=int, default=16)
+    ap.add_argument("--cpu-sample-top", type=int, default=192)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, one device copy of this size: calibrates HBM counters under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs the single-GPU path only (asked for {args.gpus} GPUs); the multi-GPU split of "
@@ -183,6 +185,13 @@ def main():
         "roofline": roof,
         "other_kernels": other,
     }
+    if args.copy_probe_mib:
+        n4 = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 4 * n4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_top)
     print(json.dumps(out), flush=True)

@@ -389,6 +389,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_items(int32_t parent_leve
     const uint64_t n = level_items(meta, parent_level, n_mesh, P);
     const uint32_t out_level = parent_level == 0 ? nl - 1 : (uint32_t)parent_level - 2;
     const uint64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (blockIdx.x >= ntiles) return;       // only ntiles blocks take a tile
     if (threadIdx.x == 0) s_tile = atomicAdd(S.scan_ctr, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;

@@ -39,14 +39,14 @@ def oracle_run(name, seed=0, **kw):
 
 # small variants of the three plain workloads that the oracle finishes in seconds
 SMALL = {
-    "c1": {},
-    "c2s": dict(W=96, H=96),
-    "c3s": dict(W=128, H=72, n_meshes=48),
+    "shadow_128": {},
+    "refl_96": dict(W=96, H=96),
+    "mixed_128x72": dict(W=128, H=72, n_meshes=48),
 }
 
 
 def small(name, seed=0):
-    base = {"c1": "c1", "c2s": "c2", "c3s": "c3"}[name]
+    base = {"shadow_128": "shadow_128", "refl_96": "refl_1024", "mixed_128x72": "mixed_1080p"}[name]
     return base, SMALL[name]
 
 

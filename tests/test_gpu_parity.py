@@ -15,7 +15,7 @@ from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["c1", "c2s", "c3s"]
+CASES = ["shadow_128", "refl_96", "mixed_128x72"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -120,7 +120,7 @@ def test_build_bit_exact(name):
 @pytest.mark.parametrize("B,F,n", [(1, 2, 3), (4, 2, 6), (5, 7, 4), (8, 8, 2), (32, 3, 3), (16, 16, 2),
                                    (16, 4, 1)])
 def test_build_shapes(B, F, n):
-    base, kw = small("c2s")
+    base, kw = small("refl_96")
     print(f"[build-shape] B={B} F={F} n={n}", flush=True)
     o = oracle_run(base, **kw)
     ot = O.build_tree(o["hash"]["rays"], o["sorted_ids"], B, F, n)
@@ -160,7 +160,7 @@ def test_traverse_bit_exact(name):
 
 
 def test_traverse_triangle_batches():
-    base, kw = small("c2s")
+    base, kw = small("refl_96")
     wl = workload(base, **kw)
     o = oracle_run(base, **kw)
     m = wl.scene.m
@@ -178,7 +178,7 @@ def test_traverse_triangle_batches():
 
 
 def test_traverse_capacity_overflow_reports_required_size():
-    base, kw = small("c1")
+    base, kw = small("shadow_128")
     wl = workload(base, **kw)
     o = oracle_run(base, **kw)
     need = max(len(t) for t, _ in o["trav"]["pairs"].values())
@@ -222,7 +222,7 @@ def test_pipeline_end_to_end(name):
 
 
 def test_pipeline_is_deterministic():
-    base, kw = small("c2s")
+    base, kw = small("refl_96")
     wl = workload(base, **kw)
     a = _gu().run_pipeline(wl, pair_capacity=1 << 22)
     b = _gu().run_pipeline(wl, pair_capacity=1 << 22)

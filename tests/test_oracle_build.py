@@ -61,7 +61,7 @@ def check_containment(rays, sorted_ids, tree):
         assert np.all(ok), "child cone escapes its parent"
 
 
-@pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
+@pytest.mark.parametrize("name", ["shadow_128", "refl_96", "mixed_128x72"])
 def test_containment_every_node(name):
     base, kw = small(name)
     r = oracle_run(base, **kw)
@@ -70,7 +70,7 @@ def test_containment_every_node(name):
 
 @pytest.mark.parametrize("B,F,n", [(4, 2, 6), (8, 8, 2), (16, 4, 5), (32, 3, 3), (5, 7, 4)])
 def test_containment_other_shapes(B, F, n):
-    base, kw = small("c2s")
+    base, kw = small("refl_96")
     wl = workload(base, **kw)
     r = oracle_run(base, **kw)
     tree = O.build_tree(r["hash"]["rays"], r["sorted_ids"], B, F, n)

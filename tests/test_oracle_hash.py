@@ -221,17 +221,17 @@ def _interleave2(u, v):
     return m
 
 
-@pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
+@pytest.mark.parametrize("name", ["shadow_128", "refl_96", "mixed_128x72"])
 def test_workload_ray_counts(name):
     from conftest import small, oracle_run
     base, kw = small(name)
     wl = workload(base, **kw)
     h = oracle_run(base, **kw)["hash"]
     hit = wl.gbuf["mat"] >= 0
-    if name == "c1":
+    if name == "shadow_128":
         assert h["n"] == hit.sum()                     # one shadow ray per hit pixel
-    if name == "c2s":
+    if name == "refl_96":
         assert h["n"] == 2 * hit.sum()                 # shadow + reflection everywhere
-    if name == "c3s":
+    if name == "mixed_128x72":
         assert h["n"] == 3 * hit.sum()                 # 2 shadow + reflection or refraction
     assert np.all(np.diff(h["rays"]["pix"].astype(np.int64)) >= 0)

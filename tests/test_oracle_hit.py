@@ -78,7 +78,7 @@ def test_mt_matches_float64_geometry(rng):
     assert agree > 500
 
 
-@pytest.mark.parametrize("name,nsample", [("c1", None), ("c2s", 1200), ("c3s", 500)])
+@pytest.mark.parametrize("name,nsample", [("shadow_128", None), ("refl_96", 1200), ("mixed_128x72", 500)])
 def test_closest_hit_equals_brute_force(name, nsample):
     base, kw = small(name)
     wl = workload(base, **kw)
@@ -95,8 +95,8 @@ def test_closest_hit_equals_brute_force(name, nsample):
 
 @pytest.mark.parametrize("B,F,n", [(1, 2, 3), (4, 2, 6), (8, 8, 2), (32, 3, 3), (16, 4, 1)])
 def test_closest_hit_independent_of_hierarchy_shape(B, F, n):
-    wl = workload("c1")
-    r = oracle_run("c1")
+    wl = workload("shadow_128")
+    r = oracle_run("shadow_128")
     h = r["hash"]
     tree = O.build_tree(h["rays"], r["sorted_ids"], B, F, n)
     tr = O.traverse(tree, wl.scene)
@@ -106,7 +106,7 @@ def test_closest_hit_independent_of_hierarchy_shape(B, F, n):
 
 
 def test_closest_hit_over_triangle_batches():
-    base, kw = small("c2s")
+    base, kw = small("refl_96")
     wl = workload(base, **kw)
     r = oracle_run(base, **kw)
     m = wl.scene.m

@@ -113,7 +113,7 @@ def _leaf_of(sorted_ids, B):
     return leaf
 
 
-@pytest.mark.parametrize("name,nsample", [("c1", None), ("c2s", 600), ("c3s", 300)])
+@pytest.mark.parametrize("name,nsample", [("shadow_128", None), ("refl_96", 600), ("mixed_128x72", 300)])
 def test_every_brute_force_hit_survives_to_level1(name, nsample):
     """Culling is conservative: any ray-triangle hit, closest or not, keeps
     its (triangle, leaf) pair up to the final tests."""
@@ -133,7 +133,7 @@ def test_every_brute_force_hit_survives_to_level1(name, nsample):
     assert np.all(have[pos] == need)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
+@pytest.mark.parametrize("name", ["shadow_128", "refl_96", "mixed_128x72"])
 def test_pairs_descend_from_parent_pairs(name):
     base, kw = small(name)
     r = oracle_run(base, **kw)
@@ -152,7 +152,7 @@ def test_pairs_descend_from_parent_pairs(name):
         assert np.all(own[1:] != own[:-1])
 
 
-@pytest.mark.parametrize("name", ["c1", "c2s", "c3s"])
+@pytest.mark.parametrize("name", ["shadow_128", "refl_96", "mixed_128x72"])
 def test_counter_identities(name):
     base, kw = small(name)
     wl = workload(base, **kw)
@@ -194,8 +194,8 @@ def test_paper_tables_obey_the_counting_convention():
 def test_oracle_counters_follow_the_paper_convention():
     """With every node full, the oracle's counters reduce to the paper's:
     tests(k) = F * hits(k+1) and final tests = B * hits(1)."""
-    wl = workload("c1")
-    r = oracle_run("c1")
+    wl = workload("shadow_128")
+    r = oracle_run("shadow_128")
     B, F = 8, 4
     ids = r["sorted_ids"][:B * F ** 3 * 16]
     tree = O.build_tree(r["hash"]["rays"], ids, B, F, 4)
@@ -207,7 +207,7 @@ def test_oracle_counters_follow_the_paper_convention():
 
 
 def test_triangle_batches_partition_the_pairs():
-    base, kw = small("c2s")
+    base, kw = small("refl_96")
     wl = workload(base, **kw)
     r = oracle_run(base, **kw)
     m = wl.scene.m
@@ -231,7 +231,7 @@ def test_triangle_batches_partition_the_pairs():
 
 
 def test_top_subset_restricts_to_subtrees():
-    base, kw = small("c2s")
+    base, kw = small("refl_96")
     wl = workload(base, **kw)
     r = oracle_run(base, **kw)
     tree = r["tree"]

@@ -174,7 +174,7 @@ def _ico(sub):
     return _ICO[sub]
 
 
-def make_c1(seed=0, W=128, H=128, B=8, F=4, n=4):
+def make_shadow_128(seed=0, W=128, H=128, B=8, F=4, n=4):
     """4 icospheres (subdivision 2) + ground quad; 128x128; one light; shadow rays."""
     rng = np.random.default_rng(seed)
     vs, fs = _ico(2)
@@ -189,14 +189,14 @@ def make_c1(seed=0, W=128, H=128, B=8, F=4, n=4):
     eye = np.array([0, 2, 12], np.float32)
     look = np.array([0, 0, 0], np.float32)
     lights = np.array([[5, 10, 5]], np.float32)
-    return _finish("c1", seed, sc, W, H, eye, look, 45.0, lights, B, F, n, SHADOW)
+    return _finish("shadow_128", seed, sc, W, H, eye, look, 45.0, lights, B, F, n, SHADOW)
 
 
 def _room(lo, hi, sub=8):
     return _m.room_walls(lo, hi, sub)
 
 
-def make_c2(seed=0, W=1024, H=1024, n_meshes=64, B=16, F=4, n=5, with_room=True):
+def make_refl_1024(seed=0, W=1024, H=1024, n_meshes=64, B=16, F=4, n=5, with_room=True):
     """64 mixed procedural meshes in U[-10,10]^3, 1024^2, shadow + reflection."""
     rng = np.random.default_rng(seed)
     res = {"ico": 3, "torus": (32, 16), "grid": 32}
@@ -212,10 +212,10 @@ def make_c2(seed=0, W=1024, H=1024, n_meshes=64, B=16, F=4, n=5, with_room=True)
     eye = np.array([0, 8, 38], np.float32)
     look = np.array([0, 0, 0], np.float32)
     lights = np.array([[15, 25, 15]], np.float32)
-    return _finish("c2", seed, sc, W, H, eye, look, 45.0, lights, B, F, n, SHADOW | REFLECT)
+    return _finish("refl_1024", seed, sc, W, H, eye, look, 45.0, lights, B, F, n, SHADOW | REFLECT)
 
 
-def make_c3(seed=0, W=1920, H=1080, n_meshes=256, B=16, F=4, n=6, with_room=True):
+def make_mixed_1080p(seed=0, W=1920, H=1080, n_meshes=256, B=16, F=4, n=6, with_room=True):
     """256 meshes in 8 Gaussian clusters, 25 % refractive; 1920x1080; 2 lights."""
     rng = np.random.default_rng(seed)
     res = {"ico": 3, "torus": (48, 24), "grid": 32}
@@ -236,11 +236,11 @@ def make_c3(seed=0, W=1920, H=1080, n_meshes=256, B=16, F=4, n=6, with_room=True
     eye = np.array([0, 10, 45], np.float32)
     look = np.array([0, 0, 0], np.float32)
     lights = np.array([[15, 25, 15], [-20, 22, -10]], np.float32)
-    return _finish("c3", seed, sc, W, H, eye, look, 45.0, lights, B, F, n,
+    return _finish("mixed_1080p", seed, sc, W, H, eye, look, 45.0, lights, B, F, n,
                    SHADOW | REFLECT | REFRACT)
 
 
-def make_c5(seed=0, W=512, H=512, B=16, F=4, n=5):
+def make_adjoint_512(seed=0, W=512, H=512, B=16, F=4, n=5):
     """16 displaced icospheres (subdivision 3, indexed), 512^2 reflection rays."""
     rng = np.random.default_rng(seed)
     vs, fs = _ico(3)
@@ -255,7 +255,7 @@ def make_c5(seed=0, W=512, H=512, B=16, F=4, n=5):
     eye = np.array([0, 2, 18], np.float32)
     look = np.array([0, 0, 0], np.float32)
     lights = np.zeros((0, 3), np.float32)
-    return _finish("c5", seed, sc, W, H, eye, look, 45.0, lights, B, F, n, REFLECT)
+    return _finish("adjoint_512", seed, sc, W, H, eye, look, 45.0, lights, B, F, n, REFLECT)
 
 
 def make_frame(seed, target_rays, target_tris, B=16, F=4, n=5):
@@ -299,7 +299,7 @@ def _finish(name, seed, sc, W, H, eye, look, vfov, lights, B, F, n, types):
                     lo=lo, inv_ext=inv)
 
 
-MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c5": make_c5}
+MAKERS = {"shadow_128": make_shadow_128, "refl_1024": make_refl_1024, "mixed_1080p": make_mixed_1080p, "adjoint_512": make_adjoint_512}
 
 
 def make_workload(name, seed=0, **kw):
