@@ -101,7 +101,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="refl_1024", choices=["shadow_128", "refl_1024", "mixed_1080p", "adjoint_512"])
+    ap.add_argument("--workload", default="refl_1024",
+                    choices=["shadow_128", "refl_1024", "mixed_1080p", "adjoint_512", "batch_64"])
+    ap.add_argument("--frames", type=int, default=64, help="batch_64: number of frames")
+    ap.add_argument("--tune", action="store_true",
+                    help="batch_64: tune (B, levels, hit_block) by timing the captured batch")
+    ap.add_argument("--tune-cache", default=None, help="batch_64: JSON cache of tuned points")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-top", type=int, default=192)
@@ -112,6 +117,9 @@ def main():
         print(f"bench.py runs the single-GPU path only (asked for {args.gpus} GPUs); the multi-GPU split of "
               "the path is described in DESIGN.md but not built", file=sys.stderr)
         return 2
+
+    if args.workload == "batch_64":
+        return bench_batch(args)
 
     import torch
     from workloads import make_workload
@@ -194,6 +202,99 @@ def main():
         out["copy_probe_bytes"] = 4 * n4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_top)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batch(args):
+    """Batched form: `frames` independent frames (log-uniform sizes) as one
+    captured batch, against the same frames one after the other through the
+    plain calls with the same hierarchy shape."""
+    import dataclasses
+
+    import torch
+    from workloads.scenes import make_batch
+    from paper_2312_06538_amd import crsh as X
+    from paper_2312_06538_amd import pipeline as P
+    from paper_2312_06538_amd import tune as T
+    from paper_2312_06538_amd.batch import DeviceBatch
+
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    wls = make_batch(args.seed, args.frames)
+    log(f"[bench] batch of {len(wls)} frames built in {time.perf_counter() - t0:.1f}s")
+    stream = torch.cuda.Stream()
+    p = dict(T.START)
+    db = DeviceBatch(wls, p["B"], 4, p["levels"], p["hit_block"], pair_capacity=1 << 24)
+    tuned = "default"
+    if args.tune or args.tune_cache:
+        cache = T.TuneCache(args.tune_cache) if args.tune_cache else None
+        best, ms, seen = T.tune_batch(db, stream, cache=cache, log=log)
+        p = best
+        tuned = f"tuned over {len(seen)} points" if seen else "from cache"
+    m = db.run_with_retry()
+    n = int(m.n_rays)
+    g = db.graph(stream)
+    for _ in range(args.warmup):
+        g.launch()
+    stream.synchronize()
+    ev = HipEvents(1)
+    a, b = ev.pair(0)
+    h = ev.h
+    t0 = time.perf_counter()
+    h.hipEventRecord(a, ctypes.c_void_p(stream.cuda_stream))
+    for _ in range(args.steps):
+        g.launch()
+    h.hipEventRecord(b, ctypes.c_void_p(stream.cuda_stream))
+    stream.synchronize()
+    t1 = time.perf_counter()
+    ms_batch = ev.ms(0) / args.steps
+    m2, st = db.read_meta(stream)
+    assert st == X.OK, X.last_error()
+    g.close()
+    log(f"[bench] batch: {n} rays, {ms_batch:.3f} ms per batch ({p})")
+    # the same frames one by one through the plain calls (pre-sized, no host
+    # synchronisation between frames), the same B / F / levels
+    plain = []
+    for wl in wls:
+        w2 = dataclasses.replace(wl, B=p["B"], F=4, n=p["levels"])
+        fr = P.DeviceFrame(w2)
+        bf = P.Buffers(fr, 1 << 20)
+        bf, _ = P.run_with_retry(fr, bf)
+        plain.append((fr, bf))
+    for _ in range(args.warmup):
+        for fr, bf in plain:
+            P.run_frame(fr, bf)
+    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream().cuda_stream
+    h.hipEventRecord(a, ctypes.c_void_p(cur))
+    for _ in range(args.steps):
+        for fr, bf in plain:
+            P.run_frame(fr, bf)
+    h.hipEventRecord(b, ctypes.c_void_p(cur))
+    torch.cuda.synchronize()
+    ms_plain = ev.ms(0) / args.steps
+    n_plain = sum(int(P.read_meta(bf)[0].n_rays) for _, bf in plain)
+    assert n_plain == n
+    tris = sum(wl.scene.m for wl in wls)
+    out = {
+        "metric": "secondary rays/sec (hash+sort+build+traverse+hit), batched frames",
+        "value": round(n / (ms_batch * 1e-3), 1),
+        "unit": "secondary rays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_batch, 4),
+        "host_ms_per_step": round((t1 - t0) / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch_64: {len(wls)} frames, rays per frame log-uniform in [4096, 1M], "
+                               f"triangles per frame log-uniform in [1000, 200000], shadow+reflection",
+                   "rays": n, "triangles": tris, "B": p["B"], "F": 4, "levels": p["levels"],
+                   "hit_block": p["hit_block"], "params": tuned, "seed": args.seed},
+        "per_frame_plain": {"ms_per_batch": round(ms_plain, 4), "value": round(n / (ms_plain * 1e-3), 1),
+                            "speedup_of_batch": round(ms_plain / ms_batch, 3)},
+        "tests": {"final_ray_tri_tests": int(m2.final_tests),
+                  "node_tests": sum(int(m2.tests[k]) for k in range(int(m2.n_levels)))},
+    }
     print(json.dumps(out), flush=True)
     return 0
 

@@ -56,6 +56,8 @@ typedef enum crsh_status {
 #define CRSH_OVERFLOW_RAYS 1u    /* more secondary rays than crsh_rays.capacity */
 #define CRSH_OVERFLOW_NODES 2u   /* more nodes than crsh_nodes.capacity */
 #define CRSH_OVERFLOW_PAIRS 4u   /* a pair level exceeded its crsh_pairs.capacity */
+#define CRSH_OVERFLOW_ITEMS 8u   /* batched form: more top-level (node, mesh) items than
+                                    crsh_batch.top_item_capacity */
 
 /* ray-type bits of crsh_raygen.ray_types */
 #define CRSH_RAY_SHADOW 1u
@@ -245,6 +247,151 @@ crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t *sorted_ids
                              const crsh_scene *scene, float t_min,
                              crsh_hits *hits, crsh_meta *meta,
                              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Stage 1 for rays the caller already has (e.g. a differentiable renderer):
+ * keys[i] = the hash of ray i under the same layout as crsh_hash -- `type`
+ * 0 shadow (bits 29-28 = `light`), 1 reflection, 2 refraction (origin cell
+ * in the box [lo, lo + 1/inv_ext]) -- and ids[i] = i, for i < n.  Writes
+ * meta->n_rays = n.  rays->capacity must be >= n. */
+crsh_status crsh_hash_rays(const crsh_rays *rays, uint32_t n, uint32_t type, uint32_t light,
+                           const float lo[3], const float inv_ext[3], uint32_t *keys, uint32_t *ids,
+                           crsh_meta *meta, hipStream_t stream);
+
+/* Layout helper for indexed meshes: v[k][i] = verts[3 * faces[3 * i + k / 3] + k % 3]
+ * (the nine triangle arrays of crsh_scene) for the m triangles; faces index
+ * the n_verts vertices (xyz interleaved).  A triangle with an index outside
+ * [0, n_verts) is written as all zeros (degenerate: never hit). */
+crsh_status crsh_gather_triangles(const float *verts, uint32_t n_verts, const int32_t *faces, uint32_t m,
+                                  float *const v[9], hipStream_t stream);
+
+/* Adjoint of the closest hit (Sec. 3.3.8) with respect to the triangle
+ * vertices and the ray, holding each ray's hit triangle fixed.  For ray i
+ * with hit triangle tri[i] >= 0 (t, u, v from crsh_closest_hit), the
+ * Moller-Trumbore solution satisfies O + t D = (1-u-v) v0 + u v1 + v v2; with
+ * upstream gradients (g_t, g_u, g_v) and lambda solving
+ * [D | -e1 | -e2]^T lambda = (g_t, g_u, g_v) (recomputed per hit from cross
+ * products, nothing stored by the forward pass):
+ *   dL/dO = -lambda, dL/dD = -t lambda,
+ *   dL/dv0 += (1-u-v) lambda, dL/dv1 += u lambda, dL/dv2 += v lambda.
+ * Rays are by ray id (origin, direction), n of them; hits->tri/t/u/v by ray
+ * id; faces index verts (xyz interleaved).  g_verts (3 floats per vertex) is
+ * ACCUMULATED with float32 atomics -- the caller zeroes it; g_o, g_d
+ * (3 floats per ray, xyz interleaved) are written, zero for misses.  Any of
+ * g_t, g_u, g_v may be NULL (zero). */
+crsh_status crsh_closest_hit_backward(const crsh_rays *rays, uint32_t n, const crsh_hits *hits,
+                                      const float *g_t, const float *g_u, const float *g_v,
+                                      const float *verts, uint32_t n_verts, const int32_t *faces, uint32_t m,
+                                      float *g_verts, float *g_o, float *g_d, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent frames (each its own primary-hit buffer,
+ * lights, camera, materials and meshes) run as ONE pipeline.  Arrays are the
+ * concatenation of the frames' arrays; every stage is one launch sequence
+ * for the whole batch, each kernel finding its frame from per-frame offsets
+ * on the device, so frames of a few thousand rays do not leave the chip
+ * idle.  Per frame the results are exactly those of the plain calls with the
+ * same bundle / merge / levels: a frame's rays, keys, sorted order, nodes,
+ * pairs and closest hits do not depend on the other frames (node ids and
+ * sorted positions are offset by the frame's bases).  The sequence allocates
+ * nothing, synchronises nothing and records no memset, so it can be captured
+ * into one hipGraph (crsh_batch_graph_create).
+ *
+ * Layout.  Frame f's pixels, rays, sorted rays and hits are the ranges that
+ * start at crsh_frame.pix_begin and crsh_frame_meta.ray_begin.  Level k+1 of
+ * the node arrays holds every frame's nodes of that level, frame by frame
+ * (frame f's at crsh_frame_meta.level_base[k] within the level), and levels
+ * are packed as in crsh_build (meta->level_off).  A frame's hierarchy stops
+ * after `levels` levels or at its first level with one node, so frames have
+ * different top levels; pairs[k] holds level k+1 pairs of all frames: first
+ * those that descend from level k+2, in parent order, then the top-level
+ * pairs of frames whose top is level k+1, frame by frame.  Each frame's
+ * subsequence is exactly its plain pair list with node ids offset by
+ * level_base[k].
+ * ------------------------------------------------------------------------ */
+
+#define CRSH_MAX_FRAMES 256
+
+/* One frame of a batch (an array of these lives in device memory).  Frames
+ * must cover the primary-hit buffer in order: frame 0 starts at pixel 0 and
+ * frame f+1 at pix_begin + pix_count of frame f. */
+typedef struct crsh_frame {
+    uint32_t pix_begin, pix_count;      /* this frame's pixels in the batch's primary-hit buffer */
+    uint32_t mesh_begin, mesh_count;    /* this frame's meshes in the batch's scene (their triangle
+                                           ranges index the batch's triangle arrays) */
+    uint32_t mat_begin, n_mats;         /* this frame's materials in the batch's material tables */
+    int32_t n_lights;
+    uint32_t ray_types;
+    float lights[CRSH_MAX_LIGHTS][3];
+    float eye[3];
+    float eps_off, eps_shadow, t_min;
+    float lo[3], inv_ext[3];            /* bounce-ray origin box, as in crsh_raygen */
+} crsh_frame;
+
+/* Per-frame results written on the device by the batched stages. */
+typedef struct crsh_frame_meta {
+    uint32_t ray_begin, n_rays;         /* the frame's rays in the batch's ray arrays */
+    uint32_t n_levels;                  /* levels of the frame's hierarchy (top = n_levels) */
+    uint32_t reserved;
+    uint32_t level_base[CRSH_MAX_LEVELS];   /* first node of the frame within level k+1 */
+    uint32_t level_cnt[CRSH_MAX_LEVELS];    /* nodes of the frame on level k+1 */
+    uint64_t item_base;                 /* scratch of the top-level traversal pass */
+} crsh_frame_meta;
+
+/* Everything a batch reads and writes; all pointers are device pointers.
+ * gbuf covers all frames' pixels (w = total pixels, h = 1); material indices
+ * in gbuf.mat are frame-local.  rays, sorted and keys/ids/skeys/sids/
+ * ray_frame hold rays.capacity entries (enough for every pixel's
+ * n_lights + 2 slots never overflows); ray_frame receives each ray's frame.
+ * meta receives batch totals (n_rays, per-level node offsets and totals,
+ * pair counts, counters summed over frames).  nodes, pairs and hits as in
+ * the plain calls.  top_item_capacity bounds the (top node, mesh) items of
+ * one top-level pass: the sum over the frames that share a top level of
+ * top nodes x meshes.  bundle / merge / levels shape every frame's
+ * hierarchy; hit_block (64, 128 or 256) is the workgroup size of the final
+ * tests.  ws: crsh_batch_ws_size() bytes. */
+typedef struct crsh_batch {
+    uint32_t n_frames;                  /* 1 .. CRSH_MAX_FRAMES */
+    const crsh_frame *frames;
+    crsh_frame_meta *frame_meta;
+    crsh_gbuf gbuf;
+    const uint32_t *mat_flags;
+    const float *mat_ior;
+    crsh_scene scene;
+    crsh_rays rays, sorted;
+    uint32_t *keys, *ids, *skeys, *sids, *ray_frame;
+    crsh_nodes nodes;
+    crsh_pairs pairs[CRSH_MAX_LEVELS];
+    crsh_hits hits;
+    crsh_meta *meta;
+    uint64_t top_item_capacity;
+    void *ws;
+    size_t ws_bytes;
+    int32_t bundle, merge, levels, hit_block;
+} crsh_batch;
+
+typedef struct crsh_graph crsh_graph;
+
+/* Workspace of a batch: max_rays rays (and at most as many pixels),
+ * max_tris triangles, max_nodes nodes, max_pairs pairs per level and
+ * max_top_items top-level items. */
+size_t crsh_batch_ws_size(uint32_t max_rays, uint32_t max_tris, uint32_t max_nodes, uint64_t max_pairs,
+                          uint64_t max_top_items);
+
+/* Enqueue the whole batched pipeline (clear, hash, sort, build, traverse,
+ * closest hit) on a stream.  Overflow is reported through meta as for the
+ * plain calls (crsh_read_meta after the stream completes); the caller then
+ * grows the named buffer and runs the batch again.  Argument errors return
+ * CRSH_ERR_INVALID before anything is enqueued. */
+crsh_status crsh_batch_enqueue(const crsh_batch *b, hipStream_t stream);
+
+/* Capture crsh_batch_enqueue on `stream` (not the legacy default stream) into
+ * a hipGraph and instantiate it; crsh_graph_launch replays the whole batch
+ * with one launch.  The graph keeps the pointers and sizes of `b`: replays
+ * read the device arrays' current contents.  No kernel timer may be armed
+ * (crsh_profile_next) while capturing. */
+crsh_status crsh_batch_graph_create(const crsh_batch *b, hipStream_t stream, crsh_graph **out);
+crsh_status crsh_graph_launch(crsh_graph *g, hipStream_t stream);
+void crsh_graph_destroy(crsh_graph *g);
 
 /* Instrumentation.  Arms a one-shot timer: the `occurrence`-th launch
  * (0-based, counted from this call, in the calling thread) of the library

@@ -14,9 +14,10 @@ MAX_LEVELS = 16
 MAX_LIGHTS = 4
 MAX_BUNDLE = 32
 MAX_MERGE = 16
+MAX_FRAMES = 256
 
 OK, ERR_INVALID, ERR_CAPACITY, ERR_HIP = 0, 1, 2, 3
-OVERFLOW_RAYS, OVERFLOW_NODES, OVERFLOW_PAIRS = 1, 2, 4
+OVERFLOW_RAYS, OVERFLOW_NODES, OVERFLOW_PAIRS, OVERFLOW_ITEMS = 1, 2, 4, 8
 RAY_SHADOW, RAY_REFLECT, RAY_REFRACT = 1, 2, 4
 
 vp = C.c_void_p
@@ -75,6 +76,32 @@ class Hits(C.Structure):
 
 PairTable = Pairs * MAX_LEVELS
 
+
+class Frame(C.Structure):
+    _fields_ = [("pix_begin", C.c_uint32), ("pix_count", C.c_uint32),
+                ("mesh_begin", C.c_uint32), ("mesh_count", C.c_uint32),
+                ("mat_begin", C.c_uint32), ("n_mats", C.c_uint32),
+                ("n_lights", C.c_int32), ("ray_types", C.c_uint32),
+                ("lights", (C.c_float * 3) * MAX_LIGHTS), ("eye", C.c_float * 3),
+                ("eps_off", C.c_float), ("eps_shadow", C.c_float), ("t_min", C.c_float),
+                ("lo", C.c_float * 3), ("inv_ext", C.c_float * 3)]
+
+
+class FrameMeta(C.Structure):
+    _fields_ = [("ray_begin", C.c_uint32), ("n_rays", C.c_uint32), ("n_levels", C.c_uint32),
+                ("reserved", C.c_uint32),
+                ("level_base", C.c_uint32 * MAX_LEVELS), ("level_cnt", C.c_uint32 * MAX_LEVELS),
+                ("item_base", C.c_uint64)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("n_frames", C.c_uint32), ("frames", vp), ("frame_meta", vp), ("gbuf", Gbuf),
+                ("mat_flags", vp), ("mat_ior", vp), ("scene", Scene), ("rays", Rays), ("sorted", Rays),
+                ("keys", vp), ("ids", vp), ("skeys", vp), ("sids", vp), ("ray_frame", vp),
+                ("nodes", Nodes), ("pairs", PairTable), ("hits", Hits), ("meta", vp),
+                ("top_item_capacity", C.c_uint64), ("ws", vp), ("ws_bytes", C.c_size_t),
+                ("bundle", C.c_int32), ("merge", C.c_int32), ("levels", C.c_int32), ("hit_block", C.c_int32)]
+
 _lib = None
 
 
@@ -111,8 +138,26 @@ def lib():
                                     C.c_int32, PairTable, vp, vp, C.c_size_t, vp]
         L.crsh_hits_reset.restype = st
         L.crsh_hits_reset.argtypes = [C.POINTER(Hits), vp]
+        L.crsh_hash_rays.restype = st
+        L.crsh_hash_rays.argtypes = [C.POINTER(Rays), C.c_uint32, C.c_uint32, C.c_uint32, C.c_float * 3,
+                                     C.c_float * 3, vp, vp, vp, vp]
+        L.crsh_gather_triangles.restype = st
+        L.crsh_gather_triangles.argtypes = [vp, C.c_uint32, vp, C.c_uint32, vp * 9, vp]
+        L.crsh_closest_hit_backward.restype = st
+        L.crsh_closest_hit_backward.argtypes = [C.POINTER(Rays), C.c_uint32, C.POINTER(Hits), vp, vp, vp, vp,
+                                                C.c_uint32, vp, C.c_uint32, vp, vp, vp, vp]
         L.crsh_profile_next.restype = st
         L.crsh_profile_next.argtypes = [C.c_char_p, C.c_int32, vp, vp]
+        L.crsh_batch_ws_size.restype = C.c_size_t
+        L.crsh_batch_ws_size.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint64]
+        L.crsh_batch_enqueue.restype = st
+        L.crsh_batch_enqueue.argtypes = [C.POINTER(Batch), vp]
+        L.crsh_batch_graph_create.restype = st
+        L.crsh_batch_graph_create.argtypes = [C.POINTER(Batch), vp, C.POINTER(vp)]
+        L.crsh_graph_launch.restype = st
+        L.crsh_graph_launch.argtypes = [vp, vp]
+        L.crsh_graph_destroy.restype = None
+        L.crsh_graph_destroy.argtypes = [vp]
         L.crsh_closest_hit.restype = st
         L.crsh_closest_hit.argtypes = [C.POINTER(Rays), vp, C.c_int32, C.POINTER(Pairs), C.POINTER(Scene),
                                        C.c_float, C.POINTER(Hits), vp, vp, C.c_size_t, vp]
@@ -176,3 +221,44 @@ def crsh_closest_hit(sorted_rays, sorted_ids, bundle, level1, scene, t_min, hits
 def crsh_profile_next(kernel, occurrence, start_event, stop_event):
     """Arm the one-shot timer; events are hipEvent_t handles (torch.cuda.Event.cuda_event)."""
     return _check(lib().crsh_profile_next(kernel.encode(), occurrence, start_event, stop_event))
+
+
+def crsh_hash_rays(rays, n, typ, light, lo, inv_ext, keys, ids, meta, stream):
+    lo3 = (C.c_float * 3)(*[float(x) for x in lo])
+    inv3 = (C.c_float * 3)(*[float(x) for x in inv_ext])
+    return _check(lib().crsh_hash_rays(C.byref(rays), n, typ, light, lo3, inv3, keys, ids, meta, stream))
+
+
+def crsh_gather_triangles(verts, n_verts, faces, m, v9, stream):
+    return _check(lib().crsh_gather_triangles(verts, n_verts, faces, m, (vp * 9)(*v9), stream))
+
+
+def crsh_closest_hit_backward(rays, n, hits, g_t, g_u, g_v, verts, n_verts, faces, m, g_verts, g_o, g_d, stream):
+    return _check(lib().crsh_closest_hit_backward(C.byref(rays), n, C.byref(hits), g_t, g_u, g_v, verts, n_verts,
+                                                  faces, m, g_verts, g_o, g_d, stream))
+
+
+def crsh_batch_ws_size(max_rays, max_tris, max_nodes, max_pairs, max_top_items):
+    return int(lib().crsh_batch_ws_size(max_rays, max_tris, max_nodes, max_pairs, max_top_items))
+
+
+def crsh_batch_enqueue(batch, stream):
+    return _check(lib().crsh_batch_enqueue(C.byref(batch), stream))
+
+
+def crsh_batch_graph_create(batch, stream):
+    g = vp()
+    _check(lib().crsh_batch_graph_create(C.byref(batch), stream, C.byref(g)))
+    return g
+
+
+def crsh_graph_launch(graph, stream):
+    return _check(lib().crsh_graph_launch(graph, stream))
+
+
+def crsh_graph_destroy(graph):
+    lib().crsh_graph_destroy(graph)
+
+
+def ctypes_sizeof_meta():
+    return C.sizeof(Meta)

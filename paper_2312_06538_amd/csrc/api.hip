@@ -67,9 +67,9 @@ size_t sort_ws_bytes(uint32_t cap)
 {
     size_t tiles = (cap + SORT_TILE - 1) / SORT_TILE;
     return align256((size_t)cap * 4) * 2                   // alternate keys, ids
-           + align256(SORT_PASSES * 256 * 4)               // digit histograms
+           + align256((SORT_PASSES + 1) * 256 * 4)         // digit histograms (+ frame digit)
            + align256(64 * 4)                              // pass plan + tile counters
-           + align256(SORT_PASSES * tiles * 256 * 4);      // look-back words
+           + align256((SORT_PASSES + 1) * tiles * 256 * 4);   // look-back words
 }
 
 size_t hash_ws_bytes(uint64_t pixels)

@@ -11,107 +11,16 @@
 //               children's spheres (Eq. 7-8) and cones (Eq. 5-6).
 // Trees are unrolled over a power-of-two slot count, so every slot index is a
 // compile-time constant and the nodes stay in registers.
-#include "common.hpp"
+//
+// Batched form: k_batch_levels sizes every frame's levels (the same rule as
+// k_build_info, per frame) and lays each level out frame by frame; the leaf
+// and upper kernels find their frame and take their rays / children from the
+// frame's ranges, and record each node's first ray or child and its count
+// (with the frame) for the traversal and the final tests.
+#include "batch.hpp"
+#include "bounds.hpp"
 
 namespace crsh {
-
-struct cone {
-    f3 x;
-    float c, s;
-};
-struct sph {
-    f3 c;
-    float r;
-};
-
-__device__ __forceinline__ cone full_cone(f3 x)
-{
-    cone k;
-    k.x = x;
-    k.c = -1.0f;
-    k.s = 0.0f;
-    return k;
-}
-
-__device__ __forceinline__ bool is_full(const cone &k) { return !(k.c > 0.0f); }
-
-// Widen by CONE_PAD radians (a first-order rotation of (c, s)); cones of 90
-// degrees or more become the canonical full cone.
-__device__ __forceinline__ cone widen(cone k)
-{
-    if (!(k.c > 0.0f)) return full_cone(k.x);
-    cone o = k;
-    o.c = k.c - CONE_PAD * k.s;
-    o.s = k.s + CONE_PAD * k.c;
-    if (!(o.c > 0.0f)) return full_cone(k.x);
-    return o;
-}
-
-// Eq. 5-6: bisector axis; half-angle = half the axis angle + larger spread,
-// by the angle-addition formulas on (cos, sin).
-__device__ __forceinline__ cone merge_cones(const cone &a, const cone &b)
-{
-    if (is_full(a) || is_full(b)) return full_cone(a.x);
-    f3 sum = a.x + b.x;
-    float h = len(sum);
-    if (!(h >= BISECT_MIN)) return full_cone(a.x);
-    cone o;
-    o.x = sum / h;
-    float ch = h * 0.5f;
-    float sh = len(a.x - b.x) * 0.5f;
-    float cm = a.c, sm = a.s;
-    if (b.s > a.s) {
-        cm = b.c;
-        sm = b.s;
-    }
-    o.c = ch * cm - sh * sm;
-    o.s = sh * cm + ch * sm;
-    return widen(o);
-}
-
-// Eq. 1-4: grow a cone to take in ray direction r.
-__device__ __forceinline__ cone cone_take(const cone &k, f3 r)
-{
-    if (is_full(k)) return k;
-    f3 nv = cross(k.x, r);
-    float st = len(nv);
-    float ct = dot(k.x, r);
-    if (ct > 0.0f && (st == 0.0f || k.s * ct - k.c * st >= INSIDE_MARGIN)) return k;
-    if (st == 0.0f || k.s * ct + k.c * st <= 0.0f) return full_cone(k.x);
-    if (st < NEAR_PARALLEL) {
-        cone rr;
-        rr.x = r;
-        rr.c = 1.0f;
-        rr.s = 0.0f;
-        return merge_cones(k, rr);
-    }
-    f3 q = -(cross(nv, k.x) / st);         // Eq. 1: away from r, orthogonal to x
-    f3 e = k.x * k.c + q * k.s;            // Eq. 2: far edge
-    f3 er = e + r;
-    float h = len(er);
-    if (!(h >= BISECT_MIN)) return full_cone(k.x);
-    cone o;
-    o.x = er / h;                          // Eq. 3
-    o.c = dot(o.x, r);                     // Eq. 4
-    o.s = len(e - r) * 0.5f;
-    return widen(o);
-}
-
-__device__ __forceinline__ float grow_radius(f3 c, float r)
-{
-    float m = fmax2(fmax2(fabsf(c.x), fabsf(c.y)), fabsf(c.z));
-    return r + SPHERE_PAD * (r + m);
-}
-
-// Eq. 7-8
-__device__ __forceinline__ sph merge_spheres(const sph &a, const sph &b)
-{
-    sph o;
-    o.c = (a.c + b.c) * 0.5f;
-    float e = len(b.c - a.c) * 0.5f;
-    o.r = grow_radius(o.c, e + fmax2(a.r, b.r));
-    return o;
-}
 
 struct nodes_dev {
     float *cx, *cy, *cz, *r, *ax, *ay, *az, *c, *s, *tan, *sec;
@@ -166,6 +75,65 @@ __global__ void k_build_info(crsh_meta *meta, uint32_t B, uint32_t F, uint32_t l
     meta->n_levels = nl;
 }
 
+// One thread per frame (at most CRSH_MAX_FRAMES frames, one block).
+__global__ __launch_bounds__(256) void k_batch_levels(batch_dev bd, crsh_meta *meta, uint32_t B, uint32_t F,
+                                                      uint32_t levels, uint32_t node_cap, uint32_t ray_cap)
+{
+    __shared__ uint32_t scratch[256 / WAVE];
+    __shared__ uint32_t s_total[CRSH_MAX_LEVELS];
+    __shared__ uint32_t s_nl;
+    const uint32_t f = threadIdx.x;
+    const bool live = f < bd.n_frames;
+    const uint32_t n = min(meta->n_rays, ray_cap);
+    if (f == 0) s_nl = 0;
+    uint32_t rb = live ? min(bd.fm[f].ray_begin, n) : n;
+    uint32_t re = (f + 1 < bd.n_frames) ? min(bd.fm[f + 1].ray_begin, n) : n;
+    const uint32_t nr = (live && re > rb) ? re - rb : 0u;
+    __syncthreads();
+    uint32_t nl = 0, c = 0;
+    for (uint32_t k = 0; k < CRSH_MAX_LEVELS; ++k) {
+        // the plain rule per frame: ceil(n / B) leaves, then ceil(c / F) while
+        // under `levels` levels and more than one node
+        if (k == 0) {
+            c = (nr + B - 1) / B;
+            nl = nr ? 1u : 0u;
+        } else if (nl == k && k < levels && c > 1) {
+            c = (c + F - 1) / F;
+            nl = k + 1;
+        }
+        const uint32_t ck = k < nl ? c : 0u;
+        uint32_t total;
+        const uint32_t base = block_excl_scan<uint32_t, 256 / WAVE>(ck, scratch, total);
+        if (live) {
+            bd.fm[f].level_base[k] = base;
+            bd.fm[f].level_cnt[k] = ck;
+        }
+        if (f == 0) s_total[k] = total;
+    }
+    if (live) atomicMax(&s_nl, nl);
+    __syncthreads();
+    uint32_t total = 0;
+    for (uint32_t k = 0; k < CRSH_MAX_LEVELS; ++k) total += s_total[k];
+    const bool over = total > node_cap;
+    if (live) {
+        bd.fm[f].ray_begin = rb;
+        bd.fm[f].n_rays = nr;
+        bd.fm[f].n_levels = over ? 0u : nl;
+    }
+    if (f == 0) {
+        uint32_t off = 0;
+        for (uint32_t k = 0; k < CRSH_MAX_LEVELS; ++k) {
+            meta->level_off[k] = off;
+            meta->level_cnt[k] = s_total[k];
+            off += s_total[k];
+        }
+        meta->n_rays = n;
+        meta->nodes_required = total;
+        if (over) atomicOr(&meta->status, CRSH_OVERFLOW_NODES);
+        meta->n_levels = over ? 0u : s_nl;
+    }
+}
+
 struct rays_in {
     const float *ox, *oy, *oz, *dx, *dy, *dz, *tmax;
     const uint32_t *pix;
@@ -193,17 +161,26 @@ __global__ void k_permute(rays_in in, const uint32_t *sorted_ids, rays_out out, 
     }
 }
 
-template <int NB>
+template <int NB, bool BATCH>
 __global__ __launch_bounds__(256) void k_build_leaf(const float *__restrict__ ox, const float *__restrict__ oy,
                                                     const float *__restrict__ oz, const float *__restrict__ dx,
                                                     const float *__restrict__ dy, const float *__restrict__ dz,
-                                                    uint32_t B, nodes_dev nd, const crsh_meta *meta)
+                                                    uint32_t B, nodes_dev nd, const crsh_meta *meta, batch_dev bd)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (meta->n_levels == 0 || j >= meta->level_cnt[0]) return;
-    const uint32_t n = meta->n_rays;
-    const uint32_t b = j * B;
-    const uint32_t k = min(B, n - b);
+    uint32_t b, k;
+    if constexpr (BATCH) {
+        const uint32_t f = frame_of_node(bd, 0, j);
+        const uint32_t local = (j - bd.fm[f].level_base[0]) * B;
+        b = bd.fm[f].ray_begin + local;
+        k = min(B, bd.fm[f].n_rays - local);
+        bd.node_first[j] = b;
+        bd.node_info[j] = k | (f << INFO_FRAME_SHIFT);
+    } else {
+        b = j * B;
+        k = min(B, meta->n_rays - b);
+    }
     sph sp[NB];
     cone kc;
 #pragma unroll
@@ -231,15 +208,25 @@ __global__ __launch_bounds__(256) void k_build_leaf(const float *__restrict__ ox
     put_node(nd, j, sp[0], kc);
 }
 
-template <int NF>
-__global__ __launch_bounds__(256) void k_build_up(uint32_t lv, uint32_t F, nodes_dev nd, const crsh_meta *meta)
+template <int NF, bool BATCH>
+__global__ __launch_bounds__(256) void k_build_up(uint32_t lv, uint32_t F, nodes_dev nd, const crsh_meta *meta,
+                                                  batch_dev bd)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (lv >= meta->n_levels || j >= meta->level_cnt[lv]) return;
     const uint32_t below = meta->level_off[lv - 1];
-    const uint32_t nb = meta->level_cnt[lv - 1];
-    const uint32_t b = j * F;
-    const uint32_t k = min(F, nb - b);
+    uint32_t b, k;
+    if constexpr (BATCH) {
+        const uint32_t f = frame_of_node(bd, lv, j);
+        const uint32_t local = (j - bd.fm[f].level_base[lv]) * F;
+        b = bd.fm[f].level_base[lv - 1] + local;
+        k = min(F, bd.fm[f].level_cnt[lv - 1] - local);
+        bd.node_first[meta->level_off[lv] + j] = b;
+        bd.node_info[meta->level_off[lv] + j] = k | (f << INFO_FRAME_SHIFT);
+    } else {
+        b = j * F;
+        k = min(F, meta->level_cnt[lv - 1] - b);
+    }
     sph sp[NF];
     cone kc[NF];
 #pragma unroll
@@ -277,9 +264,11 @@ static int pow2_at_least(int x)
 
 using namespace crsh;
 
-extern "C" crsh_status crsh_build(const crsh_rays *rays, const uint32_t *sorted_ids, int32_t bundle, int32_t merge,
-                                  int32_t levels, crsh_nodes *nodes, crsh_rays *sorted, crsh_meta *meta,
-                                  hipStream_t stream)
+namespace crsh {
+
+crsh_status build_launch(const crsh_rays *rays, const uint32_t *sorted_ids, int32_t bundle, int32_t merge,
+                         int32_t levels, crsh_nodes *nodes, crsh_rays *sorted, crsh_meta *meta,
+                         const batch_dev *bd, hipStream_t stream)
 {
     if (!rays || !sorted_ids || !nodes || !sorted || !meta) {
         set_error("crsh_build: NULL argument");
@@ -305,8 +294,13 @@ extern "C" crsh_status crsh_build(const crsh_rays *rays, const uint32_t *sorted_
         set_error("crsh_build: incomplete node arrays");
         return CRSH_ERR_INVALID;
     }
-    k_build_info<<<1, 1, 0, stream>>>(meta, (uint32_t)bundle, (uint32_t)merge, (uint32_t)levels, nodes->capacity,
-                                      rays->capacity);
+    const batch_dev b = bd ? *bd : batch_dev{};
+    if (bd)
+        k_batch_levels<<<1, 256, 0, stream>>>(b, meta, (uint32_t)bundle, (uint32_t)merge, (uint32_t)levels,
+                                               nodes->capacity, rays->capacity);
+    else
+        k_build_info<<<1, 1, 0, stream>>>(meta, (uint32_t)bundle, (uint32_t)merge, (uint32_t)levels,
+                                          nodes->capacity, rays->capacity);
     rays_in ri{rays->ox, rays->oy, rays->oz, rays->dx, rays->dy, rays->dz, rays->tmax, rays->pix};
     rays_out ro{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax, sorted->pix};
     uint32_t cap = rays->capacity;
@@ -318,30 +312,51 @@ extern "C" crsh_status crsh_build(const crsh_rays *rays, const uint32_t *sorted_
     }
     nodes_dev nd{nodes->cx, nodes->cy, nodes->cz, nodes->r, nodes->ax, nodes->ay, nodes->az,
                  nodes->c, nodes->s, nodes->tan, nodes->sec, nodes->capacity};
-    // launch bounds from the capacity; kernels read the real counts from meta
-    uint64_t cnt = ((uint64_t)cap + bundle - 1) / bundle;
-    uint32_t g = (uint32_t)((cnt + 255) / 256);
+    // launch bounds from the capacity (every frame may add one partial node
+    // per level); kernels read the real counts from meta
+    const uint64_t extra = bd ? bd->n_frames : 0;
+    uint64_t cnt = ((uint64_t)cap + bundle - 1) / bundle + extra;
+    uint32_t g = (uint32_t)std::min<uint64_t>((cnt + 255) / 256, 1u << 22);
     if (g == 0) g = 1;
+    const float *sx = sorted->ox, *sy = sorted->oy, *sz = sorted->oz;
+    const float *tx = sorted->dx, *ty = sorted->dy, *tz = sorted->dz;
+#define CRSH_LEAF(NB)                                                                                      \
+    (bd ? k_build_leaf<NB, true><<<g, 256, 0, stream>>>(sx, sy, sz, tx, ty, tz, bundle, nd, meta, b)       \
+        : k_build_leaf<NB, false><<<g, 256, 0, stream>>>(sx, sy, sz, tx, ty, tz, bundle, nd, meta, b))
     switch (pow2_at_least(bundle)) {
-    case 1: k_build_leaf<1><<<g, 256, 0, stream>>>(sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, bundle, nd, meta); break;
-    case 2: k_build_leaf<2><<<g, 256, 0, stream>>>(sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, bundle, nd, meta); break;
-    case 4: k_build_leaf<4><<<g, 256, 0, stream>>>(sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, bundle, nd, meta); break;
-    case 8: k_build_leaf<8><<<g, 256, 0, stream>>>(sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, bundle, nd, meta); break;
-    case 16: k_build_leaf<16><<<g, 256, 0, stream>>>(sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, bundle, nd, meta); break;
-    default: k_build_leaf<32><<<g, 256, 0, stream>>>(sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, bundle, nd, meta); break;
+    case 1: CRSH_LEAF(1); break;
+    case 2: CRSH_LEAF(2); break;
+    case 4: CRSH_LEAF(4); break;
+    case 8: CRSH_LEAF(8); break;
+    case 16: CRSH_LEAF(16); break;
+    default: CRSH_LEAF(32); break;
     }
+#undef CRSH_LEAF
     int nf = pow2_at_least(merge);
+#define CRSH_UP(NF)                                                                                        \
+    (bd ? k_build_up<NF, true><<<g, 256, 0, stream>>>(lv, merge, nd, meta, b)                             \
+        : k_build_up<NF, false><<<g, 256, 0, stream>>>(lv, merge, nd, meta, b))
     for (int lv = 1; lv < levels; ++lv) {
-        cnt = (cnt + merge - 1) / merge;
-        g = (uint32_t)((cnt + 255) / 256);
+        cnt = (cnt + merge - 1) / merge + extra;
+        g = (uint32_t)std::min<uint64_t>((cnt + 255) / 256, 1u << 22);
         if (g == 0) g = 1;
         switch (nf) {
-        case 2: k_build_up<2><<<g, 256, 0, stream>>>(lv, merge, nd, meta); break;
-        case 4: k_build_up<4><<<g, 256, 0, stream>>>(lv, merge, nd, meta); break;
-        case 8: k_build_up<8><<<g, 256, 0, stream>>>(lv, merge, nd, meta); break;
-        default: k_build_up<16><<<g, 256, 0, stream>>>(lv, merge, nd, meta); break;
+        case 2: CRSH_UP(2); break;
+        case 4: CRSH_UP(4); break;
+        case 8: CRSH_UP(8); break;
+        default: CRSH_UP(16); break;
         }
-        if (cnt <= 1) break;
+        if (!bd && cnt <= 1) break;
     }
+#undef CRSH_UP
     return hip_check(hipGetLastError(), "crsh_build launch");
+}
+
+}  // namespace crsh
+
+extern "C" crsh_status crsh_build(const crsh_rays *rays, const uint32_t *sorted_ids, int32_t bundle, int32_t merge,
+                                  int32_t levels, crsh_nodes *nodes, crsh_rays *sorted, crsh_meta *meta,
+                                  hipStream_t stream)
+{
+    return build_launch(rays, sorted_ids, bundle, merge, levels, nodes, sorted, meta, nullptr, stream);
 }

@@ -202,6 +202,27 @@ size_t hash_ws_bytes(uint64_t pixels);
 size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t max_pairs);
 size_t hit_ws_bytes(uint32_t m);
 
+// Stage launchers shared by the plain entry points (bd == nullptr) and the
+// batched form (bd: the batch's device view, frame-aware kernels).
+struct batch_dev;
+crsh_status hash_launch(const crsh_gbuf *gbuf, const crsh_raygen *rg, const batch_dev *bd, crsh_rays *out,
+                        uint32_t *keys, uint32_t *ids, uint32_t *ray_frame, crsh_meta *meta, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+crsh_status sort_launch(const uint32_t *keys_in, const uint32_t *ids_in, const uint32_t *frame_of,
+                        uint32_t *keys_out, uint32_t *ids_out, uint32_t capacity, crsh_meta *meta, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+crsh_status build_launch(const crsh_rays *rays, const uint32_t *sorted_ids, int32_t bundle, int32_t merge,
+                         int32_t levels, crsh_nodes *nodes, crsh_rays *sorted, crsh_meta *meta,
+                         const batch_dev *bd, hipStream_t stream);
+crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin, uint32_t tri_end,
+                            int32_t bundle, int32_t merge, const crsh_pairs pairs[CRSH_MAX_LEVELS],
+                            crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t levels,
+                            uint64_t top_items, hipStream_t stream);
+crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
+                       const crsh_pairs *level1, const crsh_scene *scene, float t_min, crsh_hits *hits,
+                       crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t hit_block,
+                       hipStream_t stream);
+
 // launch helpers
 void set_error(const char *fmt, ...);
 crsh_status hip_check(hipError_t e, const char *what);

@@ -13,7 +13,10 @@
 //              is the closest hit with ties to the lower triangle id.
 // k_hit_final  one thread per sorted ray: decode the key, recompute u, v with
 //              the same test, write the result at the ray id.
-#include "common.hpp"
+// Batched form: a leaf's rays are the range the build recorded with it (first
+// sorted ray, count) and the accepted interval starts at its frame's t_min.
+#include "batch.hpp"
+#include "intersect.hpp"
 
 namespace crsh {
 
@@ -33,55 +36,20 @@ __global__ void k_hit_prep(const float *__restrict__ v0x, const float *__restric
     }
 }
 
-struct tri_t {
-    f3 v0, e1, e2;
-};
-
-__device__ __forceinline__ tri_t load_tri(const float4 *__restrict__ tri, uint32_t t)
-{
-    float4 a = tri[3 * t + 0];
-    float4 b = tri[3 * t + 1];
-    float4 c = tri[3 * t + 2];
-    tri_t r;
-    r.v0 = mk(a.x, a.y, a.z);
-    r.e1 = mk(a.w, b.x, b.y);
-    r.e2 = mk(b.z, b.w, c.x);
-    return r;
-}
-
-// Two-sided Moller-Trumbore, accepted for t_min < t < tmax.
-__device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float tmax, const tri_t &tr, float &tt,
-                                                float &uu, float &vv)
-{
-    f3 p = cross(D, tr.e2);
-    float det = dot(tr.e1, p);
-    if (!(fabsf(det) >= DET_EPS)) return false;
-    float inv = 1.0f / det;
-    f3 T = O - tr.v0;
-    float u = dot(T, p) * inv;
-    if (!(u >= 0.0f && u <= 1.0f)) return false;
-    f3 q = cross(T, tr.e1);
-    float v = dot(D, q) * inv;
-    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
-    float t = dot(tr.e2, q) * inv;
-    if (!(t > t_min && t < tmax)) return false;
-    tt = t;
-    uu = u;
-    vv = v;
-    return true;
-}
-
 struct sorted_rays {
     const float *ox, *oy, *oz, *dx, *dy, *dz, *tmax;
 };
 
+template <bool BATCH>
 __global__ __launch_bounds__(256) void k_hit(sorted_rays R, const float4 *__restrict__ tri,
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
-                                             uint64_t cap1, uint32_t B, uint32_t log2G, float t_min,
-                                             unsigned long long *tkey, crsh_meta *meta, uint32_t ray_cap, uint32_t m)
+                                             uint64_t cap1, uint32_t B, uint32_t log2G, float t_min0,
+                                             unsigned long long *tkey, crsh_meta *meta, uint32_t ray_cap, uint32_t m,
+                                             batch_dev bd)
 {
     __shared__ uint64_t s_red[256 / WAVE];
     const uint32_t n = min(meta->n_rays, ray_cap);
+    const uint32_t n_leaf = meta->level_cnt[0];
     uint64_t np = meta->n_levels ? meta->pairs[0] : 0;
     np = np < cap1 ? np : cap1;
     const uint32_t l = lane_id();
@@ -96,7 +64,18 @@ __global__ __launch_bounds__(256) void k_hit(sorted_rays R, const float4 *__rest
         const uint64_t q = q0 + slot;
         if (q >= np || j >= B) continue;
         const uint32_t t = ptri[q];
-        const uint32_t s = pnode[q] * B + j;
+        const uint32_t leaf = pnode[q];
+        uint32_t s;
+        float t_min = t_min0;
+        if constexpr (BATCH) {
+            if (leaf >= n_leaf) continue;
+            const uint32_t info = bd.node_info[leaf];
+            if (j >= (info & INFO_COUNT_MASK)) continue;
+            s = bd.node_first[leaf] + j;
+            t_min = bd.frames[info >> INFO_FRAME_SHIFT].t_min;
+        } else {
+            s = leaf * B + j;
+        }
         if (s >= n || t >= m) continue;
         ++tests;
         const tri_t tr = load_tri(tri, t);
@@ -113,7 +92,7 @@ __global__ __launch_bounds__(256) void k_hit(sorted_rays R, const float4 *__rest
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t tot = 0;
-        for (int i = 0; i < 256 / WAVE; ++i) tot += s_red[i];
+        for (uint32_t i = 0; i < blockDim.x / WAVE; ++i) tot += s_red[i];
         if (tot) atomicAdd((unsigned long long *)&meta->final_tests, (unsigned long long)tot);
     }
 }
@@ -123,15 +102,18 @@ struct hit_out {
     float *t, *u, *v;
 };
 
+template <bool BATCH>
 __global__ void k_hit_final(sorted_rays R, const float4 *__restrict__ tri, const uint32_t *__restrict__ sorted_ids,
-                            float t_min, const unsigned long long *tkey, hit_out out, const crsh_meta *meta,
-                            uint32_t ray_cap, uint32_t m)
+                            float t_min0, const unsigned long long *tkey, hit_out out, const crsh_meta *meta,
+                            uint32_t ray_cap, uint32_t m, batch_dev bd)
 {
     const uint32_t n = min(meta->n_rays, ray_cap);
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
         const unsigned long long key = tkey[s];
         const uint32_t id = sorted_ids[s];
         if (id >= ray_cap) continue;    // ids come from the sort: never taken
+        float t_min = t_min0;
+        if constexpr (BATCH) t_min = bd.frames[min(bd.ray_frame[id], bd.n_frames - 1)].t_min;
         int32_t best = -1;
         float th = 0.0f, uh = 0.0f, vh = 0.0f;
         if (key != ~0ull && (uint32_t)(key & 0xFFFFFFFFull) < m) {
@@ -173,10 +155,12 @@ extern "C" crsh_status crsh_hits_reset(crsh_hits *hits, hipStream_t stream)
     return hip_check(hipGetLastError(), "crsh_hits_reset launch");
 }
 
-extern "C" crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
-                                        const crsh_pairs *level1, const crsh_scene *scene, float t_min,
-                                        crsh_hits *hits, crsh_meta *meta, void *ws, size_t ws_bytes,
-                                        hipStream_t stream)
+namespace crsh {
+
+crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
+                       const crsh_pairs *level1, const crsh_scene *scene, float t_min, crsh_hits *hits,
+                       crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t hit_block,
+                       hipStream_t stream)
 {
     if (!sorted || !sorted_ids || !level1 || !scene || !hits || !meta || !ws) {
         set_error("crsh_closest_hit: NULL argument");
@@ -184,6 +168,10 @@ extern "C" crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t 
     }
     if (bundle < 1 || bundle > CRSH_MAX_BUNDLE) {
         set_error("crsh_closest_hit: bundle must be in [1, %d]", CRSH_MAX_BUNDLE);
+        return CRSH_ERR_INVALID;
+    }
+    if (hit_block != 64 && hit_block != 128 && hit_block != 256) {
+        set_error("crsh_closest_hit: workgroup size must be 64, 128 or 256");
         return CRSH_ERR_INVALID;
     }
     if (!sorted->ox || !sorted->oy || !sorted->oz || !sorted->dx || !sorted->dy || !sorted->dz ||
@@ -205,6 +193,7 @@ extern "C" crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t 
         set_error("crsh_closest_hit: workspace too small (%zu < %zu)", ws_bytes, hit_ws_bytes(scene->m));
         return CRSH_ERR_INVALID;
     }
+    const batch_dev b = bd ? *bd : batch_dev{};
     float4 *tri = (float4 *)ws;
     const float *const *v = scene->v;
     if (scene->m) {
@@ -214,19 +203,40 @@ extern "C" crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t 
     uint32_t log2G = 0;
     while ((1u << log2G) < (uint32_t)bundle) ++log2G;
     sorted_rays R{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
-    if (level1->capacity)
-        {
-            prof_scope ps("k_hit", stream);
-            k_hit<<<2048, 256, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity, (uint32_t)bundle,
-                                        log2G, t_min, hits->tkey, meta, sorted->capacity, scene->m);
-        }
+    if (level1->capacity) {
+        const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
+        prof_scope ps("k_hit", stream);
+        if (bd)
+            k_hit<true><<<grid, hit_block, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity,
+                                                        (uint32_t)bundle, log2G, t_min, hits->tkey, meta,
+                                                        sorted->capacity, scene->m, b);
+        else
+            k_hit<false><<<grid, hit_block, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity,
+                                                         (uint32_t)bundle, log2G, t_min, hits->tkey, meta,
+                                                         sorted->capacity, scene->m, b);
+    }
     uint32_t g = std::min<uint32_t>((sorted->capacity + 255) / 256, 4096);
     if (g == 0) g = 1;
     hit_out o{hits->tri, hits->t, hits->u, hits->v};
     {
         prof_scope ps("k_hit_final", stream);
-        k_hit_final<<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta, sorted->capacity,
-                                           scene->m);
+        if (bd)
+            k_hit_final<true><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta,
+                                                     sorted->capacity, scene->m, b);
+        else
+            k_hit_final<false><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta,
+                                                      sorted->capacity, scene->m, b);
     }
     return hip_check(hipGetLastError(), "crsh_closest_hit launch");
+}
+
+}  // namespace crsh
+
+extern "C" crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
+                                        const crsh_pairs *level1, const crsh_scene *scene, float t_min,
+                                        crsh_hits *hits, crsh_meta *meta, void *ws, size_t ws_bytes,
+                                        hipStream_t stream)
+{
+    return hit_launch(sorted, sorted_ids, bundle, level1, scene, t_min, hits, meta, ws, ws_bytes, nullptr, 256,
+                      stream);
 }

@@ -1,0 +1,48 @@
+// Final ray-triangle test (Sec. 3.3.8): Moller-Trumbore on triangles packed
+// as (v0, e1, e2).
+#pragma once
+
+#include "common.hpp"
+
+namespace crsh {
+
+struct tri_t {
+    f3 v0, e1, e2;
+};
+
+__device__ __forceinline__ tri_t load_tri(const float4 *__restrict__ tri, uint32_t t)
+{
+    float4 a = tri[3 * t + 0];
+    float4 b = tri[3 * t + 1];
+    float4 c = tri[3 * t + 2];
+    tri_t r;
+    r.v0 = mk(a.x, a.y, a.z);
+    r.e1 = mk(a.w, b.x, b.y);
+    r.e2 = mk(b.z, b.w, c.x);
+    return r;
+}
+
+// Two-sided Moller-Trumbore, accepted for t_min < t < tmax.
+__device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float tmax, const tri_t &tr, float &tt,
+                                                float &uu, float &vv)
+{
+    f3 p = cross(D, tr.e2);
+    float det = dot(tr.e1, p);
+    if (!(fabsf(det) >= DET_EPS)) return false;
+    float inv = 1.0f / det;
+    f3 T = O - tr.v0;
+    float u = dot(T, p) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) return false;
+    f3 q = cross(T, tr.e1);
+    float v = dot(D, q) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
+    float t = dot(tr.e2, q) * inv;
+    if (!(t > t_min && t < tmax)) return false;
+    tt = t;
+    uu = u;
+    vv = v;
+    return true;
+}
+
+
+}  // namespace crsh

@@ -1,0 +1,175 @@
+// Secondary-ray generation and ray keys (Sec. 3.3.2): per-slot rays of a
+// primary hit and their 32-bit hash keys.
+#pragma once
+
+#include "common.hpp"
+
+namespace crsh {
+
+struct raygen_dev {
+    int32_t n_lights;
+    float lx[CRSH_MAX_LIGHTS], ly[CRSH_MAX_LIGHTS], lz[CRSH_MAX_LIGHTS];
+    float ex, ey, ez;
+    const uint32_t *mat_flags;
+    const float *mat_ior;
+    int32_t n_mats;
+    uint32_t types;
+    float eps_off, eps_shadow;
+    float lo[3], inv[3];
+};
+
+struct gbuf_dev {
+    const float *px, *py, *pz, *nx, *ny, *nz;
+    const int32_t *mat;
+    uint32_t npix;
+};
+
+struct ray_t {
+    f3 o, d;
+    float tmax;
+    uint32_t key;
+};
+
+// Octahedral map of a unit direction to a 2^k x 2^k grid.
+__device__ __forceinline__ void octahedral(f3 d, int k, uint32_t &u, uint32_t &v)
+{
+    float a = (fabsf(d.x) + fabsf(d.y)) + fabsf(d.z);
+    float px = d.x / a;
+    float py = d.y / a;
+    if (d.z < 0.0f) {
+        float sx = px >= 0.0f ? 1.0f : -1.0f;
+        float sy = py >= 0.0f ? 1.0f : -1.0f;
+        float fx = (1.0f - fabsf(py)) * sx;
+        float fy = (1.0f - fabsf(px)) * sy;
+        px = fx;
+        py = fy;
+    }
+    const float half = (float)(1u << (k - 1));
+    const float top = (float)((1u << k) - 1u);
+    float fu = floorf((px + 1.0f) * half);
+    float fv = floorf((py + 1.0f) * half);
+    fu = fu >= 0.0f ? fu : 0.0f;
+    fv = fv >= 0.0f ? fv : 0.0f;
+    fu = fu > top ? top : fu;
+    fv = fv > top ? top : fv;
+    u = (uint32_t)fu;
+    v = (uint32_t)fv;
+}
+
+// Spread the low 16 bits of x to the even bit positions.
+__device__ __forceinline__ uint32_t spread2(uint32_t x)
+{
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+// Spread the low 10 bits of x to every third bit position.
+__device__ __forceinline__ uint32_t spread3(uint32_t x)
+{
+    x &= 0x3FFu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t cell64(float o, float lo, float inv)
+{
+    float f = floorf(((o - lo) * inv) * 64.0f);
+    f = f >= 0.0f ? f : 0.0f;
+    f = f > 63.0f ? 63.0f : f;
+    return (uint32_t)f;
+}
+
+// Shadow: 00 | light:2 | octahedral(14+14).  Bounce: type:2 | cell:18 | octahedral(6+6).
+__device__ __forceinline__ uint32_t key_shadow(uint32_t light, f3 d)
+{
+    uint32_t u, v;
+    octahedral(d, 14, u, v);
+    return (light << 28) | spread2(u) | (spread2(v) << 1);
+}
+
+__device__ __forceinline__ uint32_t key_bounce(uint32_t type, f3 o, f3 d, const raygen_dev &g)
+{
+    uint32_t cx = cell64(o.x, g.lo[0], g.inv[0]);
+    uint32_t cy = cell64(o.y, g.lo[1], g.inv[1]);
+    uint32_t cz = cell64(o.z, g.lo[2], g.inv[2]);
+    uint32_t u, v;
+    octahedral(d, 6, u, v);
+    uint32_t cell = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+    return (type << 30) | (cell << 12) | spread2(u) | (spread2(v) << 1);
+}
+
+// Generates slot s of a pixel (shadow rays of lights 0..L-1, reflection,
+// refraction); returns false for a hole.
+__device__ __forceinline__ bool make_slot(int s, f3 P, f3 N, uint32_t flags, float ior, const raygen_dev &g,
+                                          ray_t &r)
+{
+    if (s < g.n_lights) {
+        if (!(g.types & CRSH_RAY_SHADOW)) return false;
+        f3 L = mk(g.lx[s], g.ly[s], g.lz[s]);
+        f3 d0 = P - L;
+        float l = len(d0);
+        if (!(l > g.eps_shadow)) return false;
+        r.o = L;                  // origin moved to the light
+        r.d = d0 / l;
+        r.tmax = l - g.eps_shadow;
+        r.key = key_shadow((uint32_t)s, r.d);
+        return true;
+    }
+    f3 E = mk(g.ex, g.ey, g.ez);
+    f3 v0 = P - E;
+    f3 v = v0 / len(v0);
+    float k = dot(v, N);
+    if (s == g.n_lights) {
+        if (!(g.types & CRSH_RAY_REFLECT) || !(flags & CRSH_MAT_REFLECTIVE)) return false;
+        f3 rr = v - N * (2.0f * k);
+        r.d = rr / len(rr);
+        r.o = P + N * g.eps_off;
+        r.tmax = FLT_MAX;
+        r.key = key_bounce(1u, r.o, r.d, g);
+        return true;
+    }
+    if (!(g.types & CRSH_RAY_REFRACT) || !(flags & CRSH_MAT_REFRACTIVE)) return false;
+    float eta = 1.0f / ior;
+    float ci = -k;
+    float k2 = 1.0f - (eta * eta) * (1.0f - ci * ci);
+    if (k2 < 0.0f) return false;    // total internal reflection
+    float b = eta * ci - sqrtf(k2);
+    f3 t = v * eta + N * b;
+    r.d = t / len(t);
+    r.o = P - N * g.eps_off;
+    r.tmax = FLT_MAX;
+    r.key = key_bounce(2u, r.o, r.d, g);
+    return true;
+}
+
+struct pixel_t {
+    f3 P, N;
+    uint32_t flags;
+    float ior;
+    bool hit;
+};
+
+__device__ __forceinline__ pixel_t load_pixel(const gbuf_dev &gb, const raygen_dev &g, uint32_t p)
+{
+    pixel_t px;
+    px.hit = false;
+    if (p >= gb.npix) return px;
+    int32_t m = gb.mat[p];
+    if (m < 0) return px;
+    px.hit = true;
+    px.P = mk(gb.px[p], gb.py[p], gb.pz[p]);
+    px.N = mk(gb.nx[p], gb.ny[p], gb.nz[p]);
+    px.flags = m < g.n_mats ? g.mat_flags[m] : 0u;
+    px.ior = m < g.n_mats ? g.mat_ior[m] : 1.0f;
+    return px;
+}
+
+
+}  // namespace crsh

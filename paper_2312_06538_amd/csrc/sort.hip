@@ -26,12 +26,16 @@ constexpr uint32_t SLB_AGG = 1u << 30;
 constexpr uint32_t SLB_INC = 2u << 30;
 constexpr uint32_t SLB_MASK = (1u << 30) - 1;
 
+// The batched form adds a fifth, most significant digit: the frame of the
+// ray, read through the value (ray id) from a per-ray frame table.
+constexpr uint32_t MAX_PASSES = SORT_PASSES + 1;
+
 // plan codes for the source / destination of each pass
 enum : uint32_t { BUF_IN = 0, BUF_OUT = 1, BUF_ALT = 2, BUF_SKIP = 3 };
 
 struct sort_ctl {
-    uint32_t src[SORT_PASSES], dst[SORT_PASSES];
-    uint32_t tile_ctr[SORT_PASSES];
+    uint32_t src[MAX_PASSES], dst[MAX_PASSES];
+    uint32_t tile_ctr[MAX_PASSES];
     uint32_t copy_through;   // every pass skipped: copy input to output
     uint32_t n;
 };
@@ -41,25 +45,26 @@ __global__ void k_sort_clear(uint32_t *hist, sort_ctl *ctl, uint32_t *flags, con
 {
     uint32_t n = min(meta->n_rays, cap);
     uint32_t tiles = (n + SORT_TILE - 1) / SORT_TILE;
-    uint64_t nflag = (uint64_t)SORT_PASSES * tiles_cap * 256;
+    uint64_t nflag = (uint64_t)MAX_PASSES * tiles_cap * 256;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nflag;
          i += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t tile = (uint32_t)((i / 256) % tiles_cap);
         if (tile < tiles) flags[i] = 0;
     }
     uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < SORT_PASSES * 256) hist[g] = 0;
+    if (g < MAX_PASSES * 256) hist[g] = 0;
     if (g < sizeof(sort_ctl) / 4) ((uint32_t *)ctl)[g] = 0;
 }
 
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t *keys, const crsh_meta *meta,
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t *keys, const uint32_t *vals,
+                                                            const uint32_t *frame_of, const crsh_meta *meta,
                                                             uint32_t *hist, uint32_t cap)
 {
-    __shared__ uint32_t h[SORT_PASSES * 256];
+    __shared__ uint32_t h[MAX_PASSES * 256];
     uint32_t n = min(meta->n_rays, cap);
     uint32_t base = blockIdx.x * SORT_TILE;
     if (base >= n) return;
-    for (uint32_t i = threadIdx.x; i < SORT_PASSES * 256; i += SORT_THREADS) h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < MAX_PASSES * 256; i += SORT_THREADS) h[i] = 0;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < SORT_TILE; i += SORT_THREADS) {
         uint32_t g = base + i;
@@ -67,23 +72,24 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t *keys
             uint32_t k = keys[g];
 #pragma unroll
             for (uint32_t p = 0; p < SORT_PASSES; ++p) atomicAdd(&h[p * 256 + ((k >> (8 * p)) & 255u)], 1u);
+            if (frame_of) atomicAdd(&h[SORT_PASSES * 256 + (frame_of[vals[g]] & 255u)], 1u);
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < SORT_PASSES * 256; i += SORT_THREADS)
+    for (uint32_t i = threadIdx.x; i < MAX_PASSES * 256; i += SORT_THREADS)
         if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
 __global__ __launch_bounds__(256) void k_sort_plan(uint32_t *hist, sort_ctl *ctl, const crsh_meta *meta,
-                                                  uint32_t cap)
+                                                  uint32_t cap, uint32_t passes)
 {
     __shared__ uint32_t scratch[256 / WAVE];
-    __shared__ uint32_t skip[SORT_PASSES];
+    __shared__ uint32_t skip[MAX_PASSES];
     uint32_t n = min(meta->n_rays, cap);
     uint32_t d = threadIdx.x;
-    if (d < SORT_PASSES) skip[d] = (n == 0);
+    if (d < MAX_PASSES) skip[d] = (n == 0) || d >= passes;
     __syncthreads();
-    for (uint32_t p = 0; p < SORT_PASSES; ++p) {
+    for (uint32_t p = 0; p < passes; ++p) {
         uint32_t c = hist[p * 256 + d];
         if (c == n) skip[p] = 1;    // one digit value holds every key
         uint32_t total;
@@ -95,7 +101,7 @@ __global__ __launch_bounds__(256) void k_sort_plan(uint32_t *hist, sort_ctl *ctl
         // walk the kept passes backwards: the last writes OUT, the one before ALT, ...
         uint32_t target = BUF_OUT;
         int first = -1;
-        for (int p = SORT_PASSES - 1; p >= 0; --p) {
+        for (int p = MAX_PASSES - 1; p >= 0; --p) {
             if (skip[p]) {
                 ctl->src[p] = BUF_SKIP;
                 ctl->dst[p] = BUF_SKIP;
@@ -105,7 +111,7 @@ __global__ __launch_bounds__(256) void k_sort_plan(uint32_t *hist, sort_ctl *ctl
             target = (target == BUF_OUT) ? BUF_ALT : BUF_OUT;
             first = p;
         }
-        for (int p = 0; p < (int)SORT_PASSES; ++p) {
+        for (int p = 0; p < (int)MAX_PASSES; ++p) {
             if (skip[p]) continue;
             ctl->src[p] = (p == first) ? BUF_IN : (ctl->dst[p] == BUF_OUT ? BUF_ALT : BUF_OUT);
         }
@@ -132,9 +138,10 @@ __device__ __forceinline__ uint32_t *pick_dst(const sort_bufs &b, uint32_t code,
     return key ? b.kalt : b.valt;
 }
 
+template <bool FRAME>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(sort_bufs bufs, const uint32_t *offsets,
                                                             sort_ctl *ctl, uint32_t *flags, uint32_t pass,
-                                                            uint32_t tiles_cap)
+                                                            uint32_t tiles_cap, const uint32_t *frame_of)
 {
     __shared__ uint32_t s_keys[SORT_TILE];
     __shared__ uint32_t s_vals[SORT_TILE];
@@ -159,7 +166,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(sort_bufs bufs, cons
     const uint32_t *vin = pick_src(bufs, src, false);
     const uint32_t w = threadIdx.x / WAVE;
     const uint32_t l = lane_id();
-    const uint32_t shift = 8 * pass;
+    const uint32_t shift = 8 * (pass & 3u);
     const uint32_t base = tile * SORT_TILE + w * (WAVE * SORT_ROUNDS);
 
     uint32_t key[SORT_ROUNDS], val[SORT_ROUNDS], rank[SORT_ROUNDS];
@@ -175,7 +182,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(sort_bufs bufs, cons
     for (uint32_t r = 0; r < SORT_ROUNDS; ++r) {
         uint32_t g = base + r * WAVE + l;
         bool ok = g < n;
-        uint32_t d = (key[r] >> shift) & 255u;
+        uint32_t d = FRAME ? (ok ? frame_of[val[r]] & 255u : 0u) : (key[r] >> shift) & 255u;
         uint64_t peers = ballot(ok);
 #pragma unroll
         for (uint32_t b = 0; b < 8; ++b) {
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(sort_bufs bufs, cons
     for (uint32_t r = 0; r < SORT_ROUNDS; ++r) {
         uint32_t g = base + r * WAVE + l;
         if (g < n) {
-            uint32_t dd = (key[r] >> shift) & 255u;
+            uint32_t dd = FRAME ? frame_of[val[r]] & 255u : (key[r] >> shift) & 255u;
             uint32_t q = s_start[dd] + s_wcnt[w * 256 + dd] + rank[r];
             if (q < SORT_TILE) {
                 s_keys[q] = key[r];
@@ -247,10 +254,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(sort_bufs bufs, cons
     const uint32_t tile_n = min(SORT_TILE, n - tile * SORT_TILE);
     for (uint32_t q = threadIdx.x; q < tile_n; q += SORT_THREADS) {
         uint32_t k = s_keys[q];
-        uint32_t pos = s_base[(k >> shift) & 255u] + q;
+        uint32_t vq = s_vals[q];
+        uint32_t pos = s_base[FRAME ? frame_of[vq] & 255u : (k >> shift) & 255u] + q;
         if (pos < n) {
             kout[pos] = k;
-            vout[pos] = s_vals[q];
+            vout[pos] = vq;
         }
     }
 }
@@ -270,9 +278,11 @@ __global__ void k_sort_copy(const uint32_t *kin, const uint32_t *vin, uint32_t *
 
 using namespace crsh;
 
-extern "C" crsh_status crsh_sort(const uint32_t *keys_in, const uint32_t *ids_in, uint32_t *keys_out,
-                                 uint32_t *ids_out, uint32_t capacity, crsh_meta *meta, void *ws, size_t ws_bytes,
-                                 hipStream_t stream)
+namespace crsh {
+
+crsh_status sort_launch(const uint32_t *keys_in, const uint32_t *ids_in, const uint32_t *frame_of,
+                        uint32_t *keys_out, uint32_t *ids_out, uint32_t capacity, crsh_meta *meta, void *ws,
+                        size_t ws_bytes, hipStream_t stream)
 {
     if (!keys_in || !ids_in || !keys_out || !ids_out || !meta || !ws) {
         set_error("crsh_sort: NULL argument");
@@ -298,23 +308,35 @@ extern "C" crsh_status crsh_sort(const uint32_t *keys_in, const uint32_t *ids_in
     uint32_t *valt = (uint32_t *)w;
     w += align256((size_t)capacity * 4);
     uint32_t *hist = (uint32_t *)w;
-    w += align256(SORT_PASSES * 256 * 4);
+    w += align256(MAX_PASSES * 256 * 4);
     sort_ctl *ctl = (sort_ctl *)w;
     w += align256(64 * 4);
     uint32_t *flags = (uint32_t *)w;
+    const uint32_t passes = frame_of ? MAX_PASSES : SORT_PASSES;
 
     k_sort_clear<<<1024, 256, 0, stream>>>(hist, ctl, flags, meta, tiles_cap, capacity);
     {
         prof_scope ps("k_sort_hist", stream);
-        k_sort_hist<<<tiles_cap, SORT_THREADS, 0, stream>>>(keys_in, meta, hist, capacity);
+        k_sort_hist<<<tiles_cap, SORT_THREADS, 0, stream>>>(keys_in, ids_in, frame_of, meta, hist, capacity);
     }
-    k_sort_plan<<<1, 256, 0, stream>>>(hist, ctl, meta, capacity);
+    k_sort_plan<<<1, 256, 0, stream>>>(hist, ctl, meta, capacity, passes);
     sort_bufs b{keys_in, ids_in, keys_out, ids_out, kalt, valt};
-    for (uint32_t p = 0; p < SORT_PASSES; ++p)
-        {
-            prof_scope ps("k_sort_pass", stream);
-            k_sort_pass<<<tiles_cap, SORT_THREADS, 0, stream>>>(b, hist, ctl, flags, p, tiles_cap);
-        }
+    for (uint32_t p = 0; p < passes; ++p) {
+        prof_scope ps("k_sort_pass", stream);
+        if (p < SORT_PASSES)
+            k_sort_pass<false><<<tiles_cap, SORT_THREADS, 0, stream>>>(b, hist, ctl, flags, p, tiles_cap, nullptr);
+        else
+            k_sort_pass<true><<<tiles_cap, SORT_THREADS, 0, stream>>>(b, hist, ctl, flags, p, tiles_cap, frame_of);
+    }
     k_sort_copy<<<256, 256, 0, stream>>>(keys_in, ids_in, keys_out, ids_out, ctl);
     return hip_check(hipGetLastError(), "crsh_sort launch");
+}
+
+}  // namespace crsh
+
+extern "C" crsh_status crsh_sort(const uint32_t *keys_in, const uint32_t *ids_in, uint32_t *keys_out,
+                                 uint32_t *ids_out, uint32_t capacity, crsh_meta *meta, void *ws, size_t ws_bytes,
+                                 hipStream_t stream)
+{
+    return sort_launch(keys_in, ids_in, nullptr, keys_out, ids_out, capacity, meta, ws, ws_bytes, stream);
 }

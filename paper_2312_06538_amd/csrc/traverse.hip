@@ -11,7 +11,16 @@
 // The pair arrays therefore come out trimmed (Fig. 4) and in the order of a
 // sequential traversal, so they are deterministic.  Work is spread with
 // grid-stride loops; nothing depends on which blocks are resident.
-#include "common.hpp"
+//
+// Batched form: frames have their own top levels, so levels are produced from
+// the highest down; on each level the pairs that descend from the level above
+// come first, then a top-level pass appends the (node, mesh, triangle) pairs
+// of the frames whose top is this level.  A top-level item is (frame, top
+// node, mesh of the frame); a parent's children are the range recorded with
+// it by the build (first child, count), so no frame lookup is needed below
+// the top.
+#include "batch.hpp"
+#include "bounds.hpp"
 
 namespace crsh {
 
@@ -75,20 +84,6 @@ __global__ void k_node_pack(node_arrays nd, crsh_meta *meta, float4 *na, float4 
     if (blockIdx.x == 0 && threadIdx.x < CRSH_MAX_LEVELS) meta->pairs[threadIdx.x] = 0;
 }
 
-// Eq. 9 with H the projection of P on the node axis: |P-H| = |(P-C) x a|,
-// |C-H| = |(P-C).a|; pass iff |P-H|^2 <= (|C-H| tan + (d + r) sec)^2.
-__device__ __forceinline__ bool packed_meets(float4 A, float4 Bv, float sec, f3 P, float d)
-{
-    if (!(sec > 0.0f)) return true;
-    f3 v = P - mk(A.x, A.y, A.z);
-    f3 a = mk(Bv.x, Bv.y, Bv.z);
-    float t = dot(v, a);
-    f3 w = cross(v, a);
-    float lhs2 = dot(w, w);
-    float rhs = fabsf(t) * Bv.w + (d + A.w) * sec;
-    return lhs2 <= rhs * rhs;
-}
-
 // number of work items of a level: top level (parent_level 0) = top nodes x
 // meshes, lower levels = tiles of LEVEL_TILE parent pairs
 __device__ __forceinline__ uint64_t level_items(const crsh_meta *meta, int32_t parent_level, uint32_t n_mesh,
@@ -112,18 +107,33 @@ __device__ __forceinline__ void clear_scan(const trav_scratch &S, uint64_t items
 }
 
 // ------------------------------------------------------------- top level
-__device__ __forceinline__ void top_item(uint32_t item, uint32_t n_mesh, uint32_t off, const float4 *na,
-                                         const float4 *nb, const float *ns, const float *msph,
-                                         const uint32_t *mesh_first, const uint32_t *mesh_count,
+// Item -> (node i within the level, mesh m).  Plain: item = i * n_mesh + m.
+// Batch: the item's frame, then (top node, mesh) within the frame.
+template <bool BATCH>
+__device__ __forceinline__ void top_item(uint64_t item, uint32_t n_mesh, uint32_t top, uint32_t off,
+                                         const batch_dev &bd, const float4 *na, const float4 *nb, const float *ns,
+                                         const float *msph, const uint32_t *mesh_first, const uint32_t *mesh_count,
                                          uint32_t tri_begin, uint32_t tri_end, float4 &A, float4 &Bv, float &S,
                                          uint32_t &i, uint32_t &b, uint32_t &e, bool &pass)
 {
-    i = item / n_mesh;
-    const uint32_t m = item - i * n_mesh;
+    uint32_t m;
+    if constexpr (BATCH) {
+        const uint32_t f = frame_of_item(bd, item);
+        const uint64_t local = item - bd.fm[f].item_base;
+        const uint32_t mc = bd.frames[f].mesh_count;
+        const uint32_t li = (uint32_t)(local / mc);
+        i = bd.fm[f].level_base[top] + li;
+        m = bd.frames[f].mesh_begin + (uint32_t)(local - (uint64_t)li * mc);
+    } else {
+        i = (uint32_t)item / n_mesh;
+        m = (uint32_t)item - i * n_mesh;
+    }
     A = na[off + i];
     Bv = nb[off + i];
     S = ns[off + i];
-    pass = packed_meets(A, Bv, S, mk(msph[4 * m], msph[4 * m + 1], msph[4 * m + 2]), msph[4 * m + 3]);
+    const bool real = !BATCH || m < n_mesh;    // frames name meshes of the batch's scene
+    if (!real) m = 0;
+    pass = real && packed_meets(A, Bv, S, mk(msph[4 * m], msph[4 * m + 1], msph[4 * m + 2]), msph[4 * m + 3]);
     b = e = 0;
     if (pass) {
         b = max(mesh_first[m], tri_begin);
@@ -132,19 +142,37 @@ __device__ __forceinline__ void top_item(uint32_t item, uint32_t n_mesh, uint32_
     }
 }
 
+// top level of this pass (0-based) and its number of items
+template <bool BATCH>
+__device__ __forceinline__ bool top_pass(const crsh_meta *meta, const batch_dev &bd, uint32_t L, uint32_t n_mesh,
+                                         const pair_levels &P, uint32_t &top, uint64_t &n_items)
+{
+    const uint32_t nl = meta->n_levels;
+    if (nl == 0) return false;
+    if constexpr (BATCH) {
+        if (L > nl) return false;
+        top = L - 1;
+        n_items = bd.top[0];
+    } else {
+        top = nl - 1;
+        n_items = level_items(meta, 0, n_mesh, P);
+    }
+    return true;
+}
+
+template <bool BATCH>
 __global__ __launch_bounds__(256) void k_top_count(const float4 *__restrict__ na, const float4 *__restrict__ nb,
                                                    const float *__restrict__ ns, const float4 *__restrict__ tsph,
                                                    const uint32_t *__restrict__ mesh_first,
                                                    const uint32_t *__restrict__ mesh_count,
                                                    const float *__restrict__ msph, uint32_t n_mesh,
                                                    uint32_t tri_begin, uint32_t tri_end, pair_levels P,
-                                                   trav_scratch S, crsh_meta *meta)
+                                                   trav_scratch S, crsh_meta *meta, batch_dev bd, uint32_t L)
 {
     __shared__ uint64_t s_red[3][256 / WAVE];
-    const uint32_t nl = meta->n_levels;
-    if (nl == 0) return;
-    const uint32_t top = nl - 1;
-    const uint64_t n_items = level_items(meta, 0, n_mesh, P);
+    uint32_t top;
+    uint64_t n_items;
+    if (!top_pass<BATCH>(meta, bd, L, n_mesh, P, top, n_items)) return;
     clear_scan(S, n_items);
     const uint32_t off = meta->level_off[top];
     const uint32_t l = lane_id();
@@ -156,8 +184,8 @@ __global__ __launch_bounds__(256) void k_top_count(const float4 *__restrict__ na
         float Sg;
         uint32_t i, b, e;
         bool pass;
-        top_item((uint32_t)it, n_mesh, off, na, nb, ns, msph, mesh_first, mesh_count, tri_begin, tri_end, A, Bv,
-                 Sg, i, b, e, pass);
+        top_item<BATCH>(it, n_mesh, top, off, bd, na, nb, ns, msph, mesh_first, mesh_count, tri_begin, tri_end,
+                        A, Bv, Sg, i, b, e, pass);
         ++items;
         mhits += pass ? 1 : 0;
         tests += e - b;
@@ -192,20 +220,20 @@ __global__ __launch_bounds__(256) void k_top_count(const float4 *__restrict__ na
     }
 }
 
+template <bool BATCH>
 __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na, const float4 *__restrict__ nb,
                                                   const float *__restrict__ ns, const float4 *__restrict__ tsph,
                                                   const uint32_t *__restrict__ mesh_first,
                                                   const uint32_t *__restrict__ mesh_count,
                                                   const float *__restrict__ msph, uint32_t n_mesh,
                                                   uint32_t tri_begin, uint32_t tri_end, pair_levels P,
-                                                  trav_scratch S, const crsh_meta *meta)
+                                                  trav_scratch S, const crsh_meta *meta, batch_dev bd, uint32_t L)
 {
-    const uint32_t nl = meta->n_levels;
-    if (nl == 0) return;
-    const uint32_t top = nl - 1;
+    uint32_t top;
+    uint64_t n_items;
+    if (!top_pass<BATCH>(meta, bd, L, n_mesh, P, top, n_items)) return;
     const pairs_dev out = P.p[top];
     if (out.tri == nullptr) return;
-    const uint64_t n_items = level_items(meta, 0, n_mesh, P);
     const uint32_t off = meta->level_off[top];
     const uint32_t l = lane_id();
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
@@ -216,8 +244,8 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
         float Sg;
         uint32_t i, b, e;
         bool pass;
-        top_item((uint32_t)it, n_mesh, off, na, nb, ns, msph, mesh_first, mesh_count, tri_begin, tri_end, A, Bv,
-                 Sg, i, b, e, pass);
+        top_item<BATCH>(it, n_mesh, top, off, bd, na, nb, ns, msph, mesh_first, mesh_count, tri_begin, tri_end,
+                        A, Bv, Sg, i, b, e, pass);
         uint64_t pos = S.off[it];
         for (uint32_t t0 = b; t0 < e; t0 += WAVE) {
             const uint32_t t = t0 + l;
@@ -238,11 +266,15 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
 }
 
 // ----------------------------------------------------------- lower levels
-template <int NF, int PPT>
+// Children of a parent: plain, par * F + [0, F) below nk; batch, the range
+// (pfirst[par], count) recorded by the build.
+template <int NF, int PPT, bool BATCH>
 __device__ __forceinline__ uint32_t level_tile_mask(uint64_t q0, uint64_t nin, const pairs_dev &in, uint32_t F,
                                                     uint32_t nk, uint32_t offk, const float4 *__restrict__ na,
                                                     const float4 *__restrict__ nb, const float *__restrict__ ns,
-                                                    const float4 *__restrict__ tsph, uint32_t m, uint32_t *tri,
+                                                    const float4 *__restrict__ tsph, uint32_t m,
+                                                    const uint32_t *__restrict__ pfirst,
+                                                    const uint32_t *__restrict__ pinfo, uint32_t np, uint32_t *tri,
                                                     uint32_t *par, uint64_t &tests)
 {
     float4 sp[PPT];
@@ -254,6 +286,15 @@ __device__ __forceinline__ uint32_t level_tile_mask(uint64_t q0, uint64_t nin, c
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) sp[k] = tsph[tri[k] < m ? tri[k] : 0u];
+    uint32_t cfirst[PPT], ccount[PPT];
+    if constexpr (BATCH) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const bool ok = par[k] < np;
+            cfirst[k] = ok ? pfirst[par[k]] : 0u;
+            ccount[k] = ok ? pinfo[par[k]] & INFO_COUNT_MASK : 0u;
+        }
+    }
     uint32_t mask = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -262,8 +303,14 @@ __device__ __forceinline__ uint32_t level_tile_mask(uint64_t q0, uint64_t nin, c
         bool ok[NF];
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
-            const uint32_t ch = par[k] * F + (uint32_t)j;
-            ok[j] = par[k] != 0xFFFFFFFFu && (uint32_t)j < F && ch < nk;
+            uint32_t ch;
+            if constexpr (BATCH) {
+                ch = cfirst[k] + (uint32_t)j;
+                ok[j] = (uint32_t)j < ccount[k] && ch < nk;
+            } else {
+                ch = par[k] * F + (uint32_t)j;
+                ok[j] = par[k] != 0xFFFFFFFFu && (uint32_t)j < F && ch < nk;
+            }
             const uint32_t g = offk + (ok[j] ? ch : 0u);
             A[j] = na[g];
             Bv[j] = nb[g];
@@ -280,13 +327,14 @@ __device__ __forceinline__ uint32_t level_tile_mask(uint64_t q0, uint64_t nin, c
     return mask;
 }
 
-template <int NF, int PPT>
+template <int NF, int PPT, bool BATCH>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_level, uint32_t F,
                                                                const float4 *__restrict__ na,
                                                                const float4 *__restrict__ nb,
                                                                const float *__restrict__ ns,
                                                                const float4 *__restrict__ tsph, uint32_t m,
-                                                               pair_levels P, trav_scratch S, crsh_meta *meta)
+                                                               pair_levels P, trav_scratch S, crsh_meta *meta,
+                                                               batch_dev bd)
 {
     static_assert(NF * PPT <= 32, "one bit per child test");
     static_assert(LEVEL_THREADS * PPT == LEVEL_TILE, "tile size");
@@ -302,12 +350,16 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     nin = nin < in.cap ? nin : in.cap;
     const uint32_t nk = meta->level_cnt[parent_level - 2];
     const uint32_t offk = meta->level_off[parent_level - 2];
+    const uint32_t offp = meta->level_off[parent_level - 1];
+    const uint32_t np = meta->level_cnt[parent_level - 1];
+    const uint32_t *pfirst = BATCH ? bd.node_first + offp : nullptr;
+    const uint32_t *pinfo = BATCH ? bd.node_info + offp : nullptr;
     uint64_t tests = 0;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         uint32_t tri[PPT], par[PPT];
         const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
-        const uint32_t mask =
-            level_tile_mask<NF, PPT>(q0, nin, in, F, nk, offk, na, nb, ns, tsph, m, tri, par, tests);
+        const uint32_t mask = level_tile_mask<NF, PPT, BATCH>(q0, nin, in, F, nk, offk, na, nb, ns, tsph, m,
+                                                              pfirst, pinfo, np, tri, par, tests);
         S.mask[tile * LEVEL_THREADS + threadIdx.x] = mask;
         const uint32_t c = wave_sum((uint32_t)__popc(mask));
         if (lane_id() == 0) s_red32[threadIdx.x / WAVE] = c;
@@ -329,9 +381,9 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     }
 }
 
-template <int NF, int PPT>
+template <int NF, int PPT, bool BATCH>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_level, uint32_t F, pair_levels P,
-                                                              trav_scratch S, const crsh_meta *meta)
+                                                              trav_scratch S, const crsh_meta *meta, batch_dev bd)
 {
     __shared__ uint32_t s_scan[LEVEL_THREADS / WAVE];
     const uint32_t nl = meta->n_levels;
@@ -342,6 +394,8 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
     uint64_t nin = meta->pairs[parent_level - 1];
     nin = nin < in.cap ? nin : in.cap;
     const uint64_t ntiles = (nin + LEVEL_TILE - 1) / LEVEL_TILE;
+    const uint32_t offp = meta->level_off[parent_level - 1];
+    const uint32_t np = meta->level_cnt[parent_level - 1];
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         if (S.cnt[tile] == 0) continue;          // uniform over the block
         const uint32_t mask = S.mask[tile * LEVEL_THREADS + threadIdx.x];
@@ -359,12 +413,14 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
         uint64_t at = S.off[tile] + ex;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
+            uint32_t first = par[k] * F;
+            if constexpr (BATCH) first = par[k] < np ? bd.node_first[offp + par[k]] : 0u;
 #pragma unroll
             for (int j = 0; j < NF; ++j) {
                 if (!((mask >> (k * NF + j)) & 1u)) continue;
                 if (at < out.cap) {
                     out.tri[at] = tri[k];
-                    out.node[at] = par[k] * F + (uint32_t)j;
+                    out.node[at] = first + (uint32_t)j;
                 }
                 ++at;
             }
@@ -378,28 +434,33 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
 // counter in launch order, so every tile waited on in the look-back has
 // started and publishes its sum without waiting: the look-back always ends.
 // There are few tiles (SCAN_TILE items each).
+// A batch's top-level pass (batch_top = its level, 1-based) scans bd_top[0]
+// items and appends after the bd_top[1] pairs already on that level.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_items(int32_t parent_level, uint32_t n_mesh, pair_levels P,
-                                                             trav_scratch S, crsh_meta *meta)
+                                                             trav_scratch S, crsh_meta *meta, uint32_t batch_top,
+                                                             const uint64_t *bd_top)
 {
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_excl;
     __shared__ uint64_t s_scan[SCAN_THREADS / WAVE];
     const uint32_t nl = meta->n_levels;
     if (nl == 0) return;
-    const uint64_t n = level_items(meta, parent_level, n_mesh, P);
-    const uint32_t out_level = parent_level == 0 ? nl - 1 : (uint32_t)parent_level - 2;
+    if (batch_top > nl) return;
+    const uint64_t n = batch_top ? bd_top[0] : level_items(meta, parent_level, n_mesh, P);
+    const uint64_t base = batch_top ? bd_top[1] : 0u;
+    const uint32_t out_level = batch_top ? batch_top - 1 : (parent_level == 0 ? nl - 1 : (uint32_t)parent_level - 2);
     const uint64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (blockIdx.x >= ntiles) return;       // only ntiles blocks take a tile
     if (threadIdx.x == 0) s_tile = atomicAdd(S.scan_ctr, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= ntiles) return;
-    const uint64_t base = (uint64_t)tile * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    const uint64_t first = (uint64_t)tile * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
     uint64_t v[SCAN_ITEMS];
     uint64_t sum = 0;
 #pragma unroll
     for (uint32_t k = 0; k < SCAN_ITEMS; ++k) {
-        v[k] = base + k < n ? S.cnt[base + k] : 0u;
+        v[k] = first + k < n ? S.cnt[first + k] : 0u;
         sum += v[k];
     }
     uint64_t total;
@@ -412,13 +473,37 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_items(int32_t parent_leve
     uint64_t run = s_excl + ex;
 #pragma unroll
     for (uint32_t k = 0; k < SCAN_ITEMS; ++k) {
-        if (base + k < n) S.off[base + k] = run;
+        if (first + k < n) S.off[first + k] = base + run;
         run += v[k];
     }
     if (tile == ntiles - 1 && threadIdx.x == SCAN_THREADS - 1) {
-        meta->pairs[out_level] = run;
+        meta->pairs[out_level] = base + run;
         atomicAdd((unsigned long long *)&meta->hits[out_level], (unsigned long long)run);
-        if (run > P.p[out_level].cap) atomicOr(&meta->status, CRSH_OVERFLOW_PAIRS);
+        if (base + run > P.p[out_level].cap) atomicOr(&meta->status, CRSH_OVERFLOW_PAIRS);
+    }
+}
+
+// Batch, before the top-level pass of level L: item ranges of the frames
+// whose top is L (one thread per frame), their total, and the pairs already
+// on that level (the append base).  Too many items: flagged, pass skipped.
+__global__ __launch_bounds__(256) void k_batch_top_plan(batch_dev bd, crsh_meta *meta, uint32_t L)
+{
+    __shared__ uint64_t scratch[256 / WAVE];
+    const uint32_t f = threadIdx.x;
+    const bool live = f < bd.n_frames;
+    uint64_t items = 0;
+    if (live && bd.fm[f].n_levels == L && L >= 1)
+        items = (uint64_t)bd.fm[f].level_cnt[L - 1] * bd.frames[f].mesh_count;
+    uint64_t total;
+    const uint64_t ex = block_excl_scan<uint64_t, 256 / WAVE>(items, scratch, total);
+    if (live) bd.fm[f].item_base = ex;
+    if (f == 0) {
+        if (total > bd.top_cap) {
+            atomicOr(&meta->status, CRSH_OVERFLOW_ITEMS);
+            total = 0;
+        }
+        bd.top[0] = total;
+        bd.top[1] = L >= 1 ? meta->pairs[L - 1] : 0u;
     }
 }
 
@@ -431,10 +516,12 @@ __global__ void k_no_storage(crsh_meta *meta, uint32_t levels_given)
 
 using namespace crsh;
 
-extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin,
-                                     uint32_t tri_end, int32_t bundle, int32_t merge,
-                                     const crsh_pairs pairs[CRSH_MAX_LEVELS], crsh_meta *meta, void *ws,
-                                     size_t ws_bytes, hipStream_t stream)
+namespace crsh {
+
+crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin, uint32_t tri_end,
+                            int32_t bundle, int32_t merge, const crsh_pairs pairs[CRSH_MAX_LEVELS],
+                            crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t batch_levels,
+                            uint64_t batch_top_items, hipStream_t stream)
 {
     if (!nodes || !scene || !pairs || !meta || !ws) {
         set_error("crsh_traverse: NULL argument");
@@ -468,7 +555,11 @@ extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *
         set_error("crsh_traverse: no pair storage");
         return CRSH_ERR_INVALID;
     }
-    const uint64_t top_items = (uint64_t)nodes->capacity * scene->n_mesh;
+    if (bd && levels < batch_levels) {
+        set_error("crsh_batch: pair storage for %d levels, %d needed", levels, batch_levels);
+        return CRSH_ERR_INVALID;
+    }
+    const uint64_t top_items = bd ? batch_top_items : (uint64_t)nodes->capacity * scene->n_mesh;
     size_t need = trav_ws_bytes(scene->m, nodes->capacity, top_items, max_pairs);
     if (ws_bytes < need) {
         set_error("crsh_traverse: workspace too small (%zu < %zu)", ws_bytes, need);
@@ -506,6 +597,7 @@ extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *
         P.p[k].node = k < levels ? pairs[k].node : nullptr;
         P.p[k].cap = k < levels ? pairs[k].capacity : 0;
     }
+    const batch_dev b = bd ? *bd : batch_dev{};
     const float *const *v = scene->v;
     if (tri_end > tri_begin) {
         uint32_t g = std::min<uint32_t>((tri_end - tri_begin + 255) / 256, 2048);
@@ -514,48 +606,114 @@ extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *
     }
     {
         uint32_t g = std::min<uint32_t>((nodes->capacity + 255) / 256, 2048);
+        if (g == 0) g = 1;
         k_node_pack<<<g, 256, 0, stream>>>(nd, meta, na, nb, ns);
     }
     k_no_storage<<<1, 1, 0, stream>>>(meta, (uint32_t)levels);
     const uint32_t scan_grid = (uint32_t)std::min<uint64_t>((items + SCAN_TILE - 1) / SCAN_TILE, 1u << 20);
-    {
-        uint32_t g = (uint32_t)std::min<uint64_t>((top_items + 3) / 4, 2048);
-        if (g == 0) g = 1;
-        {
-            prof_scope ps("k_top_count", stream);
-            k_top_count<<<g, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first, scene->mesh_count, scene->msph,
-                                               scene->n_mesh, tri_begin, tri_end, P, S, meta);
+    const uint32_t top_grid = (uint32_t)std::max<uint64_t>(std::min<uint64_t>((top_items + 3) / 4, 2048), 1);
+    const uint32_t Fu = (uint32_t)merge;
+
+    // top-level pass: plain (L = 0, the one top level) or a batch level L
+    auto top_pass_launch = [&](uint32_t L) {
+        if (bd) {
+            k_batch_top_plan<<<1, 256, 0, stream>>>(b, meta, L);
+            {
+                prof_scope ps("k_top_count", stream);
+                k_top_count<true><<<top_grid, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first,
+                                                                scene->mesh_count, scene->msph, scene->n_mesh,
+                                                                tri_begin, tri_end, P, S, meta, b, L);
+            }
+            k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(0, scene->n_mesh, P, S, meta, L, b.top);
+            {
+                prof_scope ps("k_top_emit", stream);
+                k_top_emit<true><<<top_grid, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first,
+                                                               scene->mesh_count, scene->msph, scene->n_mesh,
+                                                               tri_begin, tri_end, P, S, meta, b, L);
+            }
+        } else {
+            {
+                prof_scope ps("k_top_count", stream);
+                k_top_count<false><<<top_grid, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first,
+                                                                 scene->mesh_count, scene->msph, scene->n_mesh,
+                                                                 tri_begin, tri_end, P, S, meta, b, 0);
+            }
+            k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(0, scene->n_mesh, P, S, meta, 0, nullptr);
+            {
+                prof_scope ps("k_top_emit", stream);
+                k_top_emit<false><<<top_grid, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first,
+                                                                scene->mesh_count, scene->msph, scene->n_mesh,
+                                                                tri_begin, tri_end, P, S, meta, b, 0);
+            }
         }
-        k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(0, scene->n_mesh, P, S, meta);
-        {
-            prof_scope ps("k_top_emit", stream);
-            k_top_emit<<<g, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first, scene->mesh_count, scene->msph,
-                                              scene->n_mesh, tri_begin, tri_end, P, S, meta);
-        }
-    }
-    for (int L = levels; L >= 2; --L) {
+    };
+    // one level pass: pairs of level L (1-based parent) -> level L - 1
+    auto level_pass_launch = [&](int L) {
         const uint64_t tiles = (pairs[L - 1].capacity + LEVEL_TILE - 1) / LEVEL_TILE;
         uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096);
-        const uint32_t Fu = (uint32_t)merge;
+#define CRSH_COUNT(NF, BT)                                                                                   \
+    k_level_count<NF, LEVEL_PPT, BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, \
+                                                                      meta, b)
+#define CRSH_EMIT(NF, BT) k_level_emit<NF, LEVEL_PPT, BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta, b)
         {
             prof_scope ps("k_level", stream);
-            switch (nf) {
-            case 2: k_level_count<2, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, meta); break;
-            case 4: k_level_count<4, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, meta); break;
-            case 8: k_level_count<8, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, meta); break;
-            default: k_level_count<16, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, meta); break;
+            if (bd) {
+                switch (nf) {
+                case 2: CRSH_COUNT(2, true); break;
+                case 4: CRSH_COUNT(4, true); break;
+                case 8: CRSH_COUNT(8, true); break;
+                default: CRSH_COUNT(16, true); break;
+                }
+            } else {
+                switch (nf) {
+                case 2: CRSH_COUNT(2, false); break;
+                case 4: CRSH_COUNT(4, false); break;
+                case 8: CRSH_COUNT(8, false); break;
+                default: CRSH_COUNT(16, false); break;
+                }
             }
         }
-        k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta);
+        k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
             prof_scope ps("k_level_emit", stream);
-            switch (nf) {
-            case 2: k_level_emit<2, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta); break;
-            case 4: k_level_emit<4, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta); break;
-            case 8: k_level_emit<8, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta); break;
-            default: k_level_emit<16, LEVEL_PPT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta); break;
+            if (bd) {
+                switch (nf) {
+                case 2: CRSH_EMIT(2, true); break;
+                case 4: CRSH_EMIT(4, true); break;
+                case 8: CRSH_EMIT(8, true); break;
+                default: CRSH_EMIT(16, true); break;
+                }
+            } else {
+                switch (nf) {
+                case 2: CRSH_EMIT(2, false); break;
+                case 4: CRSH_EMIT(4, false); break;
+                case 8: CRSH_EMIT(8, false); break;
+                default: CRSH_EMIT(16, false); break;
+                }
             }
         }
+#undef CRSH_COUNT
+#undef CRSH_EMIT
+    };
+    if (bd) {
+        for (int L = batch_levels; L >= 1; --L) {
+            if (L < batch_levels) level_pass_launch(L + 1);
+            top_pass_launch((uint32_t)L);
+        }
+    } else {
+        top_pass_launch(0);
+        for (int L = levels; L >= 2; --L) level_pass_launch(L);
     }
     return hip_check(hipGetLastError(), "crsh_traverse launch");
+}
+
+}  // namespace crsh
+
+extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin,
+                                     uint32_t tri_end, int32_t bundle, int32_t merge,
+                                     const crsh_pairs pairs[CRSH_MAX_LEVELS], crsh_meta *meta, void *ws,
+                                     size_t ws_bytes, hipStream_t stream)
+{
+    return traverse_launch(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, nullptr, 0,
+                           0, stream);
 }

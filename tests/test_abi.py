@@ -47,6 +47,12 @@ int main(void) {
   S(crsh_scene) O(crsh_scene, m) O(crsh_scene, msph) O(crsh_scene, n_mesh)
   S(crsh_pairs) O(crsh_pairs, capacity)
   S(crsh_hits) O(crsh_hits, v) O(crsh_hits, capacity)
+  S(crsh_frame) O(crsh_frame, n_lights) O(crsh_frame, lights) O(crsh_frame, eye) O(crsh_frame, t_min)
+  O(crsh_frame, inv_ext)
+  S(crsh_frame_meta) O(crsh_frame_meta, level_base) O(crsh_frame_meta, level_cnt) O(crsh_frame_meta, item_base)
+  S(crsh_batch) O(crsh_batch, gbuf) O(crsh_batch, scene) O(crsh_batch, rays) O(crsh_batch, sorted)
+  O(crsh_batch, ray_frame) O(crsh_batch, nodes) O(crsh_batch, pairs) O(crsh_batch, hits) O(crsh_batch, meta)
+  O(crsh_batch, top_item_capacity) O(crsh_batch, ws_bytes) O(crsh_batch, hit_block)
   return 0;
 }
 """
@@ -60,7 +66,8 @@ def test_ctypes_layouts_match_header(tmp_path):
                            "-I", "/opt/rocm/include", str(c), "-o", str(exe)])
     got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
     mirror = {"crsh_meta": X.Meta, "crsh_gbuf": X.Gbuf, "crsh_raygen": X.Raygen, "crsh_rays": X.Rays,
-              "crsh_nodes": X.Nodes, "crsh_scene": X.Scene, "crsh_pairs": X.Pairs, "crsh_hits": X.Hits}
+              "crsh_nodes": X.Nodes, "crsh_scene": X.Scene, "crsh_pairs": X.Pairs, "crsh_hits": X.Hits,
+              "crsh_frame": X.Frame, "crsh_frame_meta": X.FrameMeta, "crsh_batch": X.Batch}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")
@@ -102,6 +109,51 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert L.crsh_closest_hit(ctypes.byref(r), 1, 0, ctypes.byref(pt[0]), ctypes.byref(sc), ctypes.c_float(1e-4),
                               ctypes.byref(h), 1, 1, 1 << 30, None) == X.ERR_INVALID
     assert L.crsh_profile_next(None, 0, 1, 1) == X.ERR_INVALID
+
+
+def _dummy_batch(**kw):
+    b = X.Batch()
+    b.n_frames, b.frames, b.frame_meta = 2, 1, 1
+    b.gbuf = X.Gbuf(*([1] * 7), 64, 1)
+    b.mat_flags = b.mat_ior = b.keys = b.ids = b.skeys = b.sids = b.ray_frame = b.meta = b.ws = 1
+    b.rays = X.Rays(*([1] * 8), 100)
+    b.sorted = X.Rays(*([1] * 8), 100)
+    b.nodes = X.Nodes(*([1] * 11), 100)
+    b.scene = X.Scene((X.vp * 9)(*([1] * 9)), 10, 1, 1, 1, 1)
+    for k in range(4):
+        b.pairs[k] = X.Pairs(1, 1, 100)
+    b.hits = X.Hits(1, 1, 1, 1, 1, 100)
+    b.top_item_capacity = 100
+    b.ws_bytes = 1 << 30
+    b.bundle, b.merge, b.levels, b.hit_block = 8, 4, 4, 256
+    for k, v in kw.items():
+        setattr(b, k, v)
+    return b
+
+
+def test_invalid_batches_are_rejected_on_the_host():
+    L = X.lib()
+    bad = [dict(n_frames=0), dict(n_frames=X.MAX_FRAMES + 1), dict(frames=None), dict(ray_frame=None),
+           dict(levels=5), dict(levels=0), dict(levels=17), dict(hit_block=32), dict(bundle=0), dict(merge=1),
+           dict(ws_bytes=1000)]
+    for kw in bad:
+        b = _dummy_batch(**kw)
+        assert L.crsh_batch_enqueue(ctypes.byref(b), None) == X.ERR_INVALID, kw
+    assert "workspace" in X.last_error()
+    g = X.vp()
+    b = _dummy_batch(levels=5)
+    assert L.crsh_batch_graph_create(ctypes.byref(b), None, ctypes.byref(g)) == X.ERR_INVALID
+    assert not g.value
+    assert L.crsh_graph_launch(None, None) == X.ERR_INVALID
+    L.crsh_graph_destroy(None)
+
+
+def test_batch_workspace_grows_with_every_bound():
+    base = X.crsh_batch_ws_size(1 << 16, 1000, 1 << 12, 1 << 16, 1 << 12)
+    for args in ((1 << 17, 1000, 1 << 12, 1 << 16, 1 << 12), (1 << 16, 100000, 1 << 12, 1 << 16, 1 << 12),
+                 (1 << 16, 1000, 1 << 16, 1 << 16, 1 << 12), (1 << 16, 1000, 1 << 12, 1 << 20, 1 << 12),
+                 (1 << 16, 1000, 1 << 12, 1 << 16, 1 << 22)):
+        assert X.crsh_batch_ws_size(*args) > base, args
 
 
 def test_workspace_size_covers_every_stage():

@@ -1,0 +1,179 @@
+"""GPU adjoint of the closest hit (Sec. 3.3.8) behind torch.autograd.
+
+Forward: caller-given rays through the whole path equal the oracle's closest
+hits.  Backward: checked against float64 central finite differences (h=1e-4)
+of the oracle's fixed-triangle Moller-Trumbore solve, on rays whose
+barycentric margin exceeds 1e-3, for a sample of vertex coordinates and ray
+parameters; against the translation-invariance identity (moving every vertex
+and every ray origin together changes no t, u, v, so the gradients sum to
+zero); and against a closed form.
+"""
+import numpy as np
+import pytest
+
+from conftest import workload, oracle_run
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _scene(wl, **kw):
+    from paper_2312_06538_amd.autograd import RayScene
+    sc = wl.scene
+    return RayScene(sc.faces, sc.mesh_first, sc.mesh_count, sc.mesh_sphere, wl.lo, wl.inv_ext, B=wl.B, F=wl.F,
+                    levels=wl.n, t_min=wl.t_min, ray_type=1, **kw)
+
+
+@pytest.fixture(scope="module")
+def adjoint_case():
+    import torch
+    from paper_2312_06538_amd.autograd import ClosestHit
+    print("[adjoint] building workload", flush=True)
+    wl = workload("adjoint_512")
+    o_run = oracle_run("adjoint_512")
+    h = o_run["hash"]
+    r = h["rays"]
+    o = np.stack([r["ox"], r["oy"], r["oz"]], 1)
+    d = np.stack([r["dx"], r["dy"], r["dz"]], 1)
+    verts = torch.tensor(wl.scene.verts, device="cuda", requires_grad=True)
+    ot = torch.tensor(o, device="cuda", requires_grad=True)
+    dt = torch.tensor(d, device="cuda", requires_grad=True)
+    scene = _scene(wl, pair_capacity=1 << 20)
+    tri, t, u, v = ClosestHit.apply(verts, ot, dt, scene)
+    rng = np.random.default_rng(0)
+    n = len(o)
+    w, a, b = (rng.normal(size=n).astype(np.float32) for _ in range(3))
+    tri_np, u_np, v_np = tri.cpu().numpy(), u.detach().cpu().numpy(), v.detach().cpu().numpy()
+    margin = np.minimum(np.minimum(u_np, v_np), 1 - u_np - v_np)
+    keep = (tri_np >= 0) & (margin > 1e-3)
+    w, a, b = (np.where(keep, x, 0).astype(np.float32) for x in (w, a, b))
+    W, A, Bw = (torch.tensor(x, device="cuda") for x in (w, a, b))
+    loss = (W * t).sum() + (A * u).sum() + (Bw * v).sum()
+    loss.backward()
+    return dict(wl=wl, oracle=o_run, o=o, d=d, tri=tri_np, t=t.detach().cpu().numpy(), u=u_np, v=v_np,
+                w=w, a=a, b=b, keep=keep, g_verts=verts.grad.cpu().numpy(), g_o=ot.grad.cpu().numpy(),
+                g_d=dt.grad.cpu().numpy())
+
+
+def test_forward_matches_oracle(adjoint_case):
+    c = adjoint_case
+    o = c["oracle"]["hits"]
+    assert np.array_equal(c["tri"], o[0])
+    for x, y in zip((c["t"], c["u"], c["v"]), o[1:]):
+        assert np.allclose(x, y, rtol=1e-5, atol=0)
+    assert c["keep"].sum() > 10000
+
+
+def _loss_terms(c, ray, o, d, tri9):
+    ok, tuv = O.mt64(o, d, tri9)
+    assert ok
+    return c["w"][ray] * tuv[0] + c["a"][ray] * tuv[1] + c["b"][ray] * tuv[2]
+
+
+def _check(g, g_fd):
+    g, g_fd = np.asarray(g), np.asarray(g_fd)
+    rel = np.linalg.norm(g - g_fd) / np.linalg.norm(g_fd)
+    assert rel <= 1e-3, rel
+    tol = 1e-3 * np.maximum(np.abs(g_fd), 1e-3 * np.abs(g_fd).max())
+    bad = np.abs(g - g_fd) > tol
+    assert not bad.any(), (np.nonzero(bad)[0][:10], g[bad][:5], g_fd[bad][:5])
+
+
+def test_vertex_gradients_match_finite_differences(adjoint_case):
+    c = adjoint_case
+    sc = c["wl"].scene
+    faces = sc.faces.astype(np.int64)
+    verts = sc.verts.astype(np.float64)
+    hit_rays = np.nonzero(c["keep"])[0]
+    by_vertex = {}
+    for ray in hit_rays:
+        for k in range(3):
+            by_vertex.setdefault(int(faces[c["tri"][ray], k]), []).append(ray)
+    rng = np.random.default_rng(1)
+    cand = np.array(sorted(by_vertex))
+    pick = rng.choice(len(cand) * 3, size=min(2048, len(cand) * 3), replace=False)
+    h = 1e-4
+    g, g_fd = [], []
+    for p in pick:
+        vj, comp = int(cand[p // 3]), int(p % 3)
+        acc = 0.0
+        for ray in by_vertex[vj]:
+            f = faces[c["tri"][ray]]
+            tri9 = verts[f].reshape(-1).copy()
+            o = c["o"][ray].astype(np.float64)
+            d = c["d"][ray].astype(np.float64)
+            for sgn in (1, -1):
+                t9 = tri9.copy()
+                for k in range(3):
+                    if f[k] == vj:
+                        t9[3 * k + comp] += sgn * h
+                acc += sgn * _loss_terms(c, ray, o, d, t9)
+        g_fd.append(acc / (2 * h))
+        g.append(c["g_verts"][vj, comp])
+    _check(g, g_fd)
+
+
+def test_ray_gradients_match_finite_differences(adjoint_case):
+    c = adjoint_case
+    sc = c["wl"].scene
+    faces = sc.faces.astype(np.int64)
+    verts = sc.verts.astype(np.float64)
+    rays = np.random.default_rng(2).choice(np.nonzero(c["keep"])[0], 342, replace=False)
+    h = 1e-4
+    g, g_fd = [], []
+    for ray in rays:
+        tri9 = verts[faces[c["tri"][ray]]].reshape(-1)
+        o = c["o"][ray].astype(np.float64)
+        d = c["d"][ray].astype(np.float64)
+        for which, vec in (("o", o), ("d", d)):
+            for comp in range(3):
+                p, m = vec.copy(), vec.copy()
+                p[comp] += h
+                m[comp] -= h
+                if which == "o":
+                    lp, lm = _loss_terms(c, ray, p, d, tri9), _loss_terms(c, ray, m, d, tri9)
+                else:
+                    lp, lm = _loss_terms(c, ray, o, p, tri9), _loss_terms(c, ray, o, m, tri9)
+                g_fd.append((lp - lm) / (2 * h))
+                g.append(c["g_o" if which == "o" else "g_d"][ray, comp])
+    _check(g, g_fd)
+
+
+def test_gradients_are_translation_invariant(adjoint_case):
+    c = adjoint_case
+    s = c["g_verts"].astype(np.float64).sum(0) + c["g_o"].astype(np.float64).sum(0)
+    scale = np.abs(c["g_verts"]).sum() + np.abs(c["g_o"]).sum()
+    assert np.all(np.abs(s) <= 1e-4 * scale), (s, scale)
+    # misses and masked rays get no gradient
+    assert np.all(c["g_o"][c["tri"] < 0] == 0) and np.all(c["g_d"][c["tri"] < 0] == 0)
+
+
+def test_closed_form_axis_aligned_triangle():
+    import torch
+    from paper_2312_06538_amd.autograd import RayScene, ClosestHit
+    verts = torch.tensor([[0, 0, 0], [1, 0, 0], [0, 1, 0]], dtype=torch.float32, device="cuda",
+                         requires_grad=True)
+    o = torch.tensor([[0.25, 0.5, 1.0]], device="cuda", requires_grad=True)
+    d = torch.tensor([[0.0, 0.0, -1.0]], device="cuda", requires_grad=True)
+    scene = RayScene(np.array([[0, 1, 2]]), [0], [1], np.array([[0.5, 0.5, 0.0, 1.0]]), [-2, -2, -2],
+                     [0.25, 0.25, 0.25], B=1, F=2, levels=1)
+    tri, t, u, v = ClosestHit.apply(verts, o, d, scene)
+    assert tri.item() == 0 and (t.item(), u.item(), v.item()) == (1.0, 0.25, 0.5)
+    t.sum().backward(retain_graph=True)
+    # t = o_z / (-d_z): dt/do = (0,0,1), dt/dd = (0,0,1); raising the plane lowers t
+    assert np.allclose(o.grad.cpu().numpy(), [[0, 0, 1]])
+    assert np.allclose(d.grad.cpu().numpy(), [[0, 0, 1]])
+    assert np.allclose(verts.grad.cpu().numpy()[:, 2], [-0.25, -0.25, -0.5])
+    for x in (verts, o, d):
+        x.grad = None
+    u.sum().backward()
+    # u follows the origin's x; stretching v1 along x shrinks it
+    assert np.allclose(o.grad.cpu().numpy(), [[1, 0, 0]])
+    assert np.allclose(verts.grad.cpu().numpy()[1], [-0.25, 0, 0])

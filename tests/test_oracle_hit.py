@@ -133,3 +133,47 @@ def test_tie_breaks_to_lower_triangle_and_tmax_respected():
     tr = O.traverse(tree, sc)
     hits = O.closest_hit(rays, np.arange(2, dtype=np.uint32), 2, tr["pairs"][1], sc, 1e-4)
     assert list(hits[0]) == [1, -1]
+
+
+def test_mt64_closed_form_and_derivatives():
+    """The float64 fixed-triangle solve used for finite differences: exact on
+    an axis-aligned case, and its derivatives there are the textbook ones
+    (t grows with the origin's height, u and v follow the origin's x, y)."""
+    tri = np.array([0, 0, 0, 1, 0, 0, 0, 1, 0], np.float64)
+    o = np.array([0.25, 0.5, 1.0])
+    d = np.array([0.0, 0.0, -1.0])
+    ok, tuv = O.mt64(o, d, tri)
+    assert ok and np.array_equal(tuv, [1.0, 0.25, 0.5])
+    h = 1e-4
+    def fd(vec, k):
+        a, b = vec.copy(), vec.copy()
+        a[k] += h
+        b[k] -= h
+        return a, b
+    for k, want in ((0, [0, 1, 0]), (1, [0, 0, 1]), (2, [1, 0, 0])):
+        a, b = fd(o, k)
+        g = (O.mt64(a, d, tri)[1] - O.mt64(b, d, tri)[1]) / (2 * h)
+        assert np.allclose(g, want, atol=1e-9)
+    # moving v1 along x by h stretches u: u = 0.25 / (1 + h)
+    a, b = fd(tri, 3)
+    g = (O.mt64(o, d, a)[1] - O.mt64(o, d, b)[1]) / (2 * h)
+    assert np.allclose(g, [0, -0.25, 0], atol=1e-7)
+
+
+def test_mt64_agrees_with_float32_test(rng):
+    n = 0
+    for _ in range(500):
+        tri = rng.normal(size=9) * 3
+        o = rng.normal(size=3) * 5
+        target = tri[:3] + 0.3 * (tri[3:6] - tri[:3]) + 0.3 * (tri[6:] - tri[:3])
+        d = (target - o) / np.linalg.norm(target - o)
+        hit, tuv = O.mt(o.astype(np.float32), d.astype(np.float32), 1e-4,
+                        np.float32(np.finfo(np.float32).max), tri.astype(np.float32))
+        ok, t64 = O.mt64(o.astype(np.float32).astype(np.float64), d.astype(np.float32).astype(np.float64),
+                         tri.astype(np.float32).astype(np.float64))
+        nrm = np.cross(tri[3:6] - tri[:3], tri[6:] - tri[:3])
+        if not hit or abs(d @ nrm) / np.linalg.norm(nrm) < 0.1:
+            continue
+        n += 1
+        assert np.allclose(tuv, t64, rtol=1e-4, atol=1e-4)
+    assert n > 100
