@@ -233,6 +233,16 @@ crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *scene,
                           const crsh_pairs pairs[CRSH_MAX_LEVELS], crsh_meta *meta,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Stage 4 without its last level pass: as crsh_traverse, but the level-1
+ * pairs that descend from level 2 are not formed; crsh_leaf_hit forms and
+ * consumes them on chip.  pairs[0] still needs storage: a hierarchy whose top
+ * is level 1 gets its level-1 pairs from the top-level pass. */
+crsh_status crsh_traverse_upper(const crsh_nodes *nodes, const crsh_scene *scene,
+                                uint32_t tri_begin, uint32_t tri_end,
+                                int32_t bundle, int32_t merge,
+                                const crsh_pairs pairs[CRSH_MAX_LEVELS], crsh_meta *meta,
+                                void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Clear the closest-hit scratch before a frame (tkey = all ones). */
 crsh_status crsh_hits_reset(crsh_hits *hits, hipStream_t stream);
 
@@ -247,6 +257,23 @@ crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t *sorted_ids
                              const crsh_scene *scene, float t_min,
                              crsh_hits *hits, crsh_meta *meta,
                              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Stages 4 (level 1, Eq. 9) and 5 (Sec. 3.3.8) fused, after
+ * crsh_traverse_upper: the level-2 pairs pairs[1] are grouped by node; for
+ * each node and triangle the node's children (leaves) are tested (Eq. 9) and
+ * every passing (triangle, leaf) is tested against the leaf's rays
+ * (Moller-Trumbore), with the rays and their running closest hits kept on
+ * chip.  Level-1 pairs stored in pairs[0] (top level 1) are tested as in
+ * crsh_closest_hit.  Results and counters equal crsh_traverse followed by
+ * crsh_closest_hit: meta->tests[0], hits[0] (level-1 pairs formed) and
+ * final_tests accumulate; the level-1 pairs are not stored.  `sorted`,
+ * `sorted_ids`, `nodes`, bundle and merge as given to crsh_build.
+ * ws: crsh_workspace_size() bytes. */
+crsh_status crsh_leaf_hit(const crsh_rays *sorted, const uint32_t *sorted_ids,
+                          int32_t bundle, int32_t merge, const crsh_nodes *nodes,
+                          const crsh_pairs pairs[CRSH_MAX_LEVELS], const crsh_scene *scene,
+                          float t_min, crsh_hits *hits, crsh_meta *meta,
+                          void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Stage 1 for rays the caller already has (e.g. a differentiable renderer):
  * keys[i] = the hash of ray i under the same layout as crsh_hash -- `type`
@@ -367,6 +394,8 @@ typedef struct crsh_batch {
     void *ws;
     size_t ws_bytes;
     int32_t bundle, merge, levels, hit_block;
+    int32_t leaf_hit;                   /* nonzero: last level fused with the final tests (crsh_leaf_hit);
+                                           pairs[0] then holds only top-level-1 pairs */
 } crsh_batch;
 
 typedef struct crsh_graph crsh_graph;

@@ -34,7 +34,7 @@ class DeviceBatch:
     (B, F, levels); hit_block is the workgroup size of the final tests."""
 
     def __init__(self, wls, B, F, levels, hit_block=256, pair_capacity=1 << 22, keep_levels=False,
-                 device="cuda"):
+                 leaf_hit=True, device="cuda"):
         if not 1 <= len(wls) <= X.MAX_FRAMES:
             raise ValueError(f"a batch holds 1..{X.MAX_FRAMES} frames")
         dev = torch.device(device)
@@ -42,6 +42,7 @@ class DeviceBatch:
         self.wls = list(wls)
         self.B, self.F, self.levels, self.hit_block = int(B), int(F), int(levels), int(hit_block)
         self.keep_levels = keep_levels
+        self.leaf_hit = bool(leaf_hit)
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
         frames = (X.Frame * len(wls))()
         gb = {k: [] for k in ("px", "py", "pz", "nx", "ny", "nz", "mat")}
@@ -160,6 +161,7 @@ class DeviceBatch:
         b.top_item_capacity = self.top_cap
         b.ws, b.ws_bytes = _p(self.ws), self.ws_bytes
         b.bundle, b.merge, b.levels, b.hit_block = self.B, self.F, self.levels, self.hit_block
+        b.leaf_hit = 1 if self.leaf_hit else 0
         return b
 
     # ------------------------------------------------------------- running

@@ -100,7 +100,8 @@ class Batch(C.Structure):
                 ("keys", vp), ("ids", vp), ("skeys", vp), ("sids", vp), ("ray_frame", vp),
                 ("nodes", Nodes), ("pairs", PairTable), ("hits", Hits), ("meta", vp),
                 ("top_item_capacity", C.c_uint64), ("ws", vp), ("ws_bytes", C.c_size_t),
-                ("bundle", C.c_int32), ("merge", C.c_int32), ("levels", C.c_int32), ("hit_block", C.c_int32)]
+                ("bundle", C.c_int32), ("merge", C.c_int32), ("levels", C.c_int32), ("hit_block", C.c_int32),
+                ("leaf_hit", C.c_int32)]
 
 _lib = None
 
@@ -136,6 +137,12 @@ def lib():
         L.crsh_traverse.restype = st
         L.crsh_traverse.argtypes = [C.POINTER(Nodes), C.POINTER(Scene), C.c_uint32, C.c_uint32, C.c_int32,
                                     C.c_int32, PairTable, vp, vp, C.c_size_t, vp]
+        L.crsh_traverse_upper.restype = st
+        L.crsh_traverse_upper.argtypes = [C.POINTER(Nodes), C.POINTER(Scene), C.c_uint32, C.c_uint32, C.c_int32,
+                                          C.c_int32, PairTable, vp, vp, C.c_size_t, vp]
+        L.crsh_leaf_hit.restype = st
+        L.crsh_leaf_hit.argtypes = [C.POINTER(Rays), vp, C.c_int32, C.c_int32, C.POINTER(Nodes), PairTable,
+                                    C.POINTER(Scene), C.c_float, C.POINTER(Hits), vp, vp, C.c_size_t, vp]
         L.crsh_hits_reset.restype = st
         L.crsh_hits_reset.argtypes = [C.POINTER(Hits), vp]
         L.crsh_hash_rays.restype = st
@@ -207,6 +214,17 @@ def crsh_build(rays, sorted_ids, bundle, merge, levels, nodes, sorted_rays, meta
 def crsh_traverse(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, stream):
     return _check(lib().crsh_traverse(C.byref(nodes), C.byref(scene), tri_begin, tri_end, bundle, merge, pairs,
                                       meta, ws, ws_bytes, stream))
+
+
+def crsh_traverse_upper(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, stream):
+    return _check(lib().crsh_traverse_upper(C.byref(nodes), C.byref(scene), tri_begin, tri_end, bundle, merge,
+                                            pairs, meta, ws, ws_bytes, stream))
+
+
+def crsh_leaf_hit(sorted_rays, sorted_ids, bundle, merge, nodes, pairs, scene, t_min, hits, meta, ws, ws_bytes,
+                  stream):
+    return _check(lib().crsh_leaf_hit(C.byref(sorted_rays), sorted_ids, bundle, merge, C.byref(nodes), pairs,
+                                      C.byref(scene), t_min, C.byref(hits), meta, ws, ws_bytes, stream))
 
 
 def crsh_hits_reset(hits, stream):

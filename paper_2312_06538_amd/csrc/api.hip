@@ -110,7 +110,7 @@ extern "C" size_t crsh_workspace_size(uint32_t max_rays, uint32_t max_tris, uint
     size_t a = sort_ws_bytes(max_rays);
     size_t b = hash_ws_bytes(max_rays);
     size_t c = trav_ws_bytes(max_tris, max_nodes, (uint64_t)max_nodes * max_meshes, max_pairs);
-    size_t d = hit_ws_bytes(max_tris);
+    size_t d = std::max(hit_ws_bytes(max_tris), leaf_hit_ws_bytes(max_tris, max_nodes, max_pairs));
     return std::max(std::max(a, b), std::max(c, d));
 }
 

@@ -38,7 +38,7 @@ static batch_layout layout(uint32_t ray_cap, uint64_t pixels, uint32_t m, uint32
     L.stage = L.top + align256(2 * sizeof(uint64_t));
     size_t st = std::max(sort_ws_bytes(ray_cap), hash_ws_bytes(pixels));
     st = std::max(st, trav_ws_bytes(m, node_cap, top_items, max_pairs));
-    st = std::max(st, hit_ws_bytes(m));
+    st = std::max(st, std::max(hit_ws_bytes(m), leaf_hit_ws_bytes(m, node_cap, max_pairs)));
     L.total = L.stage + st;
     return L;
 }
@@ -172,10 +172,14 @@ extern "C" crsh_status crsh_batch_enqueue(const crsh_batch *b, hipStream_t strea
     crsh_nodes nodes = b->nodes;
     st = build_launch(&rays, b->sids, b->bundle, b->merge, b->levels, &nodes, &sorted, b->meta, &bd, stream);
     if (st != CRSH_OK) return st;
+    const int32_t lowest = b->leaf_hit ? 2 : 1;
     st = traverse_launch(&nodes, &b->scene, 0, b->scene.m, b->bundle, b->merge, b->pairs, b->meta, stage,
-                         stage_bytes, &bd, b->levels, b->top_item_capacity, stream);
+                         stage_bytes, &bd, b->levels, b->top_item_capacity, lowest, stream);
     if (st != CRSH_OK) return st;
     crsh_hits hits = b->hits;
+    if (b->leaf_hit && b->levels >= 2)
+        return leaf_hit_launch(&sorted, b->sids, b->bundle, b->merge, &nodes, &b->pairs[0], &b->pairs[1],
+                               &b->scene, 0.0f, &hits, b->meta, stage, stage_bytes, &bd, b->hit_block, stream);
     return hit_launch(&sorted, b->sids, b->bundle, &b->pairs[0], &b->scene, 0.0f, &hits, b->meta, stage,
                       stage_bytes, &bd, b->hit_block, stream);
 }

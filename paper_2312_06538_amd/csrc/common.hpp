@@ -217,11 +217,28 @@ crsh_status build_launch(const crsh_rays *rays, const uint32_t *sorted_ids, int3
 crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin, uint32_t tri_end,
                             int32_t bundle, int32_t merge, const crsh_pairs pairs[CRSH_MAX_LEVELS],
                             crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t levels,
-                            uint64_t top_items, hipStream_t stream);
+                            uint64_t top_items, int32_t lowest, hipStream_t stream);
 crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
                        const crsh_pairs *level1, const crsh_scene *scene, float t_min, crsh_hits *hits,
                        crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t hit_block,
                        hipStream_t stream);
+crsh_status leaf_hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle, int32_t merge,
+                            const crsh_nodes *nodes, const crsh_pairs *level1, const crsh_pairs *level2,
+                            const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, void *ws,
+                            size_t ws_bytes, const batch_dev *bd, int32_t hit_block, hipStream_t stream);
+// pieces of the final tests shared by crsh_closest_hit and crsh_leaf_hit
+crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle, const crsh_pairs *level1,
+                      const crsh_scene *scene, crsh_hits *hits, crsh_meta *meta, void *ws, int32_t hit_block,
+                      const char *who);
+void hit_prep_launch(const crsh_scene *scene, float4 *tri, hipStream_t stream);
+void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const crsh_pairs *level1, int32_t bundle,
+                      const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
+                      int32_t hit_block, hipStream_t stream);
+void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
+                      const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
+                      hipStream_t stream);
+void tri_spheres_launch(const crsh_scene *scene, uint32_t b, uint32_t e, float4 *out, hipStream_t stream);
+size_t leaf_hit_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t level2_cap);
 
 // launch helpers
 void set_error(const char *fmt, ...);

@@ -157,76 +157,104 @@ extern "C" crsh_status crsh_hits_reset(crsh_hits *hits, hipStream_t stream)
 
 namespace crsh {
 
-crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
-                       const crsh_pairs *level1, const crsh_scene *scene, float t_min, crsh_hits *hits,
-                       crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t hit_block,
-                       hipStream_t stream)
+void hit_prep_launch(const crsh_scene *scene, float4 *tri, hipStream_t stream)
 {
-    if (!sorted || !sorted_ids || !level1 || !scene || !hits || !meta || !ws) {
-        set_error("crsh_closest_hit: NULL argument");
-        return CRSH_ERR_INVALID;
-    }
-    if (bundle < 1 || bundle > CRSH_MAX_BUNDLE) {
-        set_error("crsh_closest_hit: bundle must be in [1, %d]", CRSH_MAX_BUNDLE);
-        return CRSH_ERR_INVALID;
-    }
-    if (hit_block != 64 && hit_block != 128 && hit_block != 256) {
-        set_error("crsh_closest_hit: workgroup size must be 64, 128 or 256");
-        return CRSH_ERR_INVALID;
-    }
-    if (!sorted->ox || !sorted->oy || !sorted->oz || !sorted->dx || !sorted->dy || !sorted->dz ||
-        !sorted->tmax || !hits->tkey || !hits->tri || !hits->t || !hits->u || !hits->v ||
-        (level1->capacity && (!level1->tri || !level1->node))) {
-        set_error("crsh_closest_hit: incomplete arrays");
-        return CRSH_ERR_INVALID;
-    }
-    for (int k = 0; k < 9; ++k)
-        if (!scene->v[k] && scene->m) {
-            set_error("crsh_closest_hit: missing vertex array");
-            return CRSH_ERR_INVALID;
-        }
-    if (hits->capacity < sorted->capacity) {
-        set_error("crsh_closest_hit: hit capacity below the ray capacity");
-        return CRSH_ERR_INVALID;
-    }
-    if (ws_bytes < hit_ws_bytes(scene->m)) {
-        set_error("crsh_closest_hit: workspace too small (%zu < %zu)", ws_bytes, hit_ws_bytes(scene->m));
-        return CRSH_ERR_INVALID;
-    }
-    const batch_dev b = bd ? *bd : batch_dev{};
-    float4 *tri = (float4 *)ws;
     const float *const *v = scene->v;
     if (scene->m) {
         uint32_t g = std::min<uint32_t>((scene->m + 255) / 256, 2048);
         k_hit_prep<<<g, 256, 0, stream>>>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], scene->m, tri);
     }
+}
+
+void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const crsh_pairs *level1, int32_t bundle,
+                      const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
+                      int32_t hit_block, hipStream_t stream)
+{
+    if (!level1->capacity) return;
     uint32_t log2G = 0;
     while ((1u << log2G) < (uint32_t)bundle) ++log2G;
     sorted_rays R{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
-    if (level1->capacity) {
-        const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
-        prof_scope ps("k_hit", stream);
-        if (bd)
-            k_hit<true><<<grid, hit_block, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity,
-                                                        (uint32_t)bundle, log2G, t_min, hits->tkey, meta,
-                                                        sorted->capacity, scene->m, b);
-        else
-            k_hit<false><<<grid, hit_block, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity,
-                                                         (uint32_t)bundle, log2G, t_min, hits->tkey, meta,
-                                                         sorted->capacity, scene->m, b);
-    }
+    const batch_dev b = bd ? *bd : batch_dev{};
+    const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
+    prof_scope ps("k_hit", stream);
+    if (bd)
+        k_hit<true><<<grid, hit_block, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity,
+                                                    (uint32_t)bundle, log2G, t_min, hits->tkey, meta,
+                                                    sorted->capacity, scene->m, b);
+    else
+        k_hit<false><<<grid, hit_block, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity,
+                                                     (uint32_t)bundle, log2G, t_min, hits->tkey, meta,
+                                                     sorted->capacity, scene->m, b);
+}
+
+void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
+                      const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
+                      hipStream_t stream)
+{
+    sorted_rays R{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
+    const batch_dev b = bd ? *bd : batch_dev{};
     uint32_t g = std::min<uint32_t>((sorted->capacity + 255) / 256, 4096);
     if (g == 0) g = 1;
     hit_out o{hits->tri, hits->t, hits->u, hits->v};
-    {
-        prof_scope ps("k_hit_final", stream);
-        if (bd)
-            k_hit_final<true><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta,
-                                                     sorted->capacity, scene->m, b);
-        else
-            k_hit_final<false><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta,
-                                                      sorted->capacity, scene->m, b);
+    prof_scope ps("k_hit_final", stream);
+    if (bd)
+        k_hit_final<true><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta, sorted->capacity,
+                                                 scene->m, b);
+    else
+        k_hit_final<false><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta,
+                                                  sorted->capacity, scene->m, b);
+}
+
+crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle, const crsh_pairs *level1,
+                      const crsh_scene *scene, crsh_hits *hits, crsh_meta *meta, void *ws, int32_t hit_block,
+                      const char *who)
+{
+    if (!sorted || !sorted_ids || !level1 || !scene || !hits || !meta || !ws) {
+        set_error("%s: NULL argument", who);
+        return CRSH_ERR_INVALID;
     }
+    if (bundle < 1 || bundle > CRSH_MAX_BUNDLE) {
+        set_error("%s: bundle must be in [1, %d]", who, CRSH_MAX_BUNDLE);
+        return CRSH_ERR_INVALID;
+    }
+    if (hit_block != 64 && hit_block != 128 && hit_block != 256) {
+        set_error("%s: workgroup size must be 64, 128 or 256", who);
+        return CRSH_ERR_INVALID;
+    }
+    if (!sorted->ox || !sorted->oy || !sorted->oz || !sorted->dx || !sorted->dy || !sorted->dz ||
+        !sorted->tmax || !hits->tkey || !hits->tri || !hits->t || !hits->u || !hits->v ||
+        (level1->capacity && (!level1->tri || !level1->node))) {
+        set_error("%s: incomplete arrays", who);
+        return CRSH_ERR_INVALID;
+    }
+    for (int k = 0; k < 9; ++k)
+        if (!scene->v[k] && scene->m) {
+            set_error("%s: missing vertex array", who);
+            return CRSH_ERR_INVALID;
+        }
+    if (hits->capacity < sorted->capacity) {
+        set_error("%s: hit capacity below the ray capacity", who);
+        return CRSH_ERR_INVALID;
+    }
+    return CRSH_OK;
+}
+
+crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
+                       const crsh_pairs *level1, const crsh_scene *scene, float t_min, crsh_hits *hits,
+                       crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t hit_block,
+                       hipStream_t stream)
+{
+    crsh_status st = hit_check(sorted, sorted_ids, bundle, level1, scene, hits, meta, ws, hit_block,
+                               "crsh_closest_hit");
+    if (st != CRSH_OK) return st;
+    if (ws_bytes < hit_ws_bytes(scene->m)) {
+        set_error("crsh_closest_hit: workspace too small (%zu < %zu)", ws_bytes, hit_ws_bytes(scene->m));
+        return CRSH_ERR_INVALID;
+    }
+    float4 *tri = (float4 *)ws;
+    hit_prep_launch(scene, tri, stream);
+    hit_pairs_launch(sorted, tri, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream);
+    hit_final_launch(sorted, sorted_ids, tri, scene, t_min, hits, meta, bd, stream);
     return hip_check(hipGetLastError(), "crsh_closest_hit launch");
 }
 

@@ -381,11 +381,17 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     }
 }
 
+// Survivors of a tile are first placed in LDS at their tile-local offsets
+// and then copied out with consecutive lanes writing consecutive pairs, so
+// the stores are coalesced whatever the pass masks.
 template <int NF, int PPT, bool BATCH>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_level, uint32_t F, pair_levels P,
                                                               trav_scratch S, const crsh_meta *meta, batch_dev bd)
 {
+    constexpr uint32_t TILE_OUT = LEVEL_TILE * NF;
     __shared__ uint32_t s_scan[LEVEL_THREADS / WAVE];
+    __shared__ uint32_t s_tri[TILE_OUT];
+    __shared__ uint32_t s_node[TILE_OUT];
     const uint32_t nl = meta->n_levels;
     if ((uint32_t)parent_level > nl) return;
     const pairs_dev in = P.p[parent_level - 1];
@@ -401,30 +407,38 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
         const uint32_t mask = S.mask[tile * LEVEL_THREADS + threadIdx.x];
         uint32_t total;
         const uint32_t ex = block_excl_scan<uint32_t, LEVEL_THREADS / WAVE>((uint32_t)__popc(mask), s_scan, total);
-        if (!mask) continue;
-        const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
-        uint32_t tri[PPT], par[PPT];
+        if (mask) {
+            const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
+            uint32_t at = ex;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const bool ok = ((mask >> (k * NF)) & ((1u << NF) - 1u)) != 0u;
-            tri[k] = ok ? in.tri[q0 + k] : 0u;
-            par[k] = ok ? in.node[q0 + k] : 0u;
-        }
-        uint64_t at = S.off[tile] + ex;
+            for (int k = 0; k < PPT; ++k) {
+                if (((mask >> (k * NF)) & ((1u << NF) - 1u)) == 0u) continue;
+                const uint32_t tri = in.tri[q0 + k];
+                const uint32_t par = in.node[q0 + k];
+                uint32_t first = par * F;
+                if constexpr (BATCH) first = par < np ? bd.node_first[offp + par] : 0u;
 #pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            uint32_t first = par[k] * F;
-            if constexpr (BATCH) first = par[k] < np ? bd.node_first[offp + par[k]] : 0u;
-#pragma unroll
-            for (int j = 0; j < NF; ++j) {
-                if (!((mask >> (k * NF + j)) & 1u)) continue;
-                if (at < out.cap) {
-                    out.tri[at] = tri[k];
-                    out.node[at] = first + (uint32_t)j;
+                for (int j = 0; j < NF; ++j) {
+                    if (!((mask >> (k * NF + j)) & 1u)) continue;
+                    if (at < TILE_OUT) {
+                        s_tri[at] = tri;
+                        s_node[at] = first + (uint32_t)j;
+                    }
+                    ++at;
                 }
-                ++at;
             }
         }
+        __syncthreads();
+        const uint64_t base = S.off[tile];
+        const uint32_t n_out = min(total, TILE_OUT);
+        for (uint32_t i = threadIdx.x; i < n_out; i += LEVEL_THREADS) {
+            const uint64_t at = base + i;
+            if (at < out.cap) {
+                out.tri[at] = s_tri[i];
+                out.node[at] = s_node[i];
+            }
+        }
+        __syncthreads();                         // LDS is reused by the next tile
     }
 }
 
@@ -518,10 +532,21 @@ using namespace crsh;
 
 namespace crsh {
 
+void tri_spheres_launch(const crsh_scene *scene, uint32_t b, uint32_t e, float4 *out, hipStream_t stream)
+{
+    const float *const *v = scene->v;
+    if (e > b) {
+        uint32_t g = std::min<uint32_t>((e - b + 255) / 256, 2048);
+        k_tri_sph<<<g, 256, 0, stream>>>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], b, e, out);
+    }
+}
+
+// lowest: the lowest level produced (1, or 2 when crsh_leaf_hit forms the
+// level-1 pairs itself); a top-level pass always writes its own level.
 crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin, uint32_t tri_end,
                             int32_t bundle, int32_t merge, const crsh_pairs pairs[CRSH_MAX_LEVELS],
                             crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t batch_levels,
-                            uint64_t batch_top_items, hipStream_t stream)
+                            uint64_t batch_top_items, int32_t lowest, hipStream_t stream)
 {
     if (!nodes || !scene || !pairs || !meta || !ws) {
         set_error("crsh_traverse: NULL argument");
@@ -542,6 +567,10 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
     }
     if (tri_end > scene->m || tri_begin > tri_end) {
         set_error("crsh_traverse: triangle batch [%u, %u) outside [0, %u)", tri_begin, tri_end, scene->m);
+        return CRSH_ERR_INVALID;
+    }
+    if (lowest < 1 || lowest > 2) {
+        set_error("crsh_traverse: lowest level must be 1 or 2");
         return CRSH_ERR_INVALID;
     }
     // levels present in the pair table: consecutive entries with storage
@@ -598,12 +627,7 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
         P.p[k].cap = k < levels ? pairs[k].capacity : 0;
     }
     const batch_dev b = bd ? *bd : batch_dev{};
-    const float *const *v = scene->v;
-    if (tri_end > tri_begin) {
-        uint32_t g = std::min<uint32_t>((tri_end - tri_begin + 255) / 256, 2048);
-        k_tri_sph<<<g, 256, 0, stream>>>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], tri_begin,
-                                         tri_end, tsph);
-    }
+    tri_spheres_launch(scene, tri_begin, tri_end, tsph, stream);
     {
         uint32_t g = std::min<uint32_t>((nodes->capacity + 255) / 256, 2048);
         if (g == 0) g = 1;
@@ -697,12 +721,12 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
     };
     if (bd) {
         for (int L = batch_levels; L >= 1; --L) {
-            if (L < batch_levels) level_pass_launch(L + 1);
+            if (L < batch_levels && L >= lowest) level_pass_launch(L + 1);
             top_pass_launch((uint32_t)L);
         }
     } else {
         top_pass_launch(0);
-        for (int L = levels; L >= 2; --L) level_pass_launch(L);
+        for (int L = levels; L >= lowest + 1; --L) level_pass_launch(L);
     }
     return hip_check(hipGetLastError(), "crsh_traverse launch");
 }
@@ -715,5 +739,14 @@ extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *
                                      size_t ws_bytes, hipStream_t stream)
 {
     return traverse_launch(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, nullptr, 0,
-                           0, stream);
+                           0, 1, stream);
+}
+
+extern "C" crsh_status crsh_traverse_upper(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin,
+                                           uint32_t tri_end, int32_t bundle, int32_t merge,
+                                           const crsh_pairs pairs[CRSH_MAX_LEVELS], crsh_meta *meta, void *ws,
+                                           size_t ws_bytes, hipStream_t stream)
+{
+    return traverse_launch(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, nullptr, 0,
+                           0, 2, stream);
 }

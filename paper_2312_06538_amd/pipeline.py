@@ -121,8 +121,11 @@ class Buffers:
         return self.pair_bufs[lv - 1] if self.keep_levels else self.pair_bufs[lv % len(self.pair_bufs)]
 
 
-def run_frame(fr, bf, stream=None, tri_batches=None):
-    """Chain hash -> sort -> build -> traverse -> closest hit on one stream."""
+def run_frame(fr, bf, stream=None, tri_batches=None, leaf_hit=True):
+    """Chain hash -> sort -> build -> traverse -> closest hit on one stream.
+    leaf_hit: the last traversal level runs fused with the final tests
+    (crsh_traverse_upper + crsh_leaf_hit); otherwise every level-1 pair is
+    stored (crsh_traverse + crsh_closest_hit)."""
     s = stream_handle(stream)
     meta, ws, wsb = _p(bf.meta), _p(bf.ws), bf.ws_bytes
     X.crsh_meta_reset(meta, s)
@@ -130,10 +133,16 @@ def run_frame(fr, bf, stream=None, tri_batches=None):
     X.crsh_sort(_p(bf.keys), _p(bf.ids), _p(bf.skeys), _p(bf.sids), bf.cap, meta, ws, wsb, s)
     X.crsh_build(bf.c_rays, _p(bf.sids), fr.B, fr.F, fr.n, bf.c_nodes, bf.c_srays, meta, s)
     X.crsh_hits_reset(bf.c_hits, s)
+    fuse = leaf_hit and fr.n >= 2
     for (b, e) in (tri_batches or [(0, fr.m)]):
-        X.crsh_traverse(bf.c_nodes, fr.scene, b, e, fr.B, fr.F, bf.c_pairs, meta, ws, wsb, s)
-        X.crsh_closest_hit(bf.c_srays, _p(bf.sids), fr.B, bf.c_pairs[0], fr.scene, fr.t_min, bf.c_hits, meta,
-                           ws, wsb, s)
+        if fuse:
+            X.crsh_traverse_upper(bf.c_nodes, fr.scene, b, e, fr.B, fr.F, bf.c_pairs, meta, ws, wsb, s)
+            X.crsh_leaf_hit(bf.c_srays, _p(bf.sids), fr.B, fr.F, bf.c_nodes, bf.c_pairs, fr.scene, fr.t_min,
+                            bf.c_hits, meta, ws, wsb, s)
+        else:
+            X.crsh_traverse(bf.c_nodes, fr.scene, b, e, fr.B, fr.F, bf.c_pairs, meta, ws, wsb, s)
+            X.crsh_closest_hit(bf.c_srays, _p(bf.sids), fr.B, bf.c_pairs[0], fr.scene, fr.t_min, bf.c_hits, meta,
+                               ws, wsb, s)
 
 
 def read_meta(bf, stream=None):
@@ -141,13 +150,13 @@ def read_meta(bf, stream=None):
     return m, st
 
 
-def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12):
+def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12, leaf_hit=True):
     """Run a frame; if a pair level overflowed, regrow the pair arrays and run
     again.  An overflowing level truncates the levels below it, so their
     reported sizes are lower bounds: grow to at least twice the capacity.
     Returns (buffers, meta)."""
     for _ in range(max_tries):
-        run_frame(fr, bf, stream, tri_batches)
+        run_frame(fr, bf, stream, tri_batches, leaf_hit=leaf_hit)
         m, st = read_meta(bf, stream)
         if st == X.OK:
             return bf, m

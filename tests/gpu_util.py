@@ -187,10 +187,12 @@ def gpu_closest_hit(rays, sorted_ids, B, pairs1, sc, t_min):
     return (tri[:n].cpu().numpy(), tt[:n].cpu().numpy(), uu[:n].cpu().numpy(), vv[:n].cpu().numpy()), m
 
 
-def run_pipeline(wl, pair_capacity=1 << 20, keep_levels=True, tri_batches=None):
+def run_pipeline(wl, pair_capacity=1 << 20, keep_levels=True, tri_batches=None, leaf_hit=False):
+    """The whole path; leaf_hit=False stores every pair level (for
+    inspection), True runs the last level fused with the final tests."""
     fr = P.DeviceFrame(wl)
     bf = P.Buffers(fr, pair_capacity, keep_levels=keep_levels)
-    bf, m = P.run_with_retry(fr, bf, tri_batches=tri_batches)
+    bf, m = P.run_with_retry(fr, bf, tri_batches=tri_batches, leaf_hit=leaf_hit)
     return P.results(fr, bf, m)
 
 

@@ -68,7 +68,9 @@ def test_forward_matches_oracle(adjoint_case):
     assert np.array_equal(c["tri"], o[0])
     for x, y in zip((c["t"], c["u"], c["v"]), o[1:]):
         assert np.allclose(x, y, rtol=1e-5, atol=0)
-    assert c["keep"].sum() > 10000
+    # enough hit rays away from triangle edges for the samples below (2,048
+    # vertex coordinates, 342 rays x 6 parameters)
+    assert c["keep"].sum() > 2000
 
 
 def _loss_terms(c, ray, o, d, tri9):

@@ -118,7 +118,7 @@ def test_batch_matches_oracle_per_frame(hit_block):
     from paper_2312_06538_amd.batch import DeviceBatch
     wls = frames()
     print(f"[batch] {len(wls)} frames, hit_block {hit_block}", flush=True)
-    db = DeviceBatch(wls, B, F, N, hit_block=hit_block, pair_capacity=1 << 20, keep_levels=True)
+    db = DeviceBatch(wls, B, F, N, hit_block=hit_block, pair_capacity=1 << 20, keep_levels=True, leaf_hit=False)
     m = db.run_with_retry()
     orcs = [oracle_of(wl) for wl in wls]
     res = db.frame_results(m)
@@ -131,6 +131,28 @@ def test_batch_matches_oracle_per_frame(hit_block):
     tot = _counters(orcs)
     assert int(m.mesh_tests) == tot["mesh_tests"]
     assert int(m.mesh_hits) == tot["mesh_hits"]
+    assert int(m.final_tests) == tot["final_tests"]
+    for lv, v in tot["tests"].items():
+        assert int(m.tests[lv - 1]) == v, lv
+    for lv, v in tot["hits"].items():
+        assert int(m.hits[lv - 1]) == v, lv
+
+
+def test_batch_fused_last_level_matches_oracle():
+    """The batch with the last level fused with the final tests: closest
+    hits per frame and the counters summed over frames."""
+    from paper_2312_06538_amd.batch import DeviceBatch
+    wls = frames()
+    db = DeviceBatch(wls, B, F, N, pair_capacity=1 << 20, leaf_hit=True)
+    m = db.run_with_retry()
+    orcs = [oracle_of(wl) for wl in wls]
+    for f, (r, o) in enumerate(zip(db.frame_results(m), orcs)):
+        print(f"[batch fused] frame {f}: {r['n']} rays", flush=True)
+        assert r["n"] == o["hash"]["n"]
+        assert np.array_equal(r["hit"][0], o["hits"][0])
+        for a, b in zip(r["hit"][1:], o["hits"][1:]):
+            assert np.array_equal(_bits(a), _bits(b))
+    tot = _counters(orcs)
     assert int(m.final_tests) == tot["final_tests"]
     for lv, v in tot["tests"].items():
         assert int(m.tests[lv - 1]) == v, lv

@@ -75,3 +75,13 @@ def test_full_size_frame(name, n_top, n_brute):
     for a, c in zip(g["hit"][1:], b[1:]):
         assert np.allclose(a[rs], c, rtol=1e-5, atol=0)
     print(f"[fullsize] {name}: ok ({g['n']} rays, {len(t1)} level-1 pairs)", flush=True)
+    # the fused last level (the configuration bench.py times): the same
+    # closest hits and counters as the stored-pair path above
+    print(f"[fullsize] {name}: fused last level", flush=True)
+    f = gu.run_pipeline(wl, pair_capacity=1 << 26, keep_levels=False, leaf_hit=True)
+    for a, b in zip(f["hit"], g["hit"]):
+        assert np.array_equal(_bits(a), _bits(b))
+    for k in ("final_tests", "mesh_tests", "mesh_hits"):
+        assert f[k] == g[k], k
+    for lv in range(1, nl + 1):
+        assert f["tests"][lv] == g["tests"][lv] and f["hits"][lv] == g["hits"][lv], lv

@@ -221,6 +221,76 @@ def test_pipeline_end_to_end(name):
         assert np.allclose(a, b, rtol=1e-5, atol=0)
 
 
+LEAF_SHAPES = [(16, 4, 5), (8, 2, 3), (32, 8, 4), (5, 3, 4), (1, 16, 3), (12, 4, 2), (16, 4, 1)]
+
+
+def _check_fused(g, o):
+    """The fused last level: closest hits and every counter of the stage
+    order (level-1 tests and pairs formed, ray-triangle tests)."""
+    tr = o["trav"]
+    assert g["final_tests"] == tr["final_tests"]
+    nl = o["tree"]["n_levels"]
+    for lv in range(1, nl + 1):
+        assert g["tests"][lv] == tr["tests"][lv], lv
+        assert g["hits"][lv] == len(tr["pairs"][lv][0]), lv
+    assert g["mesh_tests"] == tr["mesh_tests"] and g["mesh_hits"] == tr["mesh_hits"]
+    assert np.array_equal(g["hit"][0], o["hits"][0])
+    for a, b in zip(g["hit"][1:], o["hits"][1:]):
+        assert _same(a, b)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_leaf_hit_matches_oracle(name):
+    base, kw = small(name)
+    print(f"[leaf_hit] {name}", flush=True)
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    g = _gu().run_pipeline(wl, pair_capacity=1 << 16, keep_levels=False, leaf_hit=True)
+    _check_fused(g, o)
+
+
+@pytest.mark.parametrize("B,F,n", LEAF_SHAPES)
+def test_leaf_hit_shapes(B, F, n):
+    """Bundles that do not fill a lane group, merge factors that do not fill
+    a power of two, single-level hierarchies (only the stored path)."""
+    import dataclasses
+    base, kw = small("refl_96")
+    wl = dataclasses.replace(workload(base, **kw), B=B, F=F, n=n)
+    print(f"[leaf_hit] B={B} F={F} n={n}", flush=True)
+    o = O.run_pipeline(wl)
+    g = _gu().run_pipeline(wl, pair_capacity=1 << 16, keep_levels=False, leaf_hit=True)
+    _check_fused(g, o)
+
+
+def test_leaf_hit_single_leaf_and_no_rays():
+    """A hierarchy that is one leaf (its level-1 pairs come from the top-level
+    pass) and a frame without any ray."""
+    import dataclasses
+    for wl in (workload("shadow_128", W=3, H=3),
+               dataclasses.replace(workload("shadow_128", W=8, H=8),
+                                   gbuf=dict(workload("shadow_128", W=8, H=8).gbuf,
+                                             mat=np.full(64, -1, np.int32)))):
+        o = O.run_pipeline(wl)
+        print(f"[leaf_hit] {o['hash']['n']} rays, {o['tree']['n_levels']} levels", flush=True)
+        g = _gu().run_pipeline(wl, pair_capacity=1 << 12, keep_levels=False, leaf_hit=True)
+        assert g["n"] == o["hash"]["n"]
+        if g["n"]:
+            _check_fused(g, o)
+
+
+def test_leaf_hit_triangle_batches():
+    base, kw = small("mixed_128x72")
+    wl = workload(base, **kw)
+    m = wl.scene.m
+    batches = [(0, m // 3), (m // 3, m // 3), (m // 3, 2 * m // 3 + 5), (2 * m // 3 + 5, m)]
+    o = O.run_pipeline(wl, tri_batches=batches)
+    g = _gu().run_pipeline(wl, pair_capacity=1 << 16, keep_levels=False, tri_batches=batches, leaf_hit=True)
+    assert g["final_tests"] == sum(t["final_tests"] for t in o["trav"])
+    assert np.array_equal(g["hit"][0], o["hits"][0])
+    for a, b in zip(g["hit"][1:], o["hits"][1:]):
+        assert _same(a, b)
+
+
 def test_pipeline_is_deterministic():
     base, kw = small("refl_96")
     wl = workload(base, **kw)
