@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="refl_1024",
                     choices=["shadow_128", "refl_1024", "mixed_1080p", "adjoint_512", "batch_64"])
+    ap.add_argument("--variant", default="crsh", choices=["crsh", "unsorted"],
+                    help="unsorted: the comparison hierarchy without ray sorting, whole-mesh culling or a "
+                         "level cap, on the same inputs")
     ap.add_argument("--frames", type=int, default=64, help="batch_64: number of frames")
     ap.add_argument("--tune", action="store_true",
                     help="batch_64: tune (B, levels, hit_block) by timing the captured batch")
@@ -128,6 +131,9 @@ def main():
 
     t0 = time.perf_counter()
     wl = make_workload(args.workload, seed=args.seed)
+    if args.variant == "unsorted":
+        from workloads import unsorted_variant
+        wl = unsorted_variant(wl)
     print(f"[bench] workload {args.workload}: {wl.W}x{wl.H}, M={wl.scene.m}, built in "
           f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     fr = P.DeviceFrame(wl)
@@ -189,7 +195,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl.W}x{wl.H} shadow+reflection, "
                                f"{wl.scene.n_mesh} meshes, {wl.scene.m} triangles, B={wl.B} F={wl.F} n={wl.n}",
-                   "rays": n, "triangles": wl.scene.m, "seed": args.seed},
+                   "rays": n, "triangles": wl.scene.m, "seed": args.seed, "variant": args.variant},
         "tests": {"node_tests": node_tests, "final_ray_tri_tests": final, "total": node_tests + final,
                   "brute_force": brute, "frac_of_brute": round((node_tests + final) / brute, 5),
                   "mesh_tests": int(m.mesh_tests), "levels": nl},

@@ -63,6 +63,10 @@ typedef enum crsh_status {
 #define CRSH_RAY_SHADOW 1u
 #define CRSH_RAY_REFLECT 2u
 #define CRSH_RAY_REFRACT 4u
+/* Comparison mode (the ray-space hierarchy without ray sorting, Sec. 2):
+ * keys keep only the type and light bits (31-28), so crsh_sort only groups
+ * the rays per type and light and keeps their generation order. */
+#define CRSH_KEY_TYPE_ONLY 0x100u
 /* material bits of crsh_raygen.mat_flags[] */
 #define CRSH_MAT_REFLECTIVE 1u
 #define CRSH_MAT_REFRACTIVE 2u
@@ -203,6 +207,16 @@ crsh_status crsh_hash(const crsh_gbuf *gbuf, const crsh_raygen *rg, crsh_rays *o
 crsh_status crsh_sort(const uint32_t *keys_in, const uint32_t *ids_in,
                       uint32_t *keys_out, uint32_t *ids_out, uint32_t capacity,
                       crsh_meta *meta, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Stage 2 in the paper's layout (Sec. 3.3.3-3.3.5): compression of the
+ * pairs into chunks of equal consecutive keys (head flags + scan), a radix
+ * sort of the chunks by key, decompression (scan of the sorted chunk sizes,
+ * then every output position takes its chunk's element).  Same contract and
+ * result as crsh_sort; it moves one sort entry per chunk, which pays when
+ * runs of equal keys are long.  ws: crsh_workspace_size() bytes. */
+crsh_status crsh_sort_chunked(const uint32_t *keys_in, const uint32_t *ids_in,
+                              uint32_t *keys_out, uint32_t *ids_out, uint32_t capacity,
+                              crsh_meta *meta, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Stage 3 -- hierarchy creation (Sec. 3.3.6, Eq. 1-8).  Level 1 node j bounds
  * the rays at sorted positions [j*bundle, (j+1)*bundle); level k node j bounds

@@ -72,7 +72,8 @@ typedef struct {
     const uint32_t *mat_flags;   /* bit0 reflective, bit1 refractive */
     const float *mat_ior;
     int32_t n_mats;
-    uint32_t ray_types;          /* bit0 shadow, bit1 reflection, bit2 refraction */
+    uint32_t ray_types;          /* bit0 shadow, bit1 reflection, bit2 refraction;
+                                    bit8: keys of type and light only (unsorted comparison) */
     float eps_off, eps_shadow;
     float lo[3], inv_ext[3];     /* origin quantisation box for keys */
 } orc_raygen;
@@ -248,6 +249,10 @@ int64_t orc_hash(const orc_gbuf *gb, const orc_raygen *g, orc_rays *out,
                 }
             }
             if (!ok) continue;
+            /* Comparison hierarchy without ray sorting (the RSH of Sec. 2):
+             * the key keeps only the ray type and light, so the sort groups
+             * rays per type and light and keeps their generation order. */
+            if (g->ray_types & 0x100u) key &= 0xF0000000u;
             if (n >= capacity) return -1;
             out->ox[n] = O.x; out->oy[n] = O.y; out->oz[n] = O.z;
             out->dx[n] = D.x; out->dy[n] = D.y; out->dz[n] = D.z;

@@ -323,6 +323,24 @@ def mt64(o, d, tri9):
     return bool(ok), out
 
 
+def adjoint64(o, d, tri9, g):
+    """Gradient of g . (t, u, v) of the float64 Moller-Trumbore solution
+    (Sec. 3.3.8) with respect to v0, v1, v2, O and D, the hit triangle held
+    fixed.  Plain definition: (t, u, v) solves [D | -e1 | -e2] (t, u, v)^T =
+    v0 - O with e1 = v1 - v0, e2 = v2 - v0; by the implicit function theorem
+    the gradient is lam^T times the derivative of the residual, where
+    [D | -e1 | -e2]^T lam = g.  Returns (dv0, dv1, dv2, dO, dD, cond) in
+    float64; cond is the 2-norm condition number of the matrix."""
+    o, d, tri9, g = (np.asarray(x, np.float64) for x in (o, d, tri9, g))
+    v0, v1, v2 = tri9[0:3], tri9[3:6], tri9[6:9]
+    e1, e2 = v1 - v0, v2 - v0
+    M = np.stack([d, -e1, -e2], axis=1)
+    t, u, v = np.linalg.solve(M, v0 - o)
+    lam = np.linalg.solve(M.T, g)
+    # residual r = O + t D - (1-u-v) v0 - u v1 - v v2 = 0
+    return ((1.0 - u - v) * lam, u * lam, v * lam, -lam, -t * lam, float(np.linalg.cond(M)))
+
+
 def shadow_key(light, d):
     d = _f32(d)
     return int(lib().orc_shadow_key(light, _p(d, f32p)))

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrsh.so")
-SOURCES = ["api.hip", "hash.hip", "sort.hip", "build.hip", "traverse.hip", "hit.hip", "adjoint.hip", "batch.hip", "leafhit.hip"]
+SOURCES = ["api.hip", "hash.hip", "sort.hip", "build.hip", "traverse.hip", "hit.hip", "adjoint.hip", "batch.hip", "leafhit.hip", "sortchunk.hip"]
 ARCH = os.environ.get("CRSH_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -19,6 +19,7 @@ MAX_FRAMES = 256
 OK, ERR_INVALID, ERR_CAPACITY, ERR_HIP = 0, 1, 2, 3
 OVERFLOW_RAYS, OVERFLOW_NODES, OVERFLOW_PAIRS, OVERFLOW_ITEMS = 1, 2, 4, 8
 RAY_SHADOW, RAY_REFLECT, RAY_REFRACT = 1, 2, 4
+KEY_TYPE_ONLY = 0x100
 
 vp = C.c_void_p
 
@@ -131,6 +132,8 @@ def lib():
                                 C.c_size_t, vp]
         L.crsh_sort.restype = st
         L.crsh_sort.argtypes = [vp, vp, vp, vp, C.c_uint32, vp, vp, C.c_size_t, vp]
+        L.crsh_sort_chunked.restype = st
+        L.crsh_sort_chunked.argtypes = [vp, vp, vp, vp, C.c_uint32, vp, vp, C.c_size_t, vp]
         L.crsh_build.restype = st
         L.crsh_build.argtypes = [C.POINTER(Rays), vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Nodes),
                                  C.POINTER(Rays), vp, vp]
@@ -204,6 +207,11 @@ def crsh_hash(gbuf, raygen, rays, keys, ids, meta, ws, ws_bytes, stream):
 
 def crsh_sort(keys_in, ids_in, keys_out, ids_out, capacity, meta, ws, ws_bytes, stream):
     return _check(lib().crsh_sort(keys_in, ids_in, keys_out, ids_out, capacity, meta, ws, ws_bytes, stream))
+
+
+def crsh_sort_chunked(keys_in, ids_in, keys_out, ids_out, capacity, meta, ws, ws_bytes, stream):
+    return _check(lib().crsh_sort_chunked(keys_in, ids_in, keys_out, ids_out, capacity, meta, ws, ws_bytes,
+                                          stream))
 
 
 def crsh_build(rays, sorted_ids, bundle, merge, levels, nodes, sorted_rays, meta, stream):

@@ -107,7 +107,7 @@ extern "C" const char *crsh_last_error(void) { return g_err; }
 extern "C" size_t crsh_workspace_size(uint32_t max_rays, uint32_t max_tris, uint32_t max_meshes,
                                       uint32_t max_nodes, uint64_t max_pairs)
 {
-    size_t a = sort_ws_bytes(max_rays);
+    size_t a = std::max(sort_ws_bytes(max_rays), sort_chunked_ws_bytes(max_rays));
     size_t b = hash_ws_bytes(max_rays);
     size_t c = trav_ws_bytes(max_tris, max_nodes, (uint64_t)max_nodes * max_meshes, max_pairs);
     size_t d = std::max(hit_ws_bytes(max_tris), leaf_hit_ws_bytes(max_tris, max_nodes, max_pairs));

@@ -239,6 +239,7 @@ void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const
                       hipStream_t stream);
 void tri_spheres_launch(const crsh_scene *scene, uint32_t b, uint32_t e, float4 *out, hipStream_t stream);
 size_t leaf_hit_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t level2_cap);
+size_t sort_chunked_ws_bytes(uint32_t cap);
 
 // launch helpers
 void set_error(const char *fmt, ...);

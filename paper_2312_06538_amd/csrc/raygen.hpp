@@ -107,8 +107,21 @@ __device__ __forceinline__ uint32_t key_bounce(uint32_t type, f3 o, f3 d, const 
 
 // Generates slot s of a pixel (shadow rays of lights 0..L-1, reflection,
 // refraction); returns false for a hole.
+__device__ __forceinline__ bool make_slot_keyed(int s, f3 P, f3 N, uint32_t flags, float ior, const raygen_dev &g,
+                                                ray_t &r);
+
+// With CRSH_KEY_TYPE_ONLY the key keeps only the ray type and light: the
+// comparison hierarchy without ray sorting (Sec. 2).
 __device__ __forceinline__ bool make_slot(int s, f3 P, f3 N, uint32_t flags, float ior, const raygen_dev &g,
                                           ray_t &r)
+{
+    const bool ok = make_slot_keyed(s, P, N, flags, ior, g, r);
+    if (g.types & CRSH_KEY_TYPE_ONLY) r.key &= 0xF0000000u;
+    return ok;
+}
+
+__device__ __forceinline__ bool make_slot_keyed(int s, f3 P, f3 N, uint32_t flags, float ior, const raygen_dev &g,
+                                                ray_t &r)
 {
     if (s < g.n_lights) {
         if (!(g.types & CRSH_RAY_SHADOW)) return false;

@@ -76,7 +76,7 @@ def gpu_hash(wl):
     return {"rays": out, "keys": P.u32(keys[:n]), "ids": P.u32(ids[:n]), "n": n, "meta": m, "status": st}
 
 
-def gpu_sort(keys, ids, capacity=None):
+def gpu_sort(keys, ids, capacity=None, chunked=False):
     n = len(keys)
     cap = max(capacity or n, 1)
     kin, vin = dev_u32(keys, cap), dev_u32(ids, cap)
@@ -85,8 +85,9 @@ def gpu_sort(keys, ids, capacity=None):
     meta = new_meta(n_rays=n)
     wsb = X.crsh_workspace_size(cap, 1, 1, 1, 1)
     ws = ws_tensor(wsb)
-    X.crsh_sort(kin.data_ptr(), vin.data_ptr(), kout.data_ptr(), vout.data_ptr(), cap, meta.data_ptr(),
-                ws.data_ptr(), wsb, s())
+    fn = X.crsh_sort_chunked if chunked else X.crsh_sort
+    fn(kin.data_ptr(), vin.data_ptr(), kout.data_ptr(), vout.data_ptr(), cap, meta.data_ptr(), ws.data_ptr(), wsb,
+       s())
     read_meta(meta)
     return P.u32(kout[:n]), P.u32(vout[:n])
 

@@ -96,6 +96,29 @@ def test_sort_of_workload_keys(name):
     assert _same(gk, o["sorted_keys"]) and _same(gi, o["sorted_ids"])
 
 
+@pytest.mark.parametrize("n,span", [(0, 7), (1, 7), (4096, 3), (4097, 1 << 20), (50000, 1 << 32),
+                                    (300001, 1 << 16)])
+def test_sort_chunked_bit_exact(n, span):
+    """Compression -> chunk sort -> decompression gives the stable order."""
+    print(f"[sort chunked] n={n} span={span}", flush=True)
+    rng = np.random.default_rng(n + span % 997)
+    keys = rng.integers(0, span, size=n, dtype=np.uint64).astype(np.uint32)
+    # long runs of equal keys, as coherent rays give
+    keys = np.repeat(keys, rng.integers(1, 40, size=n))[:n] if n else keys
+    ids = rng.permutation(n).astype(np.uint32)
+    ok, oi = O.sort_rays(keys, ids)
+    gk, gi = _gu().gpu_sort(keys, ids, capacity=n + 777, chunked=True)
+    assert _same(gk, ok) and _same(gi, oi)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_sort_chunked_of_workload_keys(name):
+    base, kw = small(name)
+    o = oracle_run(base, **kw)
+    gk, gi = _gu().gpu_sort(o["hash"]["keys"], o["hash"]["ids"], chunked=True)
+    assert _same(gk, o["sorted_keys"]) and _same(gi, o["sorted_ids"])
+
+
 def _check_tree(g, o):
     assert g["n_levels"] == o["n_levels"]
     assert _same(g["level_cnt"], o["level_cnt"])
@@ -219,6 +242,24 @@ def test_pipeline_end_to_end(name):
     assert np.array_equal(g["hit"][0], o["hits"][0])
     for a, b in zip(g["hit"][1:], o["hits"][1:]):
         assert np.allclose(a, b, rtol=1e-5, atol=0)
+
+
+def test_unsorted_comparison_mode_bit_exact():
+    """The comparison configuration (keys of type and light only, one
+    always-passing mesh, hierarchy to a single top node): every product."""
+    from workloads import unsorted_variant
+    base, kw = small("mixed_128x72")
+    wl = unsorted_variant(workload(base, **kw))
+    o = O.run_pipeline(wl)
+    print(f"[unsorted] {o['hash']['n']} rays, {o['tree']['n_levels']} levels", flush=True)
+    g = _gu().run_pipeline(wl, pair_capacity=1 << 20)
+    assert _same(g["keys"], o["hash"]["keys"]) and _same(g["sorted_ids"], o["sorted_ids"])
+    _check_tree(g, o["tree"])
+    for lv, (t, n) in o["trav"]["pairs"].items():
+        assert _same(g["pairs"][lv][0], t) and _same(g["pairs"][lv][1], n), lv
+    assert np.array_equal(g["hit"][0], o["hits"][0])
+    f = _gu().run_pipeline(wl, pair_capacity=1 << 20, keep_levels=False, leaf_hit=True)
+    _check_fused(f, o)
 
 
 LEAF_SHAPES = [(16, 4, 5), (8, 2, 3), (32, 8, 4), (5, 3, 4), (1, 16, 3), (12, 4, 2), (16, 4, 1)]

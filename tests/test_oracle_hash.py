@@ -235,3 +235,20 @@ def test_workload_ray_counts(name):
     if name == "mixed_128x72":
         assert h["n"] == 3 * hit.sum()                 # 2 shadow + reflection or refraction
     assert np.all(np.diff(h["rays"]["pix"].astype(np.int64)) >= 0)
+
+
+def test_unsorted_comparison_keys_keep_type_and_light():
+    """Comparison mode (the hierarchy without ray sorting, Sec. 2): the same
+    rays, keys reduced to the type and light bits, so the sort only groups
+    the rays per type and light and keeps their generation order."""
+    from workloads import unsorted_variant
+    wl = workload("mixed_1080p", W=48, H=32, n_meshes=24)
+    a = O.hash_rays(wl)
+    b = O.hash_rays(unsorted_variant(wl))
+    assert b["n"] == a["n"]
+    for k in O.RAY_FIELDS:
+        assert np.array_equal(a["rays"][k], b["rays"][k])
+    assert np.array_equal(b["keys"], a["keys"] & np.uint32(0xF0000000))
+    ks, ids = O.sort_rays(b["keys"], b["ids"])
+    assert np.array_equal(ids, np.argsort(a["keys"] >> np.uint32(28), kind="stable").astype(np.uint32))
+    assert len(np.unique(b["keys"] >> np.uint32(28))) >= 3     # two shadow lights and a bounce type

@@ -177,3 +177,43 @@ def test_mt64_agrees_with_float32_test(rng):
         n += 1
         assert np.allclose(tuv, t64, rtol=1e-4, atol=1e-4)
     assert n > 100
+
+
+def test_adjoint64_matches_finite_differences(rng):
+    """The float64 adjoint (implicit-function form) against central
+    differences of the float64 Moller-Trumbore solve, on random rays through
+    random triangles, and its closed form for an axis-aligned triangle."""
+    h = 1e-6
+    done = 0
+    while done < 40:
+        tri = rng.normal(size=9)
+        bary = rng.dirichlet([2.0, 2.0, 2.0])
+        hit = bary[0] * tri[0:3] + bary[1] * tri[3:6] + bary[2] * tri[6:9]
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        o = hit - rng.uniform(0.5, 3.0) * d
+        g = rng.normal(size=3)
+        dv0, dv1, dv2, do, dd, cond = O.adjoint64(o, d, tri, g)
+        if cond > 50:
+            continue
+        f = lambda o_, d_, t_: float(np.dot(g, O.mt64(o_, d_, t_)[1]))
+        for vec, grad, which in ((o, do, "o"), (d, dd, "d")):
+            for k in range(3):
+                p, m = vec.copy(), vec.copy()
+                p[k] += h
+                m[k] -= h
+                fd = (f(p, d, tri) - f(m, d, tri)) / (2 * h) if which == "o" else \
+                    (f(o, p, tri) - f(o, m, tri)) / (2 * h)
+                assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(fd)), (which, k, fd, grad[k])
+        for j, grad in enumerate((dv0, dv1, dv2)):
+            for k in range(3):
+                p, m = tri.copy(), tri.copy()
+                p[3 * j + k] += h
+                m[3 * j + k] -= h
+                fd = (f(o, d, p) - f(o, d, m)) / (2 * h)
+                assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(fd)), (j, k, fd, grad[k])
+        done += 1
+    # axis-aligned triangle in z = 0, ray straight down from (0.25, 0.5, 1)
+    dv0, dv1, dv2, do, dd, _ = O.adjoint64([0.25, 0.5, 1.0], [0, 0, -1.0], [0, 0, 0, 1, 0, 0, 0, 1, 0], [1, 0, 0])
+    assert np.allclose(do, [0, 0, 1]) and np.allclose(dd, [0, 0, 1])
+    assert np.allclose([dv0[2], dv1[2], dv2[2]], [-0.25, -0.25, -0.5])

@@ -13,7 +13,7 @@ available; these procedural scenes replace them.  A workload bundles:
 
 Input generation only: no step of the secondary-ray path lives here.
 """
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -21,6 +21,7 @@ from . import meshes as _m
 from .caster import cast_primary
 
 SHADOW, REFLECT, REFRACT = 1, 2, 4
+KEY_TYPE_ONLY = 0x100           # keys of ray type and light only (comparison mode)
 MAT_REFLECT, MAT_REFRACT = 1, 2
 
 
@@ -297,6 +298,19 @@ def _finish(name, seed, sc, W, H, eye, look, vfov, lights, B, F, n, types):
     return Workload(name=name, seed=seed, scene=sc, W=W, H=H, eye=eye, look=look,
                     vfov=vfov, lights=lights, gbuf=g, B=B, F=F, n=n, ray_types=types,
                     lo=lo, inv_ext=inv)
+
+
+def unsorted_variant(wl, levels=16):
+    """The comparison configuration of the same inputs: the ray-space
+    hierarchy without ray sorting and without whole-mesh culling (Sec. 2) --
+    keys of ray type and light only, every triangle in one mesh whose sphere
+    always passes, and the hierarchy built to its single top node (up to
+    `levels` levels)."""
+    sc = wl.scene
+    one = Scene(tris=sc.tris, mesh_first=np.zeros(1, np.uint32), mesh_count=np.array([sc.m], np.uint32),
+                mesh_sphere=np.array([[0.0, 0.0, 0.0, 1e30]], np.float32), mesh_mat=np.zeros(1, np.int32),
+                mat_flags=sc.mat_flags, mat_ior=sc.mat_ior, verts=sc.verts, faces=sc.faces)
+    return replace(wl, name=wl.name + "_unsorted", scene=one, ray_types=wl.ray_types | KEY_TYPE_ONLY, n=levels)
 
 
 MAKERS = {"shadow_128": make_shadow_128, "refl_1024": make_refl_1024, "mixed_1080p": make_mixed_1080p, "adjoint_512": make_adjoint_512}
