@@ -167,12 +167,12 @@ def test_batch_shapes_and_single_frame():
     for (b, f, n) in ((8, 2, 3), (32, 8, 7)):
         wls = frames(B=b, F=f, n=n)[:4]
         print(f"[batch] shape B={b} F={f} n={n}", flush=True)
-        db = DeviceBatch(wls, b, f, n, pair_capacity=1 << 20)
+        db = DeviceBatch(wls, b, f, n, pair_capacity=1 << 20, leaf_hit=False)
         m = db.run_with_retry()
         for r, wl in zip(db.frame_results(m), wls):
             check_frame(r, wl, oracle_of(wl), all_levels=False)
     wl = frames()[5]
-    db = DeviceBatch([wl], B, F, N, pair_capacity=1 << 20)
+    db = DeviceBatch([wl], B, F, N, pair_capacity=1 << 20, leaf_hit=False)
     m = db.run_with_retry()
     check_frame(db.frame_results(m)[0], wl, oracle_of(wl), all_levels=False)
 
@@ -180,7 +180,7 @@ def test_batch_shapes_and_single_frame():
 def test_batch_pair_overflow_regrows():
     from paper_2312_06538_amd.batch import DeviceBatch
     wls = frames()[:3]
-    db = DeviceBatch(wls, B, F, N, pair_capacity=64)
+    db = DeviceBatch(wls, B, F, N, pair_capacity=64, leaf_hit=False)
     m = db.run_with_retry()
     assert db.pair_capacity > 64
     for r, wl in zip(db.frame_results(m), wls):
