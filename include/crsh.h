@@ -289,6 +289,24 @@ crsh_status crsh_leaf_hit(const crsh_rays *sorted, const uint32_t *sorted_ids,
                           float t_min, crsh_hits *hits, crsh_meta *meta,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The next bounce (Sec. 3.3.8: the algorithm goes on with a new set of
+ * secondary rays from the sorting step).  Every reflection or refraction
+ * parent ray (key type 01 or 10) with a closest hit spawns, in parent-id
+ * order, the secondary rays of its hit point exactly as crsh_hash does for a
+ * primary hit: P = O + t D, the unit geometric normal of the hit triangle
+ * (e1 x e2 normalised) turned against D, the triangle's material
+ * tri_mat[tri] (index into rg->mat_flags / mat_ior), and D itself instead of
+ * the view direction (rg->eye is not used).  Shadow parents and misses spawn
+ * nothing; children keep their parent's pix.  Parents are by ray id with
+ * their keys and hits (crsh_closest_hit's tri and t); their count is
+ * parent_meta->n_rays.  Writes out / keys / ids and meta->n_rays like
+ * crsh_hash (meta cleared by the caller, distinct from parent_meta; out and
+ * keys distinct from the parents').  ws: crsh_workspace_size() bytes. */
+crsh_status crsh_bounce(const crsh_rays *parents, const uint32_t *parent_keys, const crsh_hits *hits,
+                        const crsh_meta *parent_meta, const crsh_scene *scene, const int32_t *tri_mat,
+                        const crsh_raygen *rg, crsh_rays *out, uint32_t *keys, uint32_t *ids,
+                        crsh_meta *meta, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Stage 1 for rays the caller already has (e.g. a differentiable renderer):
  * keys[i] = the hash of ray i under the same layout as crsh_hash -- `type`
  * 0 shadow (bits 29-28 = `light`), 1 reflection, 2 refraction (origin cell

@@ -97,11 +97,17 @@ static int shadow_ray(v3 P, v3 L, float eps_shadow, v3 *O, v3 *D, float *tmax)
     return 1;
 }
 
-/* Mirror reflection of the view direction about the (camera-facing) normal. */
-static void reflect_ray(v3 P, v3 N, v3 E, float eps_off, v3 *O, v3 *D, float *tmax)
+/* Unit view direction from the eye to a primary hit. */
+static v3 view_dir(v3 P, v3 E)
 {
     v3 v0 = vsub(P, E);
-    v3 v = vdiv(v0, vnorm(v0));
+    return vdiv(v0, vnorm(v0));
+}
+
+/* Mirror reflection of the unit incoming direction v about the normal N
+ * (which faces against v). */
+static void reflect_ray(v3 P, v3 N, v3 v, float eps_off, v3 *O, v3 *D, float *tmax)
+{
     float k = vdot(v, N);
     v3 r = vsub(v, vmul(N, 2.0f * k));
     *D = vdiv(r, vnorm(r));
@@ -109,12 +115,10 @@ static void reflect_ray(v3 P, v3 N, v3 E, float eps_off, v3 *O, v3 *D, float *tm
     *tmax = FLT_MAX;
 }
 
-/* Snell refraction into the surface, relative index 1/ior; returns 0 on
- * total internal reflection. */
-static int refract_ray(v3 P, v3 N, v3 E, float ior, float eps_off, v3 *O, v3 *D, float *tmax)
+/* Snell refraction of the unit incoming direction v into the surface,
+ * relative index 1/ior; returns 0 on total internal reflection. */
+static int refract_ray(v3 P, v3 N, v3 v, float ior, float eps_off, v3 *O, v3 *D, float *tmax)
 {
-    v3 v0 = vsub(P, E);
-    v3 v = vdiv(v0, vnorm(v0));
     float k = vdot(v, N);
     float eta = 1.0f / ior;
     float ci = -k;
@@ -209,6 +213,54 @@ static uint32_t bounce_key(uint32_t type, v3 O, v3 D, const orc_raygen *g)
     return (type << 30) | (morton3(cx, cy, cz, 6) << 12) | morton2(u, v, 6);
 }
 
+/* The secondary rays of one surface point P with normal N (facing against
+ * the unit incoming direction v) and material flags / index of refraction,
+ * in slot order: shadow rays of lights 0..L-1, then reflection, then
+ * refraction.  Appends the real ones (holes trimmed, Sec. 3.3.2) at n with
+ * source index `pix`; returns the new count, or -1 past `capacity`. */
+static int64_t emit_slots(v3 P, v3 N, v3 v, uint32_t flags, float ior, uint32_t pix, const orc_raygen *g,
+                          orc_rays *out, uint32_t *keys, uint32_t *ids, uint32_t n, uint32_t capacity)
+{
+    for (int s = 0; s < g->n_lights + 2; ++s) {
+        v3 O, D;
+        float tmax;
+        uint32_t key;
+        int ok = 0;
+        if (s < g->n_lights) {
+            if (g->ray_types & 1u) {
+                v3 L = mk(g->lights[s][0], g->lights[s][1], g->lights[s][2]);
+                ok = shadow_ray(P, L, g->eps_shadow, &O, &D, &tmax);
+                if (ok) key = shadow_key(s, D);
+            }
+        } else if (s == g->n_lights) {
+            if ((g->ray_types & 2u) && (flags & 1u)) {
+                reflect_ray(P, N, v, g->eps_off, &O, &D, &tmax);
+                ok = 1;
+                key = bounce_key(1u, O, D, g);
+            }
+        } else {
+            if ((g->ray_types & 4u) && (flags & 2u)) {
+                ok = refract_ray(P, N, v, ior, g->eps_off, &O, &D, &tmax);
+                if (ok) key = bounce_key(2u, O, D, g);
+            }
+        }
+        if (!ok) continue;
+        /* Comparison hierarchy without ray sorting (the RSH of Sec. 2):
+         * the key keeps only the ray type and light, so the sort groups
+         * rays per type and light and keeps their generation order. */
+        if (g->ray_types & 0x100u) key &= 0xF0000000u;
+        if (n >= capacity) return -1;
+        out->ox[n] = O.x; out->oy[n] = O.y; out->oz[n] = O.z;
+        out->dx[n] = D.x; out->dy[n] = D.y; out->dz[n] = D.z;
+        out->tmax[n] = tmax;
+        out->pix[n] = pix;
+        keys[n] = key;
+        ids[n] = n;
+        ++n;
+    }
+    return n;
+}
+
 /* Generates every secondary ray of every pixel, in pixel order and, within a
  * pixel, shadow rays of lights 0..L-1, then reflection, then refraction.
  * Holes are trimmed away (Sec. 3.3.2): a ray's id is the number of real rays
@@ -216,7 +268,7 @@ static uint32_t bounce_key(uint32_t type, v3 O, v3 D, const orc_raygen *g)
 int64_t orc_hash(const orc_gbuf *gb, const orc_raygen *g, orc_rays *out,
                  uint32_t *keys, uint32_t *ids, uint32_t capacity)
 {
-    uint32_t n = 0;
+    int64_t n = 0;
     v3 E = mk(g->eye[0], g->eye[1], g->eye[2]);
     int64_t npx = (int64_t)gb->w * gb->h;
     for (int64_t p = 0; p < npx; ++p) {
@@ -225,43 +277,45 @@ int64_t orc_hash(const orc_gbuf *gb, const orc_raygen *g, orc_rays *out,
         v3 P = mk(gb->px[p], gb->py[p], gb->pz[p]);
         v3 N = mk(gb->nx[p], gb->ny[p], gb->nz[p]);
         uint32_t flags = (m < g->n_mats) ? g->mat_flags[m] : 0u;
-        for (int s = 0; s < g->n_lights + 2; ++s) {
-            v3 O, D;
-            float tmax;
-            uint32_t key;
-            int ok = 0;
-            if (s < g->n_lights) {
-                if (g->ray_types & 1u) {
-                    v3 L = mk(g->lights[s][0], g->lights[s][1], g->lights[s][2]);
-                    ok = shadow_ray(P, L, g->eps_shadow, &O, &D, &tmax);
-                    if (ok) key = shadow_key(s, D);
-                }
-            } else if (s == g->n_lights) {
-                if ((g->ray_types & 2u) && (flags & 1u)) {
-                    reflect_ray(P, N, E, g->eps_off, &O, &D, &tmax);
-                    ok = 1;
-                    key = bounce_key(1u, O, D, g);
-                }
-            } else {
-                if ((g->ray_types & 4u) && (flags & 2u)) {
-                    ok = refract_ray(P, N, E, g->mat_ior[m], g->eps_off, &O, &D, &tmax);
-                    if (ok) key = bounce_key(2u, O, D, g);
-                }
-            }
-            if (!ok) continue;
-            /* Comparison hierarchy without ray sorting (the RSH of Sec. 2):
-             * the key keeps only the ray type and light, so the sort groups
-             * rays per type and light and keeps their generation order. */
-            if (g->ray_types & 0x100u) key &= 0xF0000000u;
-            if (n >= capacity) return -1;
-            out->ox[n] = O.x; out->oy[n] = O.y; out->oz[n] = O.z;
-            out->dx[n] = D.x; out->dy[n] = D.y; out->dz[n] = D.z;
-            out->tmax[n] = tmax;
-            out->pix[n] = (uint32_t)p;
-            keys[n] = key;
-            ids[n] = n;
-            ++n;
-        }
+        float ior = (m < g->n_mats) ? g->mat_ior[m] : 1.0f;
+        n = emit_slots(P, N, view_dir(P, E), flags, ior, (uint32_t)p, g, out, keys, ids, (uint32_t)n, capacity);
+        if (n < 0) return -1;
+    }
+    return n;
+}
+
+/* The next bounce (Sec. 3.3.8: the algorithm continues with a new set of
+ * secondary rays from the sorting step).  Every reflection or refraction
+ * ray (key type 01 or 10) with a closest hit spawns the secondary rays of
+ * its hit point, in parent-id order: P = O + t D, the unit geometric normal
+ * of the hit triangle (e1 x e2 normalised) turned against D, the material
+ * of the triangle (tri_mat), and D itself as the incoming direction.  Shadow
+ * rays and misses spawn nothing.  Children keep their parent's source pixel.
+ * Returns the new count, or -1 past `capacity`. */
+int64_t orc_bounce(const orc_rays *par, const uint32_t *par_keys, uint32_t n_par, const int32_t *hit_tri,
+                   const float *hit_t, const float *const v[9], uint32_t m, const int32_t *tri_mat,
+                   const orc_raygen *g, orc_rays *out, uint32_t *keys, uint32_t *ids, uint32_t capacity)
+{
+    int64_t n = 0;
+    for (uint32_t i = 0; i < n_par; ++i) {
+        int32_t tri = hit_tri[i];
+        if (tri < 0 || (uint32_t)tri >= m || (par_keys[i] >> 30) == 0u) continue;
+        v3 O = mk(par->ox[i], par->oy[i], par->oz[i]);
+        v3 D = mk(par->dx[i], par->dy[i], par->dz[i]);
+        v3 P = vadd(O, vmul(D, hit_t[i]));
+        v3 a = mk(v[0][tri], v[1][tri], v[2][tri]);
+        v3 b = mk(v[3][tri], v[4][tri], v[5][tri]);
+        v3 c = mk(v[6][tri], v[7][tri], v[8][tri]);
+        v3 nn = vcross(vsub(b, a), vsub(c, a));
+        float len = vnorm(nn);
+        if (!(len > 0.0f)) continue;
+        v3 N = vdiv(nn, len);
+        if (vdot(N, D) > 0.0f) N = vneg(N);
+        int32_t mt = tri_mat[tri];
+        uint32_t flags = (mt >= 0 && mt < g->n_mats) ? g->mat_flags[mt] : 0u;
+        float ior = (mt >= 0 && mt < g->n_mats) ? g->mat_ior[mt] : 1.0f;
+        n = emit_slots(P, N, D, flags, ior, par->pix[i], g, out, keys, ids, (uint32_t)n, capacity);
+        if (n < 0) return -1;
     }
     return n;
 }

@@ -66,6 +66,9 @@ def lib():
         L.orc_hash.restype = C.c_int64
         L.orc_hash.argtypes = [C.POINTER(Gbuf), C.POINTER(Raygen), C.POINTER(Rays), u32p, u32p, C.c_uint32]
         L.orc_sort.argtypes = [u32p, u32p, C.c_uint32, u32p, u32p]
+        L.orc_bounce.restype = C.c_int64
+        L.orc_bounce.argtypes = [C.POINTER(Rays), u32p, C.c_uint32, i32p, f32p, f32p * 9, C.c_uint32, i32p,
+                                 C.POINTER(Raygen), C.POINTER(Rays), u32p, u32p, C.c_uint32]
         L.orc_level_counts.restype = C.c_int
         L.orc_level_counts.argtypes = [C.c_uint32, C.c_int, C.c_int, C.c_int, u32p]
         L.orc_build.restype = C.c_int
@@ -278,6 +281,55 @@ def closest_hit(rays, sorted_ids, B, pairs1, scene, t_min, init=None):
     lib().orc_closest_hit(C.byref(rs), _p(sorted_ids, u32p), n, B, _p(ptri, u32p), _p(pnode, u32p),
                           len(ptri), arr, t_min, _p(tri, i32p), _p(t, f32p), _p(u, f32p), _p(v, f32p))
     return tri, t, u, v
+
+
+def bounce(rays, keys, hits, wl):
+    """The next generation of secondary rays from the closest hits of the
+    reflection / refraction rays (Sec. 3.3.8), with the ray-generation
+    parameters of the workload (lights, materials, key box).  Returns the
+    same dict as hash_rays."""
+    rays = {k: _f32(rays[k]) for k in RAY_FIELDS} | {"pix": _u32(rays["pix"])}
+    keys = _u32(keys)
+    n_par = len(keys)
+    tri = np.ascontiguousarray(hits[0], np.int32)
+    t = _f32(hits[1])
+    tri_mat = np.ascontiguousarray(wl.scene.tri_mat(), np.int32)
+    g = make_raygen(wl)
+    cap = max(n_par * (len(wl.lights) + 2), 1)
+    r = {k: np.zeros(cap, np.float32) for k in RAY_FIELDS}
+    r["pix"] = np.zeros(cap, np.uint32)
+    out_keys = np.zeros(cap, np.uint32)
+    ids = np.zeros(cap, np.uint32)
+    keep, arr = _tri_arr(wl.scene)
+    ps, rs = _rays_struct(rays), _rays_struct(r)
+    n = lib().orc_bounce(C.byref(ps), _p(keys, u32p), n_par, _p(tri, i32p), _p(t, f32p), arr, wl.scene.m,
+                         _p(tri_mat, i32p), C.byref(g), C.byref(rs), _p(out_keys, u32p), _p(ids, u32p), cap)
+    assert n >= 0
+    return {"rays": {k: v[:n].copy() for k, v in r.items()}, "keys": out_keys[:n].copy(), "ids": ids[:n].copy(),
+            "n": int(n)}
+
+
+def run_generations(wl, depth, leaf_top_subset=None):
+    """`depth` generations of the whole path: the first from the primary-hit
+    buffer, each next one from the closest hits of the previous (bounce).
+    Returns the list of per-generation dicts (as run_pipeline, plus the
+    generation's rays under "hash")."""
+    out = []
+    h = hash_rays(wl)
+    for gen in range(depth):
+        ks, ids = sort_rays(h["keys"], h["ids"])
+        tree = build_tree(h["rays"], ids, wl.B, wl.F, wl.n)
+        tr = traverse(tree, wl.scene)
+        if tree["n_levels"]:
+            hits = closest_hit(h["rays"], ids, wl.B, tr["pairs"][1], wl.scene, wl.t_min)
+        else:
+            n = h["n"]
+            hits = (np.full(n, -1, np.int32), np.zeros(n, np.float32), np.zeros(n, np.float32),
+                    np.zeros(n, np.float32))
+        out.append({"hash": h, "sorted_keys": ks, "sorted_ids": ids, "tree": tree, "trav": tr, "hits": hits})
+        if gen + 1 < depth:
+            h = bounce(h["rays"], h["keys"], hits, wl)
+    return out
 
 
 def brute_closest_hit(rays, ray_list, scene, t_min):

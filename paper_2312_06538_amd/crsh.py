@@ -130,6 +130,9 @@ def lib():
         L.crsh_hash.restype = st
         L.crsh_hash.argtypes = [C.POINTER(Gbuf), C.POINTER(Raygen), C.POINTER(Rays), vp, vp, vp, vp,
                                 C.c_size_t, vp]
+        L.crsh_bounce.restype = st
+        L.crsh_bounce.argtypes = [C.POINTER(Rays), vp, C.POINTER(Hits), vp, C.POINTER(Scene), vp, C.POINTER(Raygen),
+                                  C.POINTER(Rays), vp, vp, vp, vp, C.c_size_t, vp]
         L.crsh_sort.restype = st
         L.crsh_sort.argtypes = [vp, vp, vp, vp, C.c_uint32, vp, vp, C.c_size_t, vp]
         L.crsh_sort_chunked.restype = st
@@ -203,6 +206,12 @@ def crsh_read_meta(meta, stream, allow_capacity=True):
 def crsh_hash(gbuf, raygen, rays, keys, ids, meta, ws, ws_bytes, stream):
     return _check(lib().crsh_hash(C.byref(gbuf), C.byref(raygen), C.byref(rays), keys, ids, meta, ws, ws_bytes,
                                   stream))
+
+
+def crsh_bounce(parents, parent_keys, hits, parent_meta, scene, tri_mat, raygen, out, keys, ids, meta, ws, ws_bytes,
+                stream):
+    return _check(lib().crsh_bounce(C.byref(parents), parent_keys, C.byref(hits), parent_meta, C.byref(scene),
+                                    tri_mat, C.byref(raygen), C.byref(out), keys, ids, meta, ws, ws_bytes, stream))
 
 
 def crsh_sort(keys_in, ids_in, keys_out, ids_out, capacity, meta, ws, ws_bytes, stream):

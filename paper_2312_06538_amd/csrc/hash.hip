@@ -41,34 +41,47 @@ __device__ __forceinline__ raygen_dev frame_raygen(const batch_dev &b, uint32_t 
     return g;
 }
 
-template <bool BATCH>
-__device__ __forceinline__ raygen_dev pixel_raygen(const raygen_dev &g, const batch_dev &b, uint32_t p,
-                                                   uint32_t npix, uint32_t &f)
+// Where a thread's surface point comes from.
+enum : int { SRC_GBUF = 0, SRC_BATCH = 1, SRC_BOUNCE = 2 };
+
+struct src_dev {
+    gbuf_dev gb;
+    batch_dev bd;
+    bounce_dev bo;
+    uint32_t n;        // threads to cover (pixels, or parent-ray capacity)
+};
+
+template <int SRC>
+__device__ __forceinline__ pixel_t load_point(const src_dev &src, const raygen_dev &g0, uint32_t p, raygen_dev &g,
+                                              uint32_t &f)
 {
     f = 0;
-    if constexpr (BATCH) {
-        if (p < npix) {
-            f = frame_of_pixel(b, p);
-            return frame_raygen(b, f);
+    g = g0;
+    if constexpr (SRC == SRC_BATCH) {
+        if (p < src.gb.npix) {
+            f = frame_of_pixel(src.bd, p);
+            g = frame_raygen(src.bd, f);
         }
     }
-    return g;
+    if constexpr (SRC == SRC_BOUNCE)
+        return load_bounce(src.bo, g, p);
+    else
+        return load_pixel(src.gb, g, p);
 }
 
-template <bool BATCH>
-__global__ __launch_bounds__(HASH_BLOCK) void k_hash_count(gbuf_dev gb, raygen_dev g0, batch_dev bd,
-                                                           uint32_t *block_sums)
+template <int SRC>
+__global__ __launch_bounds__(HASH_BLOCK) void k_hash_count(src_dev src, raygen_dev g0, uint32_t *block_sums)
 {
     __shared__ uint32_t red[HASH_BLOCK / WAVE];
     uint32_t p = blockIdx.x * HASH_BLOCK + threadIdx.x;
     uint32_t f;
-    const raygen_dev g = pixel_raygen<BATCH>(g0, bd, p, gb.npix, f);
-    pixel_t px = load_pixel(gb, g, p);
+    raygen_dev g;
+    const pixel_t px = load_point<SRC>(src, g0, p, g, f);
     uint32_t c = 0;
     if (px.hit) {
         for (int s = 0; s < g.n_lights + 2; ++s) {
             ray_t r;
-            c += make_slot(s, px.P, px.N, px.flags, px.ior, g, r) ? 1u : 0u;
+            c += make_slot(s, px.P, px.N, px.v, px.flags, px.ior, g, r) ? 1u : 0u;
         }
     }
     c = wave_sum(c);
@@ -118,32 +131,31 @@ struct rays_dev {
     uint32_t cap;
 };
 
-template <bool BATCH>
-__global__ __launch_bounds__(HASH_BLOCK) void k_hash_emit(gbuf_dev gb, raygen_dev g0, batch_dev bd,
-                                                          const uint32_t *block_off, rays_dev out, uint32_t *keys,
-                                                          uint32_t *ids)
+template <int SRC>
+__global__ __launch_bounds__(HASH_BLOCK) void k_hash_emit(src_dev src, raygen_dev g0, const uint32_t *block_off,
+                                                          rays_dev out, uint32_t *keys, uint32_t *ids)
 {
     __shared__ uint32_t scratch[HASH_BLOCK / WAVE];
     uint32_t p = blockIdx.x * HASH_BLOCK + threadIdx.x;
     uint32_t f;
-    const raygen_dev g = pixel_raygen<BATCH>(g0, bd, p, gb.npix, f);
-    pixel_t px = load_pixel(gb, g, p);
+    raygen_dev g;
+    const pixel_t px = load_point<SRC>(src, g0, p, g, f);
     uint32_t c = 0;
     if (px.hit) {
         for (int s = 0; s < g.n_lights + 2; ++s) {
             ray_t r;
-            c += make_slot(s, px.P, px.N, px.flags, px.ior, g, r) ? 1u : 0u;
+            c += make_slot(s, px.P, px.N, px.v, px.flags, px.ior, g, r) ? 1u : 0u;
         }
     }
     uint32_t total;
     uint32_t id = block_off[blockIdx.x] + block_excl_scan<uint32_t, HASH_BLOCK / WAVE>(c, scratch, total);
-    if constexpr (BATCH) {
-        if (p < gb.npix && p == bd.frames[f].pix_begin) bd.fm[f].ray_begin = id;
+    if constexpr (SRC == SRC_BATCH) {
+        if (p < src.gb.npix && p == src.bd.frames[f].pix_begin) src.bd.fm[f].ray_begin = id;
     }
     if (!px.hit || c == 0) return;
     for (int s = 0; s < g.n_lights + 2; ++s) {
         ray_t r;
-        if (!make_slot(s, px.P, px.N, px.flags, px.ior, g, r)) continue;
+        if (!make_slot(s, px.P, px.N, px.v, px.flags, px.ior, g, r)) continue;
         if (id < out.cap) {
             out.ox[id] = r.o.x;
             out.oy[id] = r.o.y;
@@ -152,13 +164,77 @@ __global__ __launch_bounds__(HASH_BLOCK) void k_hash_emit(gbuf_dev gb, raygen_de
             out.dy[id] = r.d.y;
             out.dz[id] = r.d.z;
             out.tmax[id] = r.tmax;
-            out.pix[id] = p;
+            out.pix[id] = px.pix;
             keys[id] = r.key;
             ids[id] = id;
-            if constexpr (BATCH) out.frame[id] = f;
+            if constexpr (SRC == SRC_BATCH) out.frame[id] = f;
         }
         ++id;
     }
+}
+
+static raygen_dev to_device(const crsh_raygen *rg)
+{
+    raygen_dev g{};
+    if (!rg) return g;
+    g.n_lights = rg->n_lights;
+    for (int i = 0; i < CRSH_MAX_LIGHTS; ++i) {
+        g.lx[i] = rg->lights[i][0];
+        g.ly[i] = rg->lights[i][1];
+        g.lz[i] = rg->lights[i][2];
+    }
+    g.ex = rg->eye[0];
+    g.ey = rg->eye[1];
+    g.ez = rg->eye[2];
+    g.mat_flags = rg->mat_flags;
+    g.mat_ior = rg->mat_ior;
+    g.n_mats = rg->n_mats;
+    g.types = rg->ray_types;
+    g.eps_off = rg->eps_off;
+    g.eps_shadow = rg->eps_shadow;
+    for (int i = 0; i < 3; ++i) {
+        g.lo[i] = rg->lo[i];
+        g.inv[i] = rg->inv_ext[i];
+    }
+    return g;
+}
+
+static crsh_status check_raygen(const crsh_raygen *rg, const char *who)
+{
+    if (rg->n_lights < 0 || rg->n_lights > CRSH_MAX_LIGHTS || rg->n_mats < 0 ||
+        (rg->n_mats > 0 && (!rg->mat_flags || !rg->mat_ior))) {
+        set_error("%s: bad ray-generation parameters", who);
+        return CRSH_ERR_INVALID;
+    }
+    return CRSH_OK;
+}
+
+static crsh_status check_out(const crsh_rays *out, const char *who)
+{
+    if (!out->ox || !out->oy || !out->oz || !out->dx || !out->dy || !out->dz || !out->tmax || !out->pix) {
+        set_error("%s: incomplete ray arrays", who);
+        return CRSH_ERR_INVALID;
+    }
+    return CRSH_OK;
+}
+
+template <int SRC>
+static crsh_status hash_kernels(const src_dev &src, const raygen_dev &g, crsh_rays *out, uint32_t *keys,
+                                uint32_t *ids, uint32_t *ray_frame, crsh_meta *meta, void *ws, hipStream_t stream)
+{
+    const uint32_t nb = (uint32_t)(((uint64_t)src.n + HASH_BLOCK - 1) / HASH_BLOCK);
+    uint32_t *blocks = (uint32_t *)ws;
+    if (nb) {
+        prof_scope ps("k_hash_count", stream);
+        k_hash_count<SRC><<<nb, HASH_BLOCK, 0, stream>>>(src, g, blocks);
+    }
+    k_hash_scan<<<1, 1024, 0, stream>>>(blocks, nb, meta, out->capacity);
+    rays_dev rd{out->ox, out->oy, out->oz, out->dx, out->dy, out->dz, out->tmax, out->pix, ray_frame, out->capacity};
+    if (nb) {
+        prof_scope ps("k_hash_emit", stream);
+        k_hash_emit<SRC><<<nb, HASH_BLOCK, 0, stream>>>(src, g, blocks, rd, keys, ids);
+    }
+    return hip_check(hipGetLastError(), "crsh_hash launch");
 }
 
 }  // namespace crsh
@@ -180,15 +256,8 @@ crsh_status hash_launch(const crsh_gbuf *gbuf, const crsh_raygen *rg, const batc
         set_error("crsh_hash: empty or incomplete primary-hit buffer");
         return CRSH_ERR_INVALID;
     }
-    if (rg && (rg->n_lights < 0 || rg->n_lights > CRSH_MAX_LIGHTS || rg->n_mats < 0 ||
-               (rg->n_mats > 0 && (!rg->mat_flags || !rg->mat_ior)))) {
-        set_error("crsh_hash: bad ray-generation parameters");
-        return CRSH_ERR_INVALID;
-    }
-    if (!out->ox || !out->oy || !out->oz || !out->dx || !out->dy || !out->dz || !out->tmax || !out->pix) {
-        set_error("crsh_hash: incomplete ray arrays");
-        return CRSH_ERR_INVALID;
-    }
+    if (rg && check_raygen(rg, "crsh_hash") != CRSH_OK) return CRSH_ERR_INVALID;
+    if (check_out(out, "crsh_hash") != CRSH_OK) return CRSH_ERR_INVALID;
     uint64_t npix = (uint64_t)gbuf->w * (uint64_t)gbuf->h;
     if (npix >= (1ull << 31)) {
         set_error("crsh_hash: too many pixels");
@@ -198,49 +267,13 @@ crsh_status hash_launch(const crsh_gbuf *gbuf, const crsh_raygen *rg, const batc
         set_error("crsh_hash: workspace too small (%zu < %zu)", ws_bytes, hash_ws_bytes(npix));
         return CRSH_ERR_INVALID;
     }
-    gbuf_dev gb{gbuf->px, gbuf->py, gbuf->pz, gbuf->nx, gbuf->ny, gbuf->nz, gbuf->mat, (uint32_t)npix};
-    raygen_dev g{};
-    if (rg) {
-        g.n_lights = rg->n_lights;
-        for (int i = 0; i < CRSH_MAX_LIGHTS; ++i) {
-            g.lx[i] = rg->lights[i][0];
-            g.ly[i] = rg->lights[i][1];
-            g.lz[i] = rg->lights[i][2];
-        }
-        g.ex = rg->eye[0];
-        g.ey = rg->eye[1];
-        g.ez = rg->eye[2];
-        g.mat_flags = rg->mat_flags;
-        g.mat_ior = rg->mat_ior;
-        g.n_mats = rg->n_mats;
-        g.types = rg->ray_types;
-        g.eps_off = rg->eps_off;
-        g.eps_shadow = rg->eps_shadow;
-        for (int i = 0; i < 3; ++i) {
-            g.lo[i] = rg->lo[i];
-            g.inv[i] = rg->inv_ext[i];
-        }
-    }
-    const batch_dev b = bd ? *bd : batch_dev{};
-    uint32_t nb = (uint32_t)((npix + HASH_BLOCK - 1) / HASH_BLOCK);
-    uint32_t *blocks = (uint32_t *)ws;
-    {
-        prof_scope ps("k_hash_count", stream);
-        if (bd)
-            k_hash_count<true><<<nb, HASH_BLOCK, 0, stream>>>(gb, g, b, blocks);
-        else
-            k_hash_count<false><<<nb, HASH_BLOCK, 0, stream>>>(gb, g, b, blocks);
-    }
-    k_hash_scan<<<1, 1024, 0, stream>>>(blocks, nb, meta, out->capacity);
-    rays_dev rd{out->ox, out->oy, out->oz, out->dx, out->dy, out->dz, out->tmax, out->pix, ray_frame, out->capacity};
-    {
-        prof_scope ps("k_hash_emit", stream);
-        if (bd)
-            k_hash_emit<true><<<nb, HASH_BLOCK, 0, stream>>>(gb, g, b, blocks, rd, keys, ids);
-        else
-            k_hash_emit<false><<<nb, HASH_BLOCK, 0, stream>>>(gb, g, b, blocks, rd, keys, ids);
-    }
-    return hip_check(hipGetLastError(), "crsh_hash launch");
+    src_dev src{};
+    src.gb = gbuf_dev{gbuf->px, gbuf->py, gbuf->pz, gbuf->nx, gbuf->ny, gbuf->nz, gbuf->mat, (uint32_t)npix};
+    src.n = (uint32_t)npix;
+    if (bd) src.bd = *bd;
+    const raygen_dev g = to_device(rg);
+    return bd ? hash_kernels<SRC_BATCH>(src, g, out, keys, ids, ray_frame, meta, ws, stream)
+              : hash_kernels<SRC_GBUF>(src, g, out, keys, ids, nullptr, meta, ws, stream);
 }
 
 }  // namespace crsh
@@ -304,4 +337,55 @@ extern "C" crsh_status crsh_hash_rays(const crsh_rays *rays, uint32_t n, uint32_
         k_hash_rays<<<grid, 256, 0, stream>>>(r, n, type, light, g, keys, ids);
     }
     return hip_check(hipGetLastError(), "crsh_hash_rays launch");
+}
+
+extern "C" crsh_status crsh_bounce(const crsh_rays *parents, const uint32_t *parent_keys, const crsh_hits *hits,
+                                   const crsh_meta *parent_meta, const crsh_scene *scene, const int32_t *tri_mat,
+                                   const crsh_raygen *rg, crsh_rays *out, uint32_t *keys, uint32_t *ids,
+                                   crsh_meta *meta, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!parents || !parent_keys || !hits || !parent_meta || !scene || !tri_mat || !rg || !out || !keys || !ids ||
+        !meta || !ws) {
+        set_error("crsh_bounce: NULL argument");
+        return CRSH_ERR_INVALID;
+    }
+    if (!parents->ox || !parents->oy || !parents->oz || !parents->dx || !parents->dy || !parents->dz ||
+        !hits->tri || !hits->t || hits->capacity < parents->capacity) {
+        set_error("crsh_bounce: incomplete parent rays or hits");
+        return CRSH_ERR_INVALID;
+    }
+    for (int k = 0; k < 9; ++k)
+        if (!scene->v[k] && scene->m) {
+            set_error("crsh_bounce: missing vertex array");
+            return CRSH_ERR_INVALID;
+        }
+    if (check_raygen(rg, "crsh_bounce") != CRSH_OK || check_out(out, "crsh_bounce") != CRSH_OK)
+        return CRSH_ERR_INVALID;
+    if (ws_bytes < hash_ws_bytes(parents->capacity)) {
+        set_error("crsh_bounce: workspace too small (%zu < %zu)", ws_bytes, hash_ws_bytes(parents->capacity));
+        return CRSH_ERR_INVALID;
+    }
+    if (out->ox == parents->ox || keys == parent_keys || meta == parent_meta) {
+        set_error("crsh_bounce: the new generation must not overwrite its parents");
+        return CRSH_ERR_INVALID;
+    }
+    src_dev src{};
+    bounce_dev &b = src.bo;
+    b.ox = parents->ox;
+    b.oy = parents->oy;
+    b.oz = parents->oz;
+    b.dx = parents->dx;
+    b.dy = parents->dy;
+    b.dz = parents->dz;
+    b.pix = parents->pix;
+    b.keys = parent_keys;
+    b.tri = hits->tri;
+    b.t = hits->t;
+    for (int k = 0; k < 9; ++k) b.v[k] = scene->v[k];
+    b.tri_mat = tri_mat;
+    b.parent_meta = parent_meta;
+    b.cap = parents->capacity;
+    b.m = scene->m;
+    src.n = parents->capacity;
+    return hash_kernels<SRC_BOUNCE>(src, to_device(rg), out, keys, ids, nullptr, meta, ws, stream);
 }

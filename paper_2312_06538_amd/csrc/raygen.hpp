@@ -105,67 +105,63 @@ __device__ __forceinline__ uint32_t key_bounce(uint32_t type, f3 o, f3 d, const 
     return (type << 30) | (cell << 12) | spread2(u) | (spread2(v) << 1);
 }
 
-// Generates slot s of a pixel (shadow rays of lights 0..L-1, reflection,
-// refraction); returns false for a hole.
-__device__ __forceinline__ bool make_slot_keyed(int s, f3 P, f3 N, uint32_t flags, float ior, const raygen_dev &g,
-                                                ray_t &r);
-
-// With CRSH_KEY_TYPE_ONLY the key keeps only the ray type and light: the
-// comparison hierarchy without ray sorting (Sec. 2).
-__device__ __forceinline__ bool make_slot(int s, f3 P, f3 N, uint32_t flags, float ior, const raygen_dev &g,
+// Slot s of a surface point P with normal N facing against the unit incoming
+// direction v (shadow rays of lights 0..L-1, reflection, refraction);
+// returns false for a hole.  With CRSH_KEY_TYPE_ONLY the key keeps only the
+// ray type and light: the comparison hierarchy without ray sorting (Sec. 2).
+__device__ __forceinline__ bool make_slot(int s, f3 P, f3 N, f3 v, uint32_t flags, float ior, const raygen_dev &g,
                                           ray_t &r)
 {
-    const bool ok = make_slot_keyed(s, P, N, flags, ior, g, r);
-    if (g.types & CRSH_KEY_TYPE_ONLY) r.key &= 0xF0000000u;
+    bool ok = false;
+    if (s < g.n_lights) {
+        if (g.types & CRSH_RAY_SHADOW) {
+            f3 L = mk(g.lx[s], g.ly[s], g.lz[s]);
+            f3 d0 = P - L;
+            float l = len(d0);
+            if (l > g.eps_shadow) {
+                r.o = L;                  // origin moved to the light
+                r.d = d0 / l;
+                r.tmax = l - g.eps_shadow;
+                r.key = key_shadow((uint32_t)s, r.d);
+                ok = true;
+            }
+        }
+    } else if (s == g.n_lights) {
+        if ((g.types & CRSH_RAY_REFLECT) && (flags & CRSH_MAT_REFLECTIVE)) {
+            float k = dot(v, N);
+            f3 rr = v - N * (2.0f * k);
+            r.d = rr / len(rr);
+            r.o = P + N * g.eps_off;
+            r.tmax = FLT_MAX;
+            r.key = key_bounce(1u, r.o, r.d, g);
+            ok = true;
+        }
+    } else if ((g.types & CRSH_RAY_REFRACT) && (flags & CRSH_MAT_REFRACTIVE)) {
+        float k = dot(v, N);
+        float eta = 1.0f / ior;
+        float ci = -k;
+        float k2 = 1.0f - (eta * eta) * (1.0f - ci * ci);
+        if (k2 >= 0.0f) {                 // otherwise total internal reflection
+            float b = eta * ci - sqrtf(k2);
+            f3 t = v * eta + N * b;
+            r.d = t / len(t);
+            r.o = P - N * g.eps_off;
+            r.tmax = FLT_MAX;
+            r.key = key_bounce(2u, r.o, r.d, g);
+            ok = true;
+        }
+    }
+    if (ok && (g.types & CRSH_KEY_TYPE_ONLY)) r.key &= 0xF0000000u;
     return ok;
 }
 
-__device__ __forceinline__ bool make_slot_keyed(int s, f3 P, f3 N, uint32_t flags, float ior, const raygen_dev &g,
-                                                ray_t &r)
-{
-    if (s < g.n_lights) {
-        if (!(g.types & CRSH_RAY_SHADOW)) return false;
-        f3 L = mk(g.lx[s], g.ly[s], g.lz[s]);
-        f3 d0 = P - L;
-        float l = len(d0);
-        if (!(l > g.eps_shadow)) return false;
-        r.o = L;                  // origin moved to the light
-        r.d = d0 / l;
-        r.tmax = l - g.eps_shadow;
-        r.key = key_shadow((uint32_t)s, r.d);
-        return true;
-    }
-    f3 E = mk(g.ex, g.ey, g.ez);
-    f3 v0 = P - E;
-    f3 v = v0 / len(v0);
-    float k = dot(v, N);
-    if (s == g.n_lights) {
-        if (!(g.types & CRSH_RAY_REFLECT) || !(flags & CRSH_MAT_REFLECTIVE)) return false;
-        f3 rr = v - N * (2.0f * k);
-        r.d = rr / len(rr);
-        r.o = P + N * g.eps_off;
-        r.tmax = FLT_MAX;
-        r.key = key_bounce(1u, r.o, r.d, g);
-        return true;
-    }
-    if (!(g.types & CRSH_RAY_REFRACT) || !(flags & CRSH_MAT_REFRACTIVE)) return false;
-    float eta = 1.0f / ior;
-    float ci = -k;
-    float k2 = 1.0f - (eta * eta) * (1.0f - ci * ci);
-    if (k2 < 0.0f) return false;    // total internal reflection
-    float b = eta * ci - sqrtf(k2);
-    f3 t = v * eta + N * b;
-    r.d = t / len(t);
-    r.o = P - N * g.eps_off;
-    r.tmax = FLT_MAX;
-    r.key = key_bounce(2u, r.o, r.d, g);
-    return true;
-}
-
+// A surface point that emits secondary rays: a primary hit (pixel) or the
+// closest hit of a previous bounce ray.
 struct pixel_t {
-    f3 P, N;
+    f3 P, N, v;       // point, normal facing against v, unit incoming direction
     uint32_t flags;
     float ior;
+    uint32_t pix;     // source pixel of the rays
     bool hit;
 };
 
@@ -179,10 +175,53 @@ __device__ __forceinline__ pixel_t load_pixel(const gbuf_dev &gb, const raygen_d
     px.hit = true;
     px.P = mk(gb.px[p], gb.py[p], gb.pz[p]);
     px.N = mk(gb.nx[p], gb.ny[p], gb.nz[p]);
+    const f3 v0 = px.P - mk(g.ex, g.ey, g.ez);
+    px.v = v0 / len(v0);
     px.flags = m < g.n_mats ? g.mat_flags[m] : 0u;
     px.ior = m < g.n_mats ? g.mat_ior[m] : 1.0f;
+    px.pix = p;
     return px;
 }
 
+// Closest hits of a previous generation (Sec. 3.3.8): reflection and
+// refraction rays with a hit spawn the secondary rays of their hit point.
+struct bounce_dev {
+    const float *ox, *oy, *oz, *dx, *dy, *dz;
+    const uint32_t *pix, *keys;
+    const int32_t *tri;
+    const float *t;
+    const float *v[9];
+    const int32_t *tri_mat;
+    const crsh_meta *parent_meta;
+    uint32_t cap, m;
+};
+
+__device__ __forceinline__ pixel_t load_bounce(const bounce_dev &b, const raygen_dev &g, uint32_t i)
+{
+    pixel_t px;
+    px.hit = false;
+    if (i >= min(b.parent_meta->n_rays, b.cap)) return px;
+    const int32_t tri = b.tri[i];
+    if (tri < 0 || (uint32_t)tri >= b.m || (b.keys[i] >> 30) == 0u) return px;
+    const f3 O = mk(b.ox[i], b.oy[i], b.oz[i]);
+    const f3 D = mk(b.dx[i], b.dy[i], b.dz[i]);
+    const f3 a = mk(b.v[0][tri], b.v[1][tri], b.v[2][tri]);
+    const f3 bb = mk(b.v[3][tri], b.v[4][tri], b.v[5][tri]);
+    const f3 c = mk(b.v[6][tri], b.v[7][tri], b.v[8][tri]);
+    const f3 nn = cross(bb - a, c - a);
+    const float l = len(nn);
+    if (!(l > 0.0f)) return px;
+    f3 N = nn / l;
+    if (dot(N, D) > 0.0f) N = -N;
+    px.hit = true;
+    px.P = O + D * b.t[i];
+    px.N = N;
+    px.v = D;
+    const int32_t mt = b.tri_mat[tri];
+    px.flags = (mt >= 0 && mt < g.n_mats) ? g.mat_flags[mt] : 0u;
+    px.ior = (mt >= 0 && mt < g.n_mats) ? g.mat_ior[mt] : 1.0f;
+    px.pix = b.pix ? b.pix[i] : i;
+    return px;
+}
 
 }  // namespace crsh

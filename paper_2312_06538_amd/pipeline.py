@@ -59,6 +59,7 @@ class DeviceFrame:
         self.mesh_first = t(sc.mesh_first.view(np.int32), I32)
         self.mesh_count = t(sc.mesh_count.view(np.int32), I32)
         self.msph = t(sc.mesh_sphere.reshape(-1), F32)
+        self.tri_mat = t(np.ascontiguousarray(sc.tri_mat(), np.int32), I32)
         self.mat_flags = t(sc.mat_flags.view(np.int32), I32)
         self.mat_ior = t(sc.mat_ior, F32)
         self.m, self.n_mesh = sc.m, sc.n_mesh
@@ -84,9 +85,9 @@ class Buffers:
     """Every device array of one frame.  keep_levels=True keeps all pair
     levels (for inspection); otherwise two arrays alternate between levels."""
 
-    def __init__(self, fr, pair_capacity, keep_levels=False, device="cuda"):
+    def __init__(self, fr, pair_capacity, keep_levels=False, device="cuda", ray_capacity=None):
         dev = torch.device(device)
-        cap = fr.max_rays
+        cap = int(ray_capacity or fr.max_rays)
         self.cap = cap
         e = lambda n, dt: torch.empty(max(int(n), 1), dtype=dt, device=dev)
         self.rays = {k: e(cap, F32) for k in RAY_KEYS}
@@ -104,6 +105,7 @@ class Buffers:
         self.tkey = e(cap, I64)
         self.hit_tri, self.hit_t, self.hit_u, self.hit_v = e(cap, I32), e(cap, F32), e(cap, F32), e(cap, F32)
         self.meta = torch.zeros(C_META_BYTES, dtype=U8, device=dev)
+        self.ray_capacity = cap
         self.ws_bytes = X.crsh_workspace_size(cap, fr.m, fr.n_mesh, self.node_cap, self.pair_capacity)
         self.ws = e(self.ws_bytes, U8)
         r = self.rays
@@ -121,15 +123,21 @@ class Buffers:
         return self.pair_bufs[lv - 1] if self.keep_levels else self.pair_bufs[lv % len(self.pair_bufs)]
 
 
-def run_frame(fr, bf, stream=None, tri_batches=None, leaf_hit=True):
+def run_frame(fr, bf, stream=None, tri_batches=None, leaf_hit=True, parent=None):
     """Chain hash -> sort -> build -> traverse -> closest hit on one stream.
     leaf_hit: the last traversal level runs fused with the final tests
     (crsh_traverse_upper + crsh_leaf_hit); otherwise every level-1 pair is
-    stored (crsh_traverse + crsh_closest_hit)."""
+    stored (crsh_traverse + crsh_closest_hit).  parent: the Buffers of the
+    previous generation; the rays then come from its closest hits
+    (crsh_bounce) instead of the primary-hit buffer."""
     s = stream_handle(stream)
     meta, ws, wsb = _p(bf.meta), _p(bf.ws), bf.ws_bytes
     X.crsh_meta_reset(meta, s)
-    X.crsh_hash(fr.gbuf, fr.raygen, bf.c_rays, _p(bf.keys), _p(bf.ids), meta, ws, wsb, s)
+    if parent is None:
+        X.crsh_hash(fr.gbuf, fr.raygen, bf.c_rays, _p(bf.keys), _p(bf.ids), meta, ws, wsb, s)
+    else:
+        X.crsh_bounce(parent.c_rays, _p(parent.keys), parent.c_hits, _p(parent.meta), fr.scene, _p(fr.tri_mat),
+                      fr.raygen, bf.c_rays, _p(bf.keys), _p(bf.ids), meta, ws, wsb, s)
     X.crsh_sort(_p(bf.keys), _p(bf.ids), _p(bf.skeys), _p(bf.sids), bf.cap, meta, ws, wsb, s)
     X.crsh_build(bf.c_rays, _p(bf.sids), fr.B, fr.F, fr.n, bf.c_nodes, bf.c_srays, meta, s)
     X.crsh_hits_reset(bf.c_hits, s)
@@ -150,22 +158,41 @@ def read_meta(bf, stream=None):
     return m, st
 
 
-def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12, leaf_hit=True):
+def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12, leaf_hit=True, parent=None):
     """Run a frame; if a pair level overflowed, regrow the pair arrays and run
-    again.  An overflowing level truncates the levels below it, so their
+    again (the ray arrays likewise for a bounce generation that outgrew
+    them).  An overflowing level truncates the levels below it, so their
     reported sizes are lower bounds: grow to at least twice the capacity.
     Returns (buffers, meta)."""
     for _ in range(max_tries):
-        run_frame(fr, bf, stream, tri_batches, leaf_hit=leaf_hit)
+        run_frame(fr, bf, stream, tri_batches, leaf_hit=leaf_hit, parent=parent)
         m, st = read_meta(bf, stream)
         if st == X.OK:
             return bf, m
-        if m.status & ~X.OVERFLOW_PAIRS:
+        if m.status & ~(X.OVERFLOW_PAIRS | X.OVERFLOW_RAYS):
             raise X.CrshError(st, X.last_error())
         need = max(int(m.pairs[k]) for k in range(X.MAX_LEVELS))
-        cap = max(int(need * grow) + 1024, 2 * bf.pair_capacity)
-        bf = Buffers(fr, cap, keep_levels=bf.keep_levels)
-    raise X.CrshError(X.ERR_CAPACITY, "pair capacity still too small after regrowing")
+        cap = max(int(need * grow) + 1024, 2 * bf.pair_capacity) if m.status & X.OVERFLOW_PAIRS else \
+            bf.pair_capacity
+        rays = max(int(m.rays_required), bf.ray_capacity)
+        bf = Buffers(fr, cap, keep_levels=bf.keep_levels, ray_capacity=rays)
+    raise X.CrshError(X.ERR_CAPACITY, "capacity still too small after regrowing")
+
+
+def run_generations(fr, depth, pair_capacity=1 << 22, keep_levels=False, leaf_hit=True, stream=None):
+    """`depth` generations of the path (Sec. 3.3.8): the first from the
+    primary-hit buffer, each next one from the closest hits of the previous
+    (crsh_bounce), every one through sort, build, traversal and final tests.
+    Returns [(buffers, meta)] per generation."""
+    out = []
+    parent = None
+    for _ in range(depth):
+        bf = Buffers(fr, pair_capacity, keep_levels=keep_levels,
+                     ray_capacity=None if parent is None else parent[0].ray_capacity)
+        bf, m = run_with_retry(fr, bf, stream, leaf_hit=leaf_hit, parent=None if parent is None else parent[0])
+        out.append((bf, m))
+        parent = (bf, m)
+    return out
 
 
 def results(fr, bf, m):

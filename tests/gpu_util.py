@@ -199,3 +199,8 @@ def run_pipeline(wl, pair_capacity=1 << 20, keep_levels=True, tri_batches=None, 
 
 def pair_keys(t, n):
     return (np.asarray(n, np.uint64) << np.uint64(32)) | np.asarray(t, np.uint64)
+
+
+def run_generations(wl, depth, pair_capacity=1 << 20, keep_levels=True, leaf_hit=False):
+    fr = P.DeviceFrame(wl)
+    return [P.results(fr, bf, m) for bf, m in P.run_generations(fr, depth, pair_capacity, keep_levels, leaf_hit)]

@@ -262,6 +262,34 @@ def test_unsorted_comparison_mode_bit_exact():
     _check_fused(f, o)
 
 
+@pytest.mark.parametrize("name", ["refl_96", "mixed_128x72"])
+def test_bounce_generations_bit_exact(name):
+    """Three generations (Sec. 3.3.8): each next generation's rays come from
+    the previous closest hits; every product of every generation, with
+    stored pairs and with the fused last level."""
+    base, kw = small(name)
+    wl = workload(base, **kw)
+    print(f"[bounce] {name}: oracle", flush=True)
+    og = O.run_generations(wl, 3)
+    gg = _gu().run_generations(wl, 3, pair_capacity=1 << 20, keep_levels=True, leaf_hit=False)
+    fg = _gu().run_generations(wl, 3, pair_capacity=1 << 20, keep_levels=False, leaf_hit=True)
+    for gen, (o, g, f) in enumerate(zip(og, gg, fg)):
+        print(f"[bounce] {name} generation {gen}: {o['hash']['n']} rays", flush=True)
+        assert g["n"] == o["hash"]["n"]
+        assert _same(g["keys"], o["hash"]["keys"])
+        for k in O.RAY_FIELDS:
+            assert _same(g["rays"][k], o["hash"]["rays"][k]), k
+        assert _same(g["rays"]["pix"], o["hash"]["rays"]["pix"])
+        assert _same(g["sorted_ids"], o["sorted_ids"])
+        _check_tree(g, o["tree"])
+        for lv, (t, n) in o["trav"]["pairs"].items():
+            assert _same(g["pairs"][lv][0], t) and _same(g["pairs"][lv][1], n), lv
+        assert np.array_equal(g["hit"][0], o["hits"][0])
+        for a, b in zip(g["hit"][1:], o["hits"][1:]):
+            assert _same(a, b)
+        _check_fused(f, o)
+
+
 LEAF_SHAPES = [(16, 4, 5), (8, 2, 3), (32, 8, 4), (5, 3, 4), (1, 16, 3), (12, 4, 2), (16, 4, 1)]
 
 
