@@ -67,6 +67,10 @@ typedef enum crsh_status {
  * keys keep only the type and light bits (31-28), so crsh_sort only groups
  * the rays per type and light and keeps their generation order. */
 #define CRSH_KEY_TYPE_ONLY 0x100u
+/* Direction codes from spherical coordinates (theta = acos dz, phi =
+ * atan2(dy, dx), Sec. 3.3.2) instead of the octahedral map; acos / atan are
+ * the Abramowitz & Stegun 4.4.45 / 4.4.47 polynomials in binary32. */
+#define CRSH_KEY_SPHERICAL 0x200u
 /* material bits of crsh_raygen.mat_flags[] */
 #define CRSH_MAT_REFLECTIVE 1u
 #define CRSH_MAT_REFRACTIVE 2u

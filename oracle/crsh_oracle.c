@@ -73,7 +73,8 @@ typedef struct {
     const float *mat_ior;
     int32_t n_mats;
     uint32_t ray_types;          /* bit0 shadow, bit1 reflection, bit2 refraction;
-                                    bit8: keys of type and light only (unsorted comparison) */
+                                    bit8: keys of type and light only (unsorted comparison);
+                                    bit9: spherical-coordinate direction codes */
     float eps_off, eps_shadow;
     float lo[3], inv_ext[3];     /* origin quantisation box for keys */
 } orc_raygen;
@@ -158,6 +159,63 @@ static void oct_code(v3 D, int k, uint32_t *u, uint32_t *v)
     *v = (uint32_t)fv;
 }
 
+/* Spherical-coordinate direction code, the layout of Sec. 3.3.2 (directions
+ * converted to spherical coordinates): theta = acos(dz) in [0, pi] and
+ * phi = atan2(dy, dx) in [-pi, pi], each quantised to k bits.  acos and
+ * atan are the polynomial approximations of Abramowitz & Stegun 4.4.45
+ * (|error| <= 6.7e-5) and 4.4.47 (|error| <= 1e-5), evaluated in binary32 in
+ * the written order, so any implementation reproduces the same codes. */
+static const float SPH_PI = 3.14159265f;
+static const float SPH_HALF_PI = 1.57079633f;
+static const float SPH_INV_PI = 0.318309886f;
+static const float SPH_INV_TWO_PI = 0.159154943f;
+
+static float sph_acos(float x)
+{
+    float ax = fabsf(x);
+    float p = ((-0.0187293f * ax + 0.0742610f) * ax - 0.2121144f) * ax + 1.5707288f;
+    float r = sqrtf(1.0f - ax) * p;
+    return x < 0.0f ? SPH_PI - r : r;
+}
+
+static float sph_atan2(float y, float x)
+{
+    float ax = fabsf(x), ay = fabsf(y);
+    float hi = ax > ay ? ax : ay;
+    float lo = ax > ay ? ay : ax;
+    if (!(hi > 0.0f)) return 0.0f;
+    float a = lo / hi;
+    float s = a * a;
+    float r = a * ((((0.0208351f * s - 0.0851330f) * s + 0.1801410f) * s - 0.3302995f) * s + 0.9998660f);
+    if (ay > ax) r = SPH_HALF_PI - r;
+    if (x < 0.0f) r = SPH_PI - r;
+    if (y < 0.0f) r = -r;
+    return r;
+}
+
+static void sph_code(v3 D, int k, uint32_t *u, uint32_t *v)
+{
+    float scale = ldexpf(1.0f, k);
+    float top = (float)((1u << k) - 1u);
+    float fu = floorf((sph_acos(D.z) * SPH_INV_PI) * scale);
+    float fv = floorf(((sph_atan2(D.y, D.x) + SPH_PI) * SPH_INV_TWO_PI) * scale);
+    if (!(fu >= 0.0f)) fu = 0.0f;
+    if (fu > top) fu = top;
+    if (!(fv >= 0.0f)) fv = 0.0f;
+    if (fv > top) fv = top;
+    *u = (uint32_t)fu;
+    *v = (uint32_t)fv;
+}
+
+/* Direction code of a key: octahedral, or spherical with ray_types bit 9. */
+static void dir_code(v3 D, int k, uint32_t types, uint32_t *u, uint32_t *v)
+{
+    if (types & 0x200u)
+        sph_code(D, k, u, v);
+    else
+        oct_code(D, k, u, v);
+}
+
 /* Interleave: bit i of u -> bit 2i, bit i of v -> bit 2i+1. */
 static uint32_t morton2(uint32_t u, uint32_t v, int k)
 {
@@ -193,10 +251,10 @@ static uint32_t cell64(float o, float lo, float inv_ext)
 /* Shadow key: type 00 | light (2 bits) | 28-bit octahedral direction code.
  * The light index sits above the direction so that rays of one light sort
  * together (Sec. 3.3.2). */
-static uint32_t shadow_key(int light, v3 D)
+static uint32_t shadow_key(int light, v3 D, uint32_t types)
 {
     uint32_t u, v;
-    oct_code(D, 14, &u, &v);
+    dir_code(D, 14, types, &u, &v);
     return ((uint32_t)light << 28) | morton2(u, v, 14);
 }
 
@@ -209,7 +267,7 @@ static uint32_t bounce_key(uint32_t type, v3 O, v3 D, const orc_raygen *g)
     uint32_t cy = cell64(O.y, g->lo[1], g->inv_ext[1]);
     uint32_t cz = cell64(O.z, g->lo[2], g->inv_ext[2]);
     uint32_t u, v;
-    oct_code(D, 6, &u, &v);
+    dir_code(D, 6, g->ray_types, &u, &v);
     return (type << 30) | (morton3(cx, cy, cz, 6) << 12) | morton2(u, v, 6);
 }
 
@@ -230,7 +288,7 @@ static int64_t emit_slots(v3 P, v3 N, v3 v, uint32_t flags, float ior, uint32_t 
             if (g->ray_types & 1u) {
                 v3 L = mk(g->lights[s][0], g->lights[s][1], g->lights[s][2]);
                 ok = shadow_ray(P, L, g->eps_shadow, &O, &D, &tmax);
-                if (ok) key = shadow_key(s, D);
+                if (ok) key = shadow_key(s, D, g->ray_types);
             }
         } else if (s == g->n_lights) {
             if ((g->ray_types & 2u) && (flags & 1u)) {
@@ -321,7 +379,8 @@ int64_t orc_bounce(const orc_rays *par, const uint32_t *par_keys, uint32_t n_par
 }
 
 /* Exposed for closed-form key checks. */
-uint32_t orc_shadow_key(int light, const float d[3]) { return shadow_key(light, mk(d[0], d[1], d[2])); }
+uint32_t orc_shadow_key(int light, const float d[3]) { return shadow_key(light, mk(d[0], d[1], d[2]), 0u); }
+void orc_sph_code(const float d[3], int k, uint32_t *u, uint32_t *v) { sph_code(mk(d[0], d[1], d[2]), k, u, v); }
 uint32_t orc_bounce_key(uint32_t type, const float o[3], const float d[3], const orc_raygen *g)
 {
     return bounce_key(type, mk(o[0], o[1], o[2]), mk(d[0], d[1], d[2]), g);

@@ -100,6 +100,7 @@ def lib():
         L.orc_bounce_key.restype = C.c_uint32
         L.orc_bounce_key.argtypes = [C.c_uint32, f32p, f32p, C.POINTER(Raygen)]
         L.orc_oct_code.argtypes = [f32p, C.c_int, u32p, u32p]
+        L.orc_sph_code.argtypes = [f32p, C.c_int, u32p, u32p]
         L.orc_cone_add_ray.argtypes = [f32p, C.c_float, C.c_float, f32p, f32p]
         L.orc_cone_union.argtypes = [f32p, f32p, f32p]
         L.orc_sphere_union.argtypes = [f32p, f32p, f32p]
@@ -402,6 +403,14 @@ def bounce_key(typ, o, d, wl):
     o, d = _f32(o), _f32(d)
     g = make_raygen(wl)
     return int(lib().orc_bounce_key(typ, _p(o, f32p), _p(d, f32p), C.byref(g)))
+
+
+def sph_code(d, k):
+    d = _f32(d)
+    u = np.zeros(1, np.uint32)
+    v = np.zeros(1, np.uint32)
+    lib().orc_sph_code(_p(d, f32p), k, _p(u, u32p), _p(v, u32p))
+    return int(u[0]), int(v[0])
 
 
 def oct_code(d, k):

@@ -20,6 +20,7 @@ OK, ERR_INVALID, ERR_CAPACITY, ERR_HIP = 0, 1, 2, 3
 OVERFLOW_RAYS, OVERFLOW_NODES, OVERFLOW_PAIRS, OVERFLOW_ITEMS = 1, 2, 4, 8
 RAY_SHADOW, RAY_REFLECT, RAY_REFRACT = 1, 2, 4
 KEY_TYPE_ONLY = 0x100
+KEY_SPHERICAL = 0x200
 
 vp = C.c_void_p
 

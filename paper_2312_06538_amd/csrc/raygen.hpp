@@ -56,6 +56,61 @@ __device__ __forceinline__ void octahedral(f3 d, int k, uint32_t &u, uint32_t &v
     v = (uint32_t)fv;
 }
 
+// Spherical coordinates of a unit direction, theta = acos(dz) and
+// phi = atan2(dy, dx), each quantised to 2^k bins (the direction layout of
+// Sec. 3.3.2).  acos and atan: Abramowitz & Stegun 4.4.45 and 4.4.47
+// polynomials in binary32, operation by operation, so the codes are
+// reproducible.
+constexpr float SPH_PI = 3.14159265f;
+constexpr float SPH_HALF_PI = 1.57079633f;
+constexpr float SPH_INV_PI = 0.318309886f;
+constexpr float SPH_INV_TWO_PI = 0.159154943f;
+
+__device__ __forceinline__ float sph_acos(float x)
+{
+    const float ax = fabsf(x);
+    const float p = ((-0.0187293f * ax + 0.0742610f) * ax - 0.2121144f) * ax + 1.5707288f;
+    const float r = sqrtf(1.0f - ax) * p;
+    return x < 0.0f ? SPH_PI - r : r;
+}
+
+__device__ __forceinline__ float sph_atan2(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float hi = ax > ay ? ax : ay;
+    const float lo = ax > ay ? ay : ax;
+    if (!(hi > 0.0f)) return 0.0f;
+    const float a = lo / hi;
+    const float s = a * a;
+    float r = a * ((((0.0208351f * s - 0.0851330f) * s + 0.1801410f) * s - 0.3302995f) * s + 0.9998660f);
+    if (ay > ax) r = SPH_HALF_PI - r;
+    if (x < 0.0f) r = SPH_PI - r;
+    if (y < 0.0f) r = -r;
+    return r;
+}
+
+__device__ __forceinline__ void spherical(f3 d, int k, uint32_t &u, uint32_t &v)
+{
+    const float scale = (float)(1u << k);
+    const float top = (float)((1u << k) - 1u);
+    float fu = floorf((sph_acos(d.z) * SPH_INV_PI) * scale);
+    float fv = floorf(((sph_atan2(d.y, d.x) + SPH_PI) * SPH_INV_TWO_PI) * scale);
+    fu = fu >= 0.0f ? fu : 0.0f;
+    fv = fv >= 0.0f ? fv : 0.0f;
+    fu = fu > top ? top : fu;
+    fv = fv > top ? top : fv;
+    u = (uint32_t)fu;
+    v = (uint32_t)fv;
+}
+
+__device__ __forceinline__ void dir_code(f3 d, int k, uint32_t types, uint32_t &u, uint32_t &v)
+{
+    if (types & CRSH_KEY_SPHERICAL)
+        spherical(d, k, u, v);
+    else
+        octahedral(d, k, u, v);
+}
+
 // Spread the low 16 bits of x to the even bit positions.
 __device__ __forceinline__ uint32_t spread2(uint32_t x)
 {
@@ -87,10 +142,10 @@ __device__ __forceinline__ uint32_t cell64(float o, float lo, float inv)
 }
 
 // Shadow: 00 | light:2 | octahedral(14+14).  Bounce: type:2 | cell:18 | octahedral(6+6).
-__device__ __forceinline__ uint32_t key_shadow(uint32_t light, f3 d)
+__device__ __forceinline__ uint32_t key_shadow(uint32_t light, f3 d, uint32_t types = 0u)
 {
     uint32_t u, v;
-    octahedral(d, 14, u, v);
+    dir_code(d, 14, types, u, v);
     return (light << 28) | spread2(u) | (spread2(v) << 1);
 }
 
@@ -100,7 +155,7 @@ __device__ __forceinline__ uint32_t key_bounce(uint32_t type, f3 o, f3 d, const 
     uint32_t cy = cell64(o.y, g.lo[1], g.inv[1]);
     uint32_t cz = cell64(o.z, g.lo[2], g.inv[2]);
     uint32_t u, v;
-    octahedral(d, 6, u, v);
+    dir_code(d, 6, g.types, u, v);
     uint32_t cell = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
     return (type << 30) | (cell << 12) | spread2(u) | (spread2(v) << 1);
 }
@@ -122,7 +177,7 @@ __device__ __forceinline__ bool make_slot(int s, f3 P, f3 N, f3 v, uint32_t flag
                 r.o = L;                  // origin moved to the light
                 r.d = d0 / l;
                 r.tmax = l - g.eps_shadow;
-                r.key = key_shadow((uint32_t)s, r.d);
+                r.key = key_shadow((uint32_t)s, r.d, g.types);
                 ok = true;
             }
         }

@@ -290,6 +290,22 @@ def test_bounce_generations_bit_exact(name):
         _check_fused(f, o)
 
 
+def test_spherical_keys_bit_exact():
+    """Spherical-coordinate direction codes: keys and the whole path."""
+    import dataclasses
+    from workloads import KEY_SPHERICAL
+    base, kw = small("mixed_128x72")
+    wl0 = workload(base, **kw)
+    wl = dataclasses.replace(wl0, ray_types=wl0.ray_types | KEY_SPHERICAL)
+    o = O.run_pipeline(wl)
+    g = _gu().run_pipeline(wl, pair_capacity=1 << 20)
+    assert _same(g["keys"], o["hash"]["keys"]) and _same(g["sorted_ids"], o["sorted_ids"])
+    _check_tree(g, o["tree"])
+    for lv, (t, n) in o["trav"]["pairs"].items():
+        assert _same(g["pairs"][lv][0], t) and _same(g["pairs"][lv][1], n), lv
+    assert np.array_equal(g["hit"][0], o["hits"][0])
+
+
 LEAF_SHAPES = [(16, 4, 5), (8, 2, 3), (32, 8, 4), (5, 3, 4), (1, 16, 3), (12, 4, 2), (16, 4, 1)]
 
 

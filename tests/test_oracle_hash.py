@@ -252,3 +252,59 @@ def test_unsorted_comparison_keys_keep_type_and_light():
     ks, ids = O.sort_rays(b["keys"], b["ids"])
     assert np.array_equal(ids, np.argsort(a["keys"] >> np.uint32(28), kind="stable").astype(np.uint32))
     assert len(np.unique(b["keys"] >> np.uint32(28))) >= 3     # two shadow lights and a bounce type
+
+
+def test_spherical_codes_follow_float64_spherical_coordinates(rng):
+    """Spherical direction codes (theta = acos dz, phi = atan2(dy, dx), each
+    in 2^k bins): within one bin of the float64 bins everywhere (the
+    polynomial acos / atan err by < 7e-5 rad, 0.37 of a 14-bit theta bin),
+    equal away from bin edges, and the poles and axes land where they must."""
+    d = rng.normal(size=(4000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = d.astype(np.float32)
+    for k in (6, 14):
+        n = 1 << k
+        for x in d:
+            u, v = O.sph_code(x, k)
+            x64 = x.astype(np.float64)
+            th = np.arccos(np.clip(x64[2], -1, 1)) / np.pi * n
+            ph = (np.arctan2(x64[1], x64[0]) + np.pi) / (2 * np.pi) * n
+            eu, ev = min(int(np.floor(th)), n - 1), min(int(np.floor(ph)), n - 1)
+            assert abs(u - eu) <= 1 and abs(v - ev) <= 1, (x, k, u, eu, v, ev)
+            # away from a bin edge by more than the approximation error plus
+            # the binary32 evaluation error (a few ulps of pi, and of the bin
+            # index), both in bins, the bin is the exact one
+            mt = (6.7e-5 + 4e-6) * n / np.pi + 8 * n * 2.0 ** -24
+            mp = (1e-5 + 4e-6) * n / (2 * np.pi) + 8 * n * 2.0 ** -24
+            if mt < th % 1 < 1 - mt:
+                assert u == eu, (x, k, u, th)
+            if mp < ph % 1 < 1 - mp:
+                assert v == ev, (x, k, v, ph)
+    assert O.sph_code([0, 0, 1], 14)[0] == 0                      # north pole
+    assert O.sph_code([0, 0, -1], 14)[0] == (1 << 14) - 1          # south pole, clamped
+    assert O.sph_code([1, 0, 0], 6) == (31, 32)                   # theta pi/2 (just below), phi 0
+    assert O.sph_code([-1, 0, 0], 6)[1] == 63                      # phi = pi, clamped
+    assert O.sph_code([0, -1, 0], 6)[1] == 16                      # phi = -pi/2
+
+
+def test_spherical_keys_replace_only_the_direction_bits():
+    wl = workload("mixed_1080p", W=48, H=32, n_meshes=24)
+    import dataclasses
+    from workloads import KEY_SPHERICAL
+    a = O.hash_rays(wl)
+    b = O.hash_rays(dataclasses.replace(wl, ray_types=wl.ray_types | KEY_SPHERICAL))
+    assert b["n"] == a["n"]
+    for k in O.RAY_FIELDS:
+        assert np.array_equal(a["rays"][k], b["rays"][k])
+    shadow = (a["keys"] >> np.uint32(30)) == 0
+    # type, light and origin cell bits unchanged
+    assert np.array_equal(a["keys"][shadow] >> np.uint32(28), b["keys"][shadow] >> np.uint32(28))
+    assert np.array_equal(a["keys"][~shadow] >> np.uint32(12), b["keys"][~shadow] >> np.uint32(12))
+    assert not np.array_equal(a["keys"], b["keys"])
+    for i in np.nonzero(shadow)[0][:200]:
+        d = np.array([b["rays"]["dx"][i], b["rays"]["dy"][i], b["rays"]["dz"][i]])
+        u, v = O.sph_code(d, 14)
+        m = 0
+        for j in range(14):
+            m |= ((u >> j) & 1) << (2 * j) | ((v >> j) & 1) << (2 * j + 1)
+        assert int(b["keys"][i]) & ((1 << 28) - 1) == m

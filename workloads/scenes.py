@@ -22,6 +22,7 @@ from .caster import cast_primary
 
 SHADOW, REFLECT, REFRACT = 1, 2, 4
 KEY_TYPE_ONLY = 0x100           # keys of ray type and light only (comparison mode)
+KEY_SPHERICAL = 0x200           # spherical-coordinate direction codes
 MAT_REFLECT, MAT_REFRACT = 1, 2
 
 
