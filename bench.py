@@ -145,11 +145,10 @@ def main():
         P.run_frame(fr, bf)
     torch.cuda.synchronize()
     ev = HipEvents(args.steps)
-    # the two heaviest kernels, timed on alternate steps: the last level
-    # fused with the final tests, and the level pass that forms level 2 (the
-    # last k_level launch of a frame)
+    # the two heaviest kernels, timed on alternate steps: the final tests and
+    # the level pass that forms level 1 (the last k_level launch of a frame)
     nl = int(m.n_levels)
-    probes = [("k_leaf_hit", 0), ("k_level", max(nl - 3, 0))]
+    probes = [("k_hit", 0), ("k_level", max(nl - 2, 0))]
     t0 = time.perf_counter()
     for k in range(args.steps):
         a, b = ev.pair(k)
@@ -172,8 +171,7 @@ def main():
     final = int(m.final_tests)
     brute = n * wl.scene.m
     kern = {}
-    work = {"k_leaf_hit": int(m.tests[0]) * NODE_OPS + final * MT_OPS,
-            "k_level": int(m.tests[1]) * NODE_OPS if nl >= 2 else 0}
+    work = {"k_hit": final * MT_OPS, "k_level": int(m.tests[0]) * NODE_OPS}
     for name in work:
         if durs.get(name):
             avg = sum(durs[name]) / len(durs[name])

@@ -60,7 +60,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             compile_lib()
         L = C.CDLL(LIB)
         L.orc_hash.restype = C.c_int64

@@ -34,7 +34,7 @@ class DeviceBatch:
     (B, F, levels); hit_block is the workgroup size of the final tests."""
 
     def __init__(self, wls, B, F, levels, hit_block=256, pair_capacity=1 << 22, keep_levels=False,
-                 leaf_hit=True, device="cuda"):
+                 leaf_hit=False, device="cuda"):
         if not 1 <= len(wls) <= X.MAX_FRAMES:
             raise ValueError(f"a batch holds 1..{X.MAX_FRAMES} frames")
         dev = torch.device(device)

@@ -90,7 +90,7 @@ size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t
            + align256(4);                                      // scan tile counter
 }
 
-size_t hit_ws_bytes(uint32_t m) { return align256((size_t)m * 48); }
+size_t hit_ws_bytes(uint32_t m, uint32_t rays) { return align256((size_t)m * 48) + align256((size_t)rays * 32); }
 
 __global__ void k_meta_clear(uint32_t *p, uint32_t n)
 {
@@ -110,7 +110,8 @@ extern "C" size_t crsh_workspace_size(uint32_t max_rays, uint32_t max_tris, uint
     size_t a = std::max(sort_ws_bytes(max_rays), sort_chunked_ws_bytes(max_rays));
     size_t b = hash_ws_bytes(max_rays);
     size_t c = trav_ws_bytes(max_tris, max_nodes, (uint64_t)max_nodes * max_meshes, max_pairs);
-    size_t d = std::max(hit_ws_bytes(max_tris), leaf_hit_ws_bytes(max_tris, max_nodes, max_pairs));
+    size_t d = std::max(hit_ws_bytes(max_tris, max_rays),
+                        leaf_hit_ws_bytes(max_tris, max_nodes, max_pairs, max_rays));
     return std::max(std::max(a, b), std::max(c, d));
 }
 

@@ -200,7 +200,7 @@ __host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(s
 size_t sort_ws_bytes(uint32_t cap);
 size_t hash_ws_bytes(uint64_t pixels);
 size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t max_pairs);
-size_t hit_ws_bytes(uint32_t m);
+size_t hit_ws_bytes(uint32_t m, uint32_t rays);
 
 // Stage launchers shared by the plain entry points (bd == nullptr) and the
 // batched form (bd: the batch's device view, frame-aware kernels).
@@ -231,14 +231,14 @@ crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32
                       const crsh_scene *scene, crsh_hits *hits, crsh_meta *meta, void *ws, int32_t hit_block,
                       const char *who);
 void hit_prep_launch(const crsh_scene *scene, float4 *tri, hipStream_t stream);
-void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const crsh_pairs *level1, int32_t bundle,
-                      const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
-                      int32_t hit_block, hipStream_t stream);
+void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, float4 *rays4, const crsh_pairs *level1,
+                      int32_t bundle, const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta,
+                      const batch_dev *bd, int32_t hit_block, hipStream_t stream);
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
                       const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
                       hipStream_t stream);
 void tri_spheres_launch(const crsh_scene *scene, uint32_t b, uint32_t e, float4 *out, hipStream_t stream);
-size_t leaf_hit_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t level2_cap);
+size_t leaf_hit_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t level2_cap, uint32_t rays);
 size_t sort_chunked_ws_bytes(uint32_t cap);
 
 // launch helpers

@@ -40,8 +40,19 @@ struct sorted_rays {
     const float *ox, *oy, *oz, *dx, *dy, *dz, *tmax;
 };
 
+// Sorted rays repacked as 2 x float4 (origin, tmax), (direction, 0): two
+// 16-byte loads per test instead of seven scattered ones.
+__global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, float4 *rays)
+{
+    const uint32_t n = min(meta->n_rays, cap);
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+        rays[2 * s] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
+        rays[2 * s + 1] = make_float4(R.dx[s], R.dy[s], R.dz[s], 0.0f);
+    }
+}
+
 template <bool BATCH>
-__global__ __launch_bounds__(256) void k_hit(sorted_rays R, const float4 *__restrict__ tri,
+__global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const float4 *__restrict__ tri,
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
                                              uint64_t cap1, uint32_t B, uint32_t log2G, float t_min0,
                                              unsigned long long *tkey, crsh_meta *meta, uint32_t ray_cap, uint32_t m,
@@ -79,10 +90,9 @@ __global__ __launch_bounds__(256) void k_hit(sorted_rays R, const float4 *__rest
         if (s >= n || t >= m) continue;
         ++tests;
         const tri_t tr = load_tri(tri, t);
-        const f3 O = mk(R.ox[s], R.oy[s], R.oz[s]);
-        const f3 D = mk(R.dx[s], R.dy[s], R.dz[s]);
+        const float4 ro = R[2 * s], rd = R[2 * s + 1];
         float th, uh, vh;
-        if (moller_trumbore(O, D, t_min, R.tmax[s], tr, th, uh, vh)) {
+        if (moller_trumbore(mk(ro.x, ro.y, ro.z), mk(rd.x, rd.y, rd.z), t_min, ro.w, tr, th, uh, vh)) {
             unsigned long long key = ((unsigned long long)__float_as_uint(th) << 32) | t;
             atomicMin(&tkey[s], key);
         }
@@ -166,14 +176,19 @@ void hit_prep_launch(const crsh_scene *scene, float4 *tri, hipStream_t stream)
     }
 }
 
-void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const crsh_pairs *level1, int32_t bundle,
-                      const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
-                      int32_t hit_block, hipStream_t stream)
+void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, float4 *rays4, const crsh_pairs *level1,
+                      int32_t bundle, const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta,
+                      const batch_dev *bd, int32_t hit_block, hipStream_t stream)
 {
     if (!level1->capacity) return;
     uint32_t log2G = 0;
     while ((1u << log2G) < (uint32_t)bundle) ++log2G;
-    sorted_rays R{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
+    {
+        sorted_rays S{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
+        uint32_t g = std::max<uint32_t>(std::min<uint32_t>((sorted->capacity + 255) / 256, 4096), 1);
+        k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, rays4);
+    }
+    const float4 *R = rays4;
     const batch_dev b = bd ? *bd : batch_dev{};
     const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
     prof_scope ps("k_hit", stream);
@@ -247,13 +262,15 @@ crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int3
     crsh_status st = hit_check(sorted, sorted_ids, bundle, level1, scene, hits, meta, ws, hit_block,
                                "crsh_closest_hit");
     if (st != CRSH_OK) return st;
-    if (ws_bytes < hit_ws_bytes(scene->m)) {
-        set_error("crsh_closest_hit: workspace too small (%zu < %zu)", ws_bytes, hit_ws_bytes(scene->m));
+    if (ws_bytes < hit_ws_bytes(scene->m, sorted->capacity)) {
+        set_error("crsh_closest_hit: workspace too small (%zu < %zu)", ws_bytes,
+                  hit_ws_bytes(scene->m, sorted->capacity));
         return CRSH_ERR_INVALID;
     }
     float4 *tri = (float4 *)ws;
+    float4 *rays4 = (float4 *)((char *)ws + align256((size_t)scene->m * 48));
     hit_prep_launch(scene, tri, stream);
-    hit_pairs_launch(sorted, tri, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream);
+    hit_pairs_launch(sorted, tri, rays4, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream);
     hit_final_launch(sorted, sorted_ids, tri, scene, t_min, hits, meta, bd, stream);
     return hip_check(hipGetLastError(), "crsh_closest_hit launch");
 }

@@ -23,15 +23,29 @@ __device__ __forceinline__ tri_t load_tri(const float4 *__restrict__ tri, uint32
 }
 
 // Two-sided Moller-Trumbore, accepted for t_min < t < tmax.
+//
+// u = a * (1/det) is first decided without the division where its sign or
+// size settles the test exactly as the rounded quotient would: with
+// |det| <= 2^60 the rounded reciprocal has magnitude >= 2^-60, so opposite
+// signs and |a| >= 2^-60 give u <= -2^-120 < 0; and |a| above the rounded
+// |det| (1 + 2^-19) with equal signs gives a quotient above 1 + 2^-20, which
+// two roundings cannot bring down to 1.  Other cases divide as written.
 __device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float tmax, const tri_t &tr, float &tt,
                                                 float &uu, float &vv)
 {
     f3 p = cross(D, tr.e2);
     float det = dot(tr.e1, p);
-    if (!(fabsf(det) >= DET_EPS)) return false;
-    float inv = 1.0f / det;
+    const float adet = fabsf(det);
+    if (!(adet >= DET_EPS)) return false;
     f3 T = O - tr.v0;
-    float u = dot(T, p) * inv;
+    const float a = dot(T, p);
+    if (adet <= 0x1p60f) {
+        const bool opposite = (a < 0.0f) != (det < 0.0f);
+        if (opposite && fabsf(a) >= 0x1p-60f) return false;
+        if (!opposite && fabsf(a) > adet * (1.0f + 0x1p-19f)) return false;
+    }
+    float inv = 1.0f / det;
+    float u = a * inv;
     if (!(u >= 0.0f && u <= 1.0f)) return false;
     f3 q = cross(T, tr.e1);
     float v = dot(D, q) * inv;

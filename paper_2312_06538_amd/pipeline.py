@@ -123,7 +123,7 @@ class Buffers:
         return self.pair_bufs[lv - 1] if self.keep_levels else self.pair_bufs[lv % len(self.pair_bufs)]
 
 
-def run_frame(fr, bf, stream=None, tri_batches=None, leaf_hit=True, parent=None):
+def run_frame(fr, bf, stream=None, tri_batches=None, leaf_hit=False, parent=None):
     """Chain hash -> sort -> build -> traverse -> closest hit on one stream.
     leaf_hit: the last traversal level runs fused with the final tests
     (crsh_traverse_upper + crsh_leaf_hit); otherwise every level-1 pair is
@@ -158,7 +158,7 @@ def read_meta(bf, stream=None):
     return m, st
 
 
-def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12, leaf_hit=True, parent=None):
+def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12, leaf_hit=False, parent=None):
     """Run a frame; if a pair level overflowed, regrow the pair arrays and run
     again (the ray arrays likewise for a bounce generation that outgrew
     them).  An overflowing level truncates the levels below it, so their
@@ -179,7 +179,7 @@ def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=1
     raise X.CrshError(X.ERR_CAPACITY, "capacity still too small after regrowing")
 
 
-def run_generations(fr, depth, pair_capacity=1 << 22, keep_levels=False, leaf_hit=True, stream=None):
+def run_generations(fr, depth, pair_capacity=1 << 22, keep_levels=False, leaf_hit=False, stream=None):
     """`depth` generations of the path (Sec. 3.3.8): the first from the
     primary-hit buffer, each next one from the closest hits of the previous
     (crsh_bounce), every one through sort, build, traversal and final tests.
