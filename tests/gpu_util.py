@@ -179,7 +179,7 @@ def gpu_closest_hit(rays, sorted_ids, B, pairs1, sc, t_min):
     tt, uu, vv = (torch.zeros(cap, dtype=torch.float32, device="cuda") for _ in range(3))
     hits = X.Hits(tkey.data_ptr(), tri.data_ptr(), tt.data_ptr(), uu.data_ptr(), vv.data_ptr(), cap)
     meta = new_meta(n_rays=n, n_levels=1, pairs=[len(pairs1[0])])
-    wsb = X.crsh_workspace_size(1, sc.m, 1, 1, 1)
+    wsb = X.crsh_workspace_size(cap, sc.m, 1, 1, 1)
     ws = ws_tensor(wsb)
     X.crsh_hits_reset(hits, s())
     X.crsh_closest_hit(c_sr, d_sid.data_ptr(), B, lvl1, c_sc, t_min, hits, meta.data_ptr(), ws.data_ptr(),
