@@ -8,7 +8,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcrsh.so")
+# CRSH_LIBRARY may name another build of the same library (e.g. a variant
+# built with different compile-time tile sizes); the default is in-tree.
+LIB_PATH = os.environ.get("CRSH_LIBRARY") or os.path.join(HERE, "libcrsh.so")
 
 MAX_LEVELS = 16
 MAX_LIGHTS = 4
