@@ -99,7 +99,7 @@ def cpu_baseline(wl, n_sample_top=16):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=12)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="refl_1024",
                     choices=["shadow_128", "refl_1024", "mixed_1080p", "adjoint_512", "batch_64"])
@@ -145,10 +145,12 @@ def main():
         P.run_frame(fr, bf)
     torch.cuda.synchronize()
     ev = HipEvents(args.steps)
-    # the two heaviest kernels, timed on alternate steps: the final tests and
-    # the level pass that forms level 1 (the last k_level launch of a frame)
+    # kernels timed on alternate steps: the two heaviest (the final tests and
+    # the level pass that forms level 1, the last k_level launch of a frame)
+    # and the sort and compaction kernels measured against HBM bandwidth (the
+    # second radix pass, the emit that writes level 1)
     nl = int(m.n_levels)
-    probes = [("k_hit", 0), ("k_level", max(nl - 2, 0))]
+    probes = [("k_hit", 0), ("k_level", max(nl - 2, 0)), ("k_sort_pass", 1), ("k_level_emit", max(nl - 2, 0))]
     t0 = time.perf_counter()
     for k in range(args.steps):
         a, b = ev.pair(k)
@@ -183,6 +185,21 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["kernel_ms"]) if kern else None
     roof = kern.get(dom)
     other = {k: v for k, v in kern.items() if k != dom}
+    # HBM kernels: algorithmic bytes per launch.  Sort pass: key + id read
+    # and written (16 B per key).  Level emit: the 4-byte pass mask of every
+    # two parent pairs, each parent pair with a survivor read (8 B, at most
+    # min(in, out) of them) and every output pair written (8 B).
+    n_in = int(m.hits[1]) if nl >= 2 else 0
+    n_out = int(m.hits[0])
+    hbm_bytes = {"k_sort_pass": 16 * n, "k_level_emit": 2 * n_in + 8 * min(n_in, n_out) + 8 * n_out}
+    hbm = {}
+    for name, nbytes in hbm_bytes.items():
+        if durs.get(name) and nbytes:
+            avg = sum(durs[name]) / len(durs[name])
+            gbs = nbytes / (avg * 1e-3) / 1e9
+            hbm[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "kernel_ms": round(avg, 4), "bytes_per_launch": nbytes,
+                         "launches_timed": len(durs[name])}
     out = {
         "metric": "secondary rays/sec (hash+sort+build+traverse+hit); ray-tri tests vs brute N×M",
         "value": round(n / (ms_step * 1e-3), 1),
@@ -199,6 +216,7 @@ def main():
                   "mesh_tests": int(m.mesh_tests), "levels": nl},
         "roofline": roof,
         "other_kernels": other,
+        "hbm_kernels": hbm,
     }
     if args.copy_probe_mib:
         n4 = args.copy_probe_mib * (1 << 20) // 4
