@@ -107,6 +107,8 @@ def main():
                     help="unsorted: the comparison hierarchy without ray sorting, whole-mesh culling or a "
                          "level cap, on the same inputs")
     ap.add_argument("--frames", type=int, default=64, help="batch_64: number of frames")
+    ap.add_argument("--sort-sweep", action="store_true",
+                    help="instead of a frame: crsh_sort on 2^20..2^27 random keys, GB/s per radix pass")
     ap.add_argument("--tune", action="store_true",
                     help="batch_64: tune (B, levels, hit_block) by timing the captured batch")
     ap.add_argument("--tune-cache", default=None, help="batch_64: JSON cache of tuned points")
@@ -121,6 +123,8 @@ def main():
               "the path is described in DESIGN.md but not built", file=sys.stderr)
         return 2
 
+    if args.sort_sweep:
+        return bench_sort_sweep(args)
     if args.workload == "batch_64":
         return bench_batch(args)
 
@@ -228,6 +232,58 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample_top)
     print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_sort_sweep(args):
+    """crsh_sort alone on uniformly random 32-bit keys (no digit pass
+    skipped) from 2^20 to 2^27 keys: the sizes past the 256 MiB last-level
+    cache show the HBM rate.  Bytes per radix pass: key and id read and
+    written (16 B per key)."""
+    import torch
+    from paper_2312_06538_amd import crsh as X
+    from paper_2312_06538_amd import pipeline as P
+
+    rows = []
+    ev = HipEvents(2)
+    h = ev.h
+    for lg in range(20, 28):
+        n = 1 << lg
+        g = torch.Generator(device="cuda").manual_seed(args.seed + lg)
+        keys = torch.randint(-(1 << 31), (1 << 31) - 1, (n,), dtype=torch.int32, device="cuda", generator=g)
+        ids = torch.arange(n, dtype=torch.int32, device="cuda")
+        ko, io = torch.empty_like(keys), torch.empty_like(ids)
+        meta = torch.zeros(ctypes.sizeof(X.Meta), dtype=torch.uint8, device="cuda")
+        meta[:4] = torch.tensor([n], dtype=torch.int32).view(torch.uint8).cuda()
+        wsb = X.crsh_workspace_size(n, 1, 1, 1, 1)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        s = P.stream_handle()
+        call = lambda: X.crsh_sort(keys.data_ptr(), ids.data_ptr(), ko.data_ptr(), io.data_ptr(), n,
+                                   meta.data_ptr(), ws.data_ptr(), wsb, s)
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        pass_ms = []
+        whole = []
+        for k in range(args.steps):
+            a, b = ev.pair(0)
+            X.crsh_profile_next("k_sort_pass", k % 4, a, b)
+            c, d = ev.pair(1)
+            h.hipEventRecord(c, ctypes.c_void_p(s))
+            call()
+            h.hipEventRecord(d, ctypes.c_void_p(s))
+            torch.cuda.synchronize()
+            pass_ms.append(ev.ms(0))
+            whole.append(ev.ms(1))
+        pm = sum(pass_ms) / len(pass_ms)
+        wm = sorted(whole)[len(whole) // 2]
+        rows.append({"keys": n, "pass_ms": round(pm, 4), "pass_GBs": round(16 * n / (pm * 1e-3) / 1e9, 1),
+                     "pass_frac": round(16 * n / (pm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "sort_ms": round(wm, 4),
+                     "sort_Mkeys_s": round(n / (wm * 1e-3) / 1e6, 1)})
+        print(f"[bench] sort 2^{lg}: pass {pm:.4f} ms, {rows[-1]['pass_GBs']} GB/s", file=sys.stderr, flush=True)
+        del keys, ids, ko, io, ws
+    print(json.dumps({"metric": "crsh_sort radix pass bandwidth (16 B per key per pass)", "unit": "GB/s",
+                      "peak": HBM_PEAK_GBS, "steps": args.steps, "rows": rows}), flush=True)
     return 0
 
 
