@@ -40,6 +40,8 @@ struct sorted_rays {
     const float *ox, *oy, *oz, *dx, *dy, *dz, *tmax;
 };
 
+constexpr int HIT_UNROLL = 2;    // pairs per lane group in flight at once
+
 // Sorted rays repacked as 2 x float4 (origin, tmax), (direction, 0): two
 // 16-byte loads per test instead of seven scattered ones.
 __global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, float4 *rays)
@@ -71,30 +73,52 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
     uint64_t tests = 0;
-    for (uint64_t q0 = wave * per_wave; q0 < np; q0 += nwaves * per_wave) {
-        const uint64_t q = q0 + slot;
-        if (q >= np || j >= B) continue;
-        const uint32_t t = ptri[q];
-        const uint32_t leaf = pnode[q];
-        uint32_t s;
-        float t_min = t_min0;
-        if constexpr (BATCH) {
-            if (leaf >= n_leaf) continue;
-            const uint32_t info = bd.node_info[leaf];
-            if (j >= (info & INFO_COUNT_MASK)) continue;
-            s = bd.node_first[leaf] + j;
-            t_min = bd.frames[info >> INFO_FRAME_SHIFT].t_min;
-        } else {
-            s = leaf * B + j;
+    // Each lane group takes HIT_UNROLL pairs per iteration, a grid stride
+    // apart, and issues all their loads before any test: the pair, triangle
+    // and ray loads of the pairs overlap instead of forming one dependent
+    // chain per pair.
+    const uint64_t step = nwaves * per_wave;
+    const bool lane_ok = j < B;
+    for (uint64_t q0 = wave * per_wave; q0 < np; q0 += HIT_UNROLL * step) {
+        uint32_t t[HIT_UNROLL], s[HIT_UNROLL];
+        bool ok[HIT_UNROLL];
+        float t_min[HIT_UNROLL];
+#pragma unroll
+        for (int k = 0; k < HIT_UNROLL; ++k) {
+            const uint64_t q = q0 + slot + k * step;
+            ok[k] = lane_ok && q < np;
+            t[k] = ok[k] ? ptri[q] : 0u;
+            const uint32_t leaf = ok[k] ? pnode[q] : 0u;
+            t_min[k] = t_min0;
+            if constexpr (BATCH) {
+                ok[k] = ok[k] && leaf < n_leaf;
+                const uint32_t info = ok[k] ? bd.node_info[leaf] : 0u;
+                ok[k] = ok[k] && j < (info & INFO_COUNT_MASK);
+                s[k] = ok[k] ? bd.node_first[leaf] + j : 0u;
+                if (ok[k]) t_min[k] = bd.frames[info >> INFO_FRAME_SHIFT].t_min;
+            } else {
+                s[k] = leaf * B + j;
+            }
+            ok[k] = ok[k] && s[k] < n && t[k] < m;
         }
-        if (s >= n || t >= m) continue;
-        ++tests;
-        const tri_t tr = load_tri(tri, t);
-        const float4 ro = R[2 * s], rd = R[2 * s + 1];
-        float th, uh, vh;
-        if (moller_trumbore(mk(ro.x, ro.y, ro.z), mk(rd.x, rd.y, rd.z), t_min, ro.w, tr, th, uh, vh)) {
-            unsigned long long key = ((unsigned long long)__float_as_uint(th) << 32) | t;
-            atomicMin(&tkey[s], key);
+        tri_t tr[HIT_UNROLL];
+        float4 ro[HIT_UNROLL], rd[HIT_UNROLL];
+#pragma unroll
+        for (int k = 0; k < HIT_UNROLL; ++k) {
+            tr[k] = load_tri(tri, ok[k] ? t[k] : 0u);
+            ro[k] = R[2 * (ok[k] ? s[k] : 0u)];
+            rd[k] = R[2 * (ok[k] ? s[k] : 0u) + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < HIT_UNROLL; ++k) {
+            if (!ok[k]) continue;
+            ++tests;
+            float th;
+            if (moller_trumbore_t(mk(ro[k].x, ro[k].y, ro[k].z), mk(rd[k].x, rd[k].y, rd[k].z), t_min[k], ro[k].w,
+                                  tr[k], th)) {
+                unsigned long long key = ((unsigned long long)__float_as_uint(th) << 32) | t[k];
+                atomicMin(&tkey[s[k]], key);
+            }
         }
     }
     tests = wave_sum(tests);

@@ -19,35 +19,10 @@
 // node, mesh of the frame); a parent's children are the range recorded with
 // it by the build (first child, count), so no frame lookup is needed below
 // the top.
-#include "batch.hpp"
 #include "bounds.hpp"
+#include "traverse.hpp"
 
 namespace crsh {
-
-struct pairs_dev {
-    uint32_t *tri, *node;
-    uint64_t cap;
-};
-struct pair_levels {
-    pairs_dev p[CRSH_MAX_LEVELS];
-};
-struct node_arrays {
-    const float *cx, *cy, *cz, *r, *ax, *ay, *az, *c, *tan, *sec;
-};
-
-// per-level scratch carved from the workspace
-struct trav_scratch {
-    uint32_t *cnt;         // survivors per work item
-    uint64_t *off;         // exclusive offsets of the work items
-    uint32_t *mask;        // pass masks of the lower-level count pass
-    uint64_t *scan_flags;  // look-back words of the scan
-    uint32_t *scan_ctr;    // tile counter of the scan
-};
-
-constexpr uint32_t SCAN_THREADS = 256;
-constexpr uint32_t SCAN_ITEMS = 16;
-constexpr uint32_t SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
-static_assert(SCAN_TILE == SCAN_TILE_ITEMS, "workspace sizing");
 
 __global__ void k_tri_sph(const float *__restrict__ v0x, const float *__restrict__ v0y,
                           const float *__restrict__ v0z, const float *__restrict__ v1x,
@@ -72,7 +47,7 @@ __global__ void k_tri_sph(const float *__restrict__ v0x, const float *__restrict
 // with sec = -1 marking a cone of 90 degrees or more (c <= 0 gives no
 // positive sec, c > 0 always does), so one test reads 36 bytes in 3 loads.
 // Also clears the per-call pair counts.
-__global__ void k_node_pack(node_arrays nd, crsh_meta *meta, float4 *na, float4 *nb, float *ns)
+__global__ void k_node_pack(node_arrays nd, crsh_meta *meta, float4 *na, float4 *nb, float *ns, bool clear_pairs)
 {
     const uint32_t nl = meta->n_levels;
     const uint32_t total = nl ? meta->level_off[nl - 1] + meta->level_cnt[nl - 1] : 0;
@@ -81,7 +56,7 @@ __global__ void k_node_pack(node_arrays nd, crsh_meta *meta, float4 *na, float4 
         nb[i] = make_float4(nd.ax[i], nd.ay[i], nd.az[i], nd.tan[i]);
         ns[i] = nd.c[i] > 0.0f ? nd.sec[i] : -1.0f;
     }
-    if (blockIdx.x == 0 && threadIdx.x < CRSH_MAX_LEVELS) meta->pairs[threadIdx.x] = 0;
+    if (clear_pairs && blockIdx.x == 0 && threadIdx.x < CRSH_MAX_LEVELS) meta->pairs[threadIdx.x] = 0;
 }
 
 // number of work items of a level: top level (parent_level 0) = top nodes x
@@ -532,6 +507,47 @@ using namespace crsh;
 
 namespace crsh {
 
+void node_pack_launch(const crsh_nodes *nodes, crsh_meta *meta, float4 *na, float4 *nb, float *ns, bool clear_pairs,
+                      hipStream_t stream)
+{
+    node_arrays nd{nodes->cx, nodes->cy, nodes->cz, nodes->r, nodes->ax, nodes->ay, nodes->az,
+                   nodes->c, nodes->tan, nodes->sec};
+    uint32_t g = std::min<uint32_t>((nodes->capacity + 255) / 256, 2048);
+    if (g == 0) g = 1;
+    k_node_pack<<<g, 256, 0, stream>>>(nd, meta, na, nb, ns, clear_pairs);
+}
+
+void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
+                        const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
+                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream)
+{
+    const batch_dev b = bd ? *bd : batch_dev{};
+    const uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), 4096);
+    const uint32_t Fu = (uint32_t)merge;
+    const int L = parent_level;
+    int nf = 2;
+    while (nf < merge) nf *= 2;
+#define CRSH_COUNT(NF, BT)                                                                                   \
+    k_level_count<NF, LEVEL_PPT, BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta, b)
+    prof_scope ps("k_level", stream);
+    if (bd) {
+        switch (nf) {
+        case 2: CRSH_COUNT(2, true); break;
+        case 4: CRSH_COUNT(4, true); break;
+        case 8: CRSH_COUNT(8, true); break;
+        default: CRSH_COUNT(16, true); break;
+        }
+    } else {
+        switch (nf) {
+        case 2: CRSH_COUNT(2, false); break;
+        case 4: CRSH_COUNT(4, false); break;
+        case 8: CRSH_COUNT(8, false); break;
+        default: CRSH_COUNT(16, false); break;
+        }
+    }
+#undef CRSH_COUNT
+}
+
 void tri_spheres_launch(const crsh_scene *scene, uint32_t b, uint32_t e, float4 *out, hipStream_t stream)
 {
     const float *const *v = scene->v;
@@ -628,11 +644,7 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
     }
     const batch_dev b = bd ? *bd : batch_dev{};
     tri_spheres_launch(scene, tri_begin, tri_end, tsph, stream);
-    {
-        uint32_t g = std::min<uint32_t>((nodes->capacity + 255) / 256, 2048);
-        if (g == 0) g = 1;
-        k_node_pack<<<g, 256, 0, stream>>>(nd, meta, na, nb, ns);
-    }
+    node_pack_launch(nodes, meta, na, nb, ns, true, stream);
     k_no_storage<<<1, 1, 0, stream>>>(meta, (uint32_t)levels);
     const uint32_t scan_grid = (uint32_t)std::min<uint64_t>((items + SCAN_TILE - 1) / SCAN_TILE, 1u << 20);
     const uint32_t top_grid = (uint32_t)std::max<uint64_t>(std::min<uint64_t>((top_items + 3) / 4, 2048), 1);
@@ -675,28 +687,8 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
     auto level_pass_launch = [&](int L) {
         const uint64_t tiles = (pairs[L - 1].capacity + LEVEL_TILE - 1) / LEVEL_TILE;
         uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096);
-#define CRSH_COUNT(NF, BT)                                                                                   \
-    k_level_count<NF, LEVEL_PPT, BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, scene->m, P, S, \
-                                                                      meta, b)
 #define CRSH_EMIT(NF, BT) k_level_emit<NF, LEVEL_PPT, BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta, b)
-        {
-            prof_scope ps("k_level", stream);
-            if (bd) {
-                switch (nf) {
-                case 2: CRSH_COUNT(2, true); break;
-                case 4: CRSH_COUNT(4, true); break;
-                case 8: CRSH_COUNT(8, true); break;
-                default: CRSH_COUNT(16, true); break;
-                }
-            } else {
-                switch (nf) {
-                case 2: CRSH_COUNT(2, false); break;
-                case 4: CRSH_COUNT(4, false); break;
-                case 8: CRSH_COUNT(8, false); break;
-                default: CRSH_COUNT(16, false); break;
-                }
-            }
-        }
+        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream);
         k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
             prof_scope ps("k_level_emit", stream);
@@ -716,7 +708,6 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
                 }
             }
         }
-#undef CRSH_COUNT
 #undef CRSH_EMIT
     };
     if (bd) {
