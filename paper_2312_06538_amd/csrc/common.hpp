@@ -191,7 +191,10 @@ constexpr uint32_t SORT_TILE = 4096;      // keys per sort tile
 constexpr uint32_t SORT_PASSES = 4;       // 8-bit digits of a 32-bit key
 constexpr uint32_t HASH_BLOCK = 256;      // pixels per hash block
 constexpr uint32_t LEVEL_THREADS = 256;   // threads of a traversal tile
-constexpr uint32_t LEVEL_PPT = 2;         // parent pairs per thread
+#ifndef CRSH_LEVEL_PPT
+#define CRSH_LEVEL_PPT 2
+#endif
+constexpr uint32_t LEVEL_PPT = CRSH_LEVEL_PPT;   // parent pairs per thread
 constexpr uint32_t LEVEL_TILE = LEVEL_THREADS * LEVEL_PPT;   // parent pairs per tile
 constexpr uint32_t SCAN_TILE_ITEMS = 4096;                 // counts per scan tile
 

@@ -40,7 +40,10 @@ struct sorted_rays {
     const float *ox, *oy, *oz, *dx, *dy, *dz, *tmax;
 };
 
-constexpr int HIT_UNROLL = 2;    // pairs per lane group in flight at once
+#ifndef CRSH_HIT_UNROLL
+#define CRSH_HIT_UNROLL 2
+#endif
+constexpr int HIT_UNROLL = CRSH_HIT_UNROLL;    // pairs per lane group in flight at once
 
 // Sorted rays repacked as 2 x float4 (origin, tmax), (direction, 0): two
 // 16-byte loads per test instead of seven scattered ones.
