@@ -90,7 +90,7 @@ size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t
            + align256(4);                                      // scan tile counter
 }
 
-size_t hit_ws_bytes(uint32_t m, uint32_t rays) { return align256((size_t)m * 48) + align256((size_t)rays * 32); }
+size_t hit_ws_bytes(uint32_t m, uint32_t slots) { return align256((size_t)m * 48) + hit_slots_bytes(slots); }
 
 __global__ void k_meta_clear(uint32_t *p, uint32_t n)
 {

@@ -38,7 +38,8 @@ static batch_layout layout(uint32_t ray_cap, uint64_t pixels, uint32_t m, uint32
     L.stage = L.top + align256(2 * sizeof(uint64_t));
     size_t st = std::max(sort_ws_bytes(ray_cap), hash_ws_bytes(pixels));
     st = std::max(st, trav_ws_bytes(m, node_cap, top_items, max_pairs));
-    st = std::max(st, std::max(hit_ws_bytes(m, ray_cap), leaf_hit_ws_bytes(m, node_cap, max_pairs, ray_cap)));
+    const uint32_t slots = hit_slots(ray_cap, true);
+    st = std::max(st, std::max(hit_ws_bytes(m, slots), leaf_hit_ws_bytes(m, node_cap, max_pairs, slots)));
     L.total = L.stage + st;
     return L;
 }

@@ -203,7 +203,29 @@ __host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(s
 size_t sort_ws_bytes(uint32_t cap);
 size_t hash_ws_bytes(uint64_t pixels);
 size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t max_pairs);
-size_t hit_ws_bytes(uint32_t m, uint32_t rays);
+// Final-test workspace: packed triangles (48 B each), then per ray slot the
+// packed ray (32 B) and a closest-hit key (8 B).  Slots: one per sorted ray in
+// the plain form; in the batched form B per level-1 node, at most the rays
+// plus B - 1 per frame.
+size_t hit_ws_bytes(uint32_t m, uint32_t slots);
+constexpr uint32_t hit_slots(uint32_t rays, bool batch)
+{
+    return batch ? rays + CRSH_MAX_FRAMES * (CRSH_MAX_BUNDLE - 1) : rays;
+}
+struct hit_slots_ws {
+    float4 *rays4;               // 2 x float4 per slot
+    unsigned long long *keys;    // per slot (batched form)
+    uint32_t slots;
+};
+inline hit_slots_ws carve_hit_slots(void *at, uint32_t slots)
+{
+    hit_slots_ws h;
+    h.rays4 = (float4 *)at;
+    h.keys = (unsigned long long *)((char *)at + align256((size_t)slots * 32));
+    h.slots = slots;
+    return h;
+}
+inline size_t hit_slots_bytes(uint32_t slots) { return align256((size_t)slots * 32) + align256((size_t)slots * 8); }
 
 // Stage launchers shared by the plain entry points (bd == nullptr) and the
 // batched form (bd: the batch's device view, frame-aware kernels).
@@ -234,12 +256,12 @@ crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32
                       const crsh_scene *scene, crsh_hits *hits, crsh_meta *meta, void *ws, int32_t hit_block,
                       const char *who);
 void hit_prep_launch(const crsh_scene *scene, float4 *tri, hipStream_t stream);
-void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, float4 *rays4, const crsh_pairs *level1,
+void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level1,
                       int32_t bundle, const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta,
                       const batch_dev *bd, int32_t hit_block, hipStream_t stream);
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
-                      const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
-                      hipStream_t stream);
+                      const hit_slots_ws &hs, int32_t bundle, const crsh_scene *scene, float t_min,
+                      crsh_hits *hits, crsh_meta *meta, const batch_dev *bd, hipStream_t stream);
 void tri_spheres_launch(const crsh_scene *scene, uint32_t b, uint32_t e, float4 *out, hipStream_t stream);
 size_t leaf_hit_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t level2_cap, uint32_t rays);
 size_t sort_chunked_ws_bytes(uint32_t cap);

@@ -13,8 +13,14 @@
 //              is the closest hit with ties to the lower triangle id.
 // k_hit_final  one thread per sorted ray: decode the key, recompute u, v with
 //              the same test, write the result at the ray id.
-// Batched form: a leaf's rays are the range the build recorded with it (first
-// sorted ray, count) and the accepted interval starts at its frame's t_min.
+// Ray slots: k_hit reads the rays of leaf l at slots l * B + j, j < B, of a
+// packed ray array whose second float4 carries the interval start t_min.  In
+// the plain form slot s is sorted ray s.  In the batched form a frame's rays
+// are bundled B at a time from its own first ray, so only a frame's last leaf
+// can hold fewer than B rays; its slots are padded (a marker in place of
+// t_min) and the closest-hit keys are kept by slot, so the pair loop finds a
+// ray with no per-leaf lookup.  k_hit_final maps each sorted ray back to its
+// slot through its frame's first leaf and first ray.
 #include "batch.hpp"
 #include "intersect.hpp"
 
@@ -41,31 +47,72 @@ struct sorted_rays {
 };
 
 #ifndef CRSH_HIT_UNROLL
-#define CRSH_HIT_UNROLL 2
+#define CRSH_HIT_UNROLL 1
 #endif
 constexpr int HIT_UNROLL = CRSH_HIT_UNROLL;    // pairs per lane group in flight at once
+#ifndef CRSH_HIT_CHUNK
+#define CRSH_HIT_CHUNK 64
+#endif
+constexpr uint32_t HIT_CHUNK = CRSH_HIT_CHUNK;  // consecutive pairs a wave tests before the grid stride
 
-// Sorted rays repacked as 2 x float4 (origin, tmax), (direction, 0): two
-// 16-byte loads per test instead of seven scattered ones.
-__global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, float4 *rays)
+// t_min word of a padded slot (a NaN); a NaN t_min of a real ray is stored as
+// the default quiet NaN, which accepts no hit either
+constexpr uint32_t PAD_SLOT = 0x7FC0DEADu;
+__device__ __forceinline__ float slot_tmin(float t_min) { return t_min != t_min ? __uint_as_float(0x7FC00000u) : t_min; }
+
+// slots of the batched form in use: B per level-1 node
+__device__ __forceinline__ uint32_t batch_slots(const crsh_meta *meta, uint32_t B, uint32_t slot_cap)
+{
+    const uint64_t ns = meta->n_levels ? (uint64_t)meta->level_cnt[0] * B : 0u;
+    return (uint32_t)(ns < slot_cap ? ns : slot_cap);
+}
+
+// Plain form: sorted rays repacked as 2 x float4 (origin, tmax), (direction,
+// t_min): two 16-byte loads per test instead of seven scattered ones.
+__global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, float t_min, float4 *rays)
 {
     const uint32_t n = min(meta->n_rays, cap);
+    const float tm = slot_tmin(t_min);
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
         rays[2 * s] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
-        rays[2 * s + 1] = make_float4(R.dx[s], R.dy[s], R.dz[s], 0.0f);
+        rays[2 * s + 1] = make_float4(R.dx[s], R.dy[s], R.dz[s], tm);
     }
 }
 
+// Batched form: slot p = leaf * B + j holds ray j of level-1 node `leaf`
+// (first ray and count as the build recorded them) with its frame's t_min,
+// or the padding marker; every slot's closest-hit key starts at all ones.
+__global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t ray_cap, uint32_t B,
+                                 uint32_t slot_cap, batch_dev bd, float4 *rays, unsigned long long *keys)
+{
+    const uint32_t n = min(meta->n_rays, ray_cap);
+    const uint32_t ns = batch_slots(meta, B, slot_cap);
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < ns; p += gridDim.x * blockDim.x) {
+        const uint32_t leaf = p / B;
+        const uint32_t j = p - leaf * B;
+        const uint32_t info = bd.node_info[leaf];
+        const uint32_t f = info >> INFO_FRAME_SHIFT;
+        const uint32_t s = bd.node_first[leaf] + j;
+        if (j < (info & INFO_COUNT_MASK) && s < n && f < bd.n_frames) {
+            rays[2 * p] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
+            rays[2 * p + 1] = make_float4(R.dx[s], R.dy[s], R.dz[s], slot_tmin(bd.frames[f].t_min));
+        } else {
+            rays[2 * p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            rays[2 * p + 1] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(PAD_SLOT));
+        }
+        keys[p] = ~0ull;
+    }
+}
+
+// Slots in use: the plain form's sorted rays, or B per level-1 node.
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const float4 *__restrict__ tri,
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
-                                             uint64_t cap1, uint32_t B, uint32_t log2G, float t_min0,
-                                             unsigned long long *tkey, crsh_meta *meta, uint32_t ray_cap, uint32_t m,
-                                             batch_dev bd)
+                                             uint64_t cap1, uint32_t B, uint32_t log2G, unsigned long long *keys,
+                                             crsh_meta *meta, uint32_t slot_cap, uint32_t m)
 {
     __shared__ uint64_t s_red[256 / WAVE];
-    const uint32_t n = min(meta->n_rays, ray_cap);
-    const uint32_t n_leaf = meta->level_cnt[0];
+    const uint32_t ns = BATCH ? batch_slots(meta, B, slot_cap) : min(meta->n_rays, slot_cap);
     uint64_t np = meta->n_levels ? meta->pairs[0] : 0;
     np = np < cap1 ? np : cap1;
     const uint32_t l = lane_id();
@@ -76,51 +123,51 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
     uint64_t tests = 0;
-    // Each lane group takes HIT_UNROLL pairs per iteration, a grid stride
-    // apart, and issues all their loads before any test: the pair, triangle
-    // and ray loads of the pairs overlap instead of forming one dependent
-    // chain per pair.
-    const uint64_t step = nwaves * per_wave;
+    // A wave tests HIT_CHUNK consecutive pairs before it moves on by the grid
+    // stride.  Neighbouring level-1 pairs share their triangle (siblings of
+    // one parent pair) or their leaves (the same parent node against the
+    // next triangle), so a wave that walks a run of them finds its rays and
+    // triangles in the vector L1 cache; with a stride of one wave step
+    // instead, the reuse depends on the waves of a workgroup staying in step,
+    // which they stop doing over a long launch.  Each lane group takes
+    // HIT_UNROLL pairs per iteration and issues all their loads before any
+    // test.
     const bool lane_ok = j < B;
-    for (uint64_t q0 = wave * per_wave; q0 < np; q0 += HIT_UNROLL * step) {
-        uint32_t t[HIT_UNROLL], s[HIT_UNROLL];
-        bool ok[HIT_UNROLL];
-        float t_min[HIT_UNROLL];
+    for (uint64_t c0 = wave * HIT_CHUNK; c0 < np; c0 += nwaves * HIT_CHUNK) {
+        const uint64_t c1 = min(np, c0 + HIT_CHUNK);
+        for (uint64_t q0 = c0; q0 < c1; q0 += HIT_UNROLL * per_wave) {
+            uint32_t t[HIT_UNROLL], s[HIT_UNROLL];
+            bool ok[HIT_UNROLL];
 #pragma unroll
-        for (int k = 0; k < HIT_UNROLL; ++k) {
-            const uint64_t q = q0 + slot + k * step;
-            ok[k] = lane_ok && q < np;
-            t[k] = ok[k] ? ptri[q] : 0u;
-            const uint32_t leaf = ok[k] ? pnode[q] : 0u;
-            t_min[k] = t_min0;
-            if constexpr (BATCH) {
-                ok[k] = ok[k] && leaf < n_leaf;
-                const uint32_t info = ok[k] ? bd.node_info[leaf] : 0u;
-                ok[k] = ok[k] && j < (info & INFO_COUNT_MASK);
-                s[k] = ok[k] ? bd.node_first[leaf] + j : 0u;
-                if (ok[k]) t_min[k] = bd.frames[info >> INFO_FRAME_SHIFT].t_min;
-            } else {
+            for (int k = 0; k < HIT_UNROLL; ++k) {
+                const uint64_t q = q0 + slot + k * per_wave;
+                ok[k] = lane_ok && q < c1;
+                t[k] = ok[k] ? ptri[q] : 0u;
+                const uint32_t leaf = ok[k] ? pnode[q] : 0u;
                 s[k] = leaf * B + j;
+                ok[k] = ok[k] && s[k] < ns && t[k] < m;
             }
-            ok[k] = ok[k] && s[k] < n && t[k] < m;
-        }
-        tri_t tr[HIT_UNROLL];
-        float4 ro[HIT_UNROLL], rd[HIT_UNROLL];
+            tri_t tr[HIT_UNROLL];
+            float4 ro[HIT_UNROLL], rd[HIT_UNROLL];
 #pragma unroll
-        for (int k = 0; k < HIT_UNROLL; ++k) {
-            tr[k] = load_tri(tri, ok[k] ? t[k] : 0u);
-            ro[k] = R[2 * (ok[k] ? s[k] : 0u)];
-            rd[k] = R[2 * (ok[k] ? s[k] : 0u) + 1];
-        }
+            for (int k = 0; k < HIT_UNROLL; ++k) {
+                tr[k] = load_tri(tri, ok[k] ? t[k] : 0u);
+                ro[k] = R[2 * (ok[k] ? s[k] : 0u)];
+                rd[k] = R[2 * (ok[k] ? s[k] : 0u) + 1];
+            }
 #pragma unroll
-        for (int k = 0; k < HIT_UNROLL; ++k) {
-            if (!ok[k]) continue;
-            ++tests;
-            float th;
-            if (moller_trumbore_t(mk(ro[k].x, ro[k].y, ro[k].z), mk(rd[k].x, rd[k].y, rd[k].z), t_min[k], ro[k].w,
-                                  tr[k], th)) {
-                unsigned long long key = ((unsigned long long)__float_as_uint(th) << 32) | t[k];
-                atomicMin(&tkey[s[k]], key);
+            for (int k = 0; k < HIT_UNROLL; ++k) {
+                if (!ok[k]) continue;
+                // a padded slot's NaN t_min accepts nothing; it only must not
+                // count as a test (branching on it would hold the triangle
+                // loads behind the ray load)
+                tests += (BATCH && __float_as_uint(rd[k].w) == PAD_SLOT) ? 0u : 1u;
+                float th;
+                if (moller_trumbore_t(mk(ro[k].x, ro[k].y, ro[k].z), mk(rd[k].x, rd[k].y, rd[k].z), rd[k].w, ro[k].w,
+                                      tr[k], th)) {
+                    unsigned long long key = ((unsigned long long)__float_as_uint(th) << 32) | t[k];
+                    atomicMin(&keys[s[k]], key);
+                }
             }
         }
     }
@@ -139,18 +186,30 @@ struct hit_out {
     float *t, *u, *v;
 };
 
+// Batched form: the key of sorted ray s is the smaller of its slot's key and
+// tkey[s] (the level-1 pairs of the fused path test by sorted ray), and is
+// left in tkey[s] as in the plain form.
 template <bool BATCH>
 __global__ void k_hit_final(sorted_rays R, const float4 *__restrict__ tri, const uint32_t *__restrict__ sorted_ids,
-                            float t_min0, const unsigned long long *tkey, hit_out out, const crsh_meta *meta,
-                            uint32_t ray_cap, uint32_t m, batch_dev bd)
+                            float t_min0, unsigned long long *tkey, const unsigned long long *__restrict__ keys,
+                            uint32_t B, uint32_t slot_cap, hit_out out, const crsh_meta *meta, uint32_t ray_cap,
+                            uint32_t m, batch_dev bd)
 {
     const uint32_t n = min(meta->n_rays, ray_cap);
+    const uint32_t ns = BATCH ? batch_slots(meta, B, slot_cap) : 0u;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
-        const unsigned long long key = tkey[s];
+        unsigned long long key = tkey[s];
         const uint32_t id = sorted_ids[s];
         if (id >= ray_cap) continue;    // ids come from the sort: never taken
         float t_min = t_min0;
-        if constexpr (BATCH) t_min = bd.frames[min(bd.ray_frame[id], bd.n_frames - 1)].t_min;
+        if constexpr (BATCH) {
+            const uint32_t f = min(bd.ray_frame[id], bd.n_frames - 1);
+            t_min = bd.frames[f].t_min;
+            const uint32_t rb = bd.fm[f].ray_begin;
+            const uint64_t p = (uint64_t)bd.fm[f].level_base[0] * B + (s - rb);
+            if (s >= rb && p < ns) key = min(key, keys[p]);
+            tkey[s] = key;
+        }
         int32_t best = -1;
         float th = 0.0f, uh = 0.0f, vh = 0.0f;
         if (key != ~0ull && (uint32_t)(key & 0xFFFFFFFFull) < m) {
@@ -203,35 +262,33 @@ void hit_prep_launch(const crsh_scene *scene, float4 *tri, hipStream_t stream)
     }
 }
 
-void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, float4 *rays4, const crsh_pairs *level1,
+void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level1,
                       int32_t bundle, const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta,
                       const batch_dev *bd, int32_t hit_block, hipStream_t stream)
 {
+    const uint32_t g = std::max<uint32_t>(std::min<uint32_t>((hs.slots + 255) / 256, 4096), 1);
+    sorted_rays S{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
+    if (bd)     // also the start value of every slot key, read by k_hit_final
+        k_hit_rays_batch<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, (uint32_t)bundle, hs.slots, *bd,
+                                                hs.rays4, hs.keys);
     if (!level1->capacity) return;
+    if (!bd) k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, t_min, hs.rays4);
     uint32_t log2G = 0;
     while ((1u << log2G) < (uint32_t)bundle) ++log2G;
-    {
-        sorted_rays S{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
-        uint32_t g = std::max<uint32_t>(std::min<uint32_t>((sorted->capacity + 255) / 256, 4096), 1);
-        k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, rays4);
-    }
-    const float4 *R = rays4;
-    const batch_dev b = bd ? *bd : batch_dev{};
     const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
     prof_scope ps("k_hit", stream);
     if (bd)
-        k_hit<true><<<grid, hit_block, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity,
-                                                    (uint32_t)bundle, log2G, t_min, hits->tkey, meta,
-                                                    sorted->capacity, scene->m, b);
+        k_hit<true><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, level1->node, level1->capacity,
+                                                    (uint32_t)bundle, log2G, hs.keys, meta, hs.slots, scene->m);
     else
-        k_hit<false><<<grid, hit_block, 0, stream>>>(R, tri, level1->tri, level1->node, level1->capacity,
-                                                     (uint32_t)bundle, log2G, t_min, hits->tkey, meta,
-                                                     sorted->capacity, scene->m, b);
+        k_hit<false><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, level1->node, level1->capacity,
+                                                     (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
+                                                     scene->m);
 }
 
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
-                      const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, const batch_dev *bd,
-                      hipStream_t stream)
+                      const hit_slots_ws &hs, int32_t bundle, const crsh_scene *scene, float t_min,
+                      crsh_hits *hits, crsh_meta *meta, const batch_dev *bd, hipStream_t stream)
 {
     sorted_rays R{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
     const batch_dev b = bd ? *bd : batch_dev{};
@@ -240,11 +297,11 @@ void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const
     hit_out o{hits->tri, hits->t, hits->u, hits->v};
     prof_scope ps("k_hit_final", stream);
     if (bd)
-        k_hit_final<true><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta, sorted->capacity,
-                                                 scene->m, b);
+        k_hit_final<true><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, hs.keys, (uint32_t)bundle,
+                                                 hs.slots, o, meta, sorted->capacity, scene->m, b);
     else
-        k_hit_final<false><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, o, meta,
-                                                  sorted->capacity, scene->m, b);
+        k_hit_final<false><<<g, 256, 0, stream>>>(R, tri, sorted_ids, t_min, hits->tkey, nullptr, (uint32_t)bundle,
+                                                  0u, o, meta, sorted->capacity, scene->m, b);
 }
 
 crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle, const crsh_pairs *level1,
@@ -289,16 +346,16 @@ crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int3
     crsh_status st = hit_check(sorted, sorted_ids, bundle, level1, scene, hits, meta, ws, hit_block,
                                "crsh_closest_hit");
     if (st != CRSH_OK) return st;
-    if (ws_bytes < hit_ws_bytes(scene->m, sorted->capacity)) {
-        set_error("crsh_closest_hit: workspace too small (%zu < %zu)", ws_bytes,
-                  hit_ws_bytes(scene->m, sorted->capacity));
+    const uint32_t slots = hit_slots(sorted->capacity, bd != nullptr);
+    if (ws_bytes < hit_ws_bytes(scene->m, slots)) {
+        set_error("crsh_closest_hit: workspace too small (%zu < %zu)", ws_bytes, hit_ws_bytes(scene->m, slots));
         return CRSH_ERR_INVALID;
     }
     float4 *tri = (float4 *)ws;
-    float4 *rays4 = (float4 *)((char *)ws + align256((size_t)scene->m * 48));
+    const hit_slots_ws hs = carve_hit_slots((char *)ws + align256((size_t)scene->m * 48), slots);
     hit_prep_launch(scene, tri, stream);
-    hit_pairs_launch(sorted, tri, rays4, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream);
-    hit_final_launch(sorted, sorted_ids, tri, scene, t_min, hits, meta, bd, stream);
+    hit_pairs_launch(sorted, tri, hs, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream);
+    hit_final_launch(sorted, sorted_ids, tri, hs, bundle, scene, t_min, hits, meta, bd, stream);
     return hip_check(hipGetLastError(), "crsh_closest_hit launch");
 }
 

@@ -59,34 +59,24 @@ __device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float t
 }
 
 
-// The same test for the final-test kernel: every operand is used before the
-// first early exit, so the loads that feed it are all in flight together
-// instead of the origin and v0 waiting behind the determinant test.  The
-// accept / reject decisions and the returned t are those of moller_trumbore.
+// The same test for the final-test kernel, without early exits: every
+// quantity of the test is computed and the acceptance conditions are combined
+// at the end, so the whole wave runs one straight sequence (the division
+// included) instead of branching on each condition.  Values and the accept
+// decision are those of moller_trumbore.
 __device__ __forceinline__ bool moller_trumbore_t(f3 O, f3 D, float t_min, float tmax, const tri_t &tr, float &tt)
 {
     const f3 p = cross(D, tr.e2);
     const float det = dot(tr.e1, p);
-    const f3 T = O - tr.v0;
-    const float a = dot(T, p);
-    const float adet = fabsf(det);
-    bool reject = !(adet >= DET_EPS);
-    if (adet <= 0x1p60f) {
-        const bool opposite = (a < 0.0f) != (det < 0.0f);
-        reject = reject || (opposite && fabsf(a) >= 0x1p-60f) ||
-                 (!opposite && fabsf(a) > adet * (1.0f + 0x1p-19f));
-    }
-    if (reject) return false;
     const float inv = 1.0f / det;
-    const float u = a * inv;
-    if (!(u >= 0.0f && u <= 1.0f)) return false;
+    const f3 T = O - tr.v0;
+    const float u = dot(T, p) * inv;
     const f3 q = cross(T, tr.e1);
     const float v = dot(D, q) * inv;
-    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
     const float t = dot(tr.e2, q) * inv;
-    if (!(t > t_min && t < tmax)) return false;
     tt = t;
-    return true;
+    return fabsf(det) >= DET_EPS && (u >= 0.0f && u <= 1.0f) && (v >= 0.0f && u + v <= 1.0f) &&
+           (t > t_min && t < tmax);
 }
 
 }  // namespace crsh

@@ -34,7 +34,7 @@ constexpr uint32_t LH_PER_THREAD = LH_TILE / LH_THREADS;
 
 struct lh_ws {
     float4 *tri;         // packed triangles (v0, e1, e2)
-    float4 *rays4;       // packed sorted rays, for level-1 pairs of a top-level pass
+    hit_slots_ws hs;     // packed ray slots and their keys, for level-1 pairs of a top-level pass
     float4 *tsph;        // triangle bounding spheres
     uint32_t *cnt;       // level-2 pairs per node
     uint32_t *cursor;    // scatter cursors
@@ -45,15 +45,15 @@ struct lh_ws {
     uint32_t *bucket;    // triangle ids grouped by node
 };
 
-static lh_ws carve(void *ws, uint32_t m, uint32_t node_cap, uint64_t cap2, uint32_t rays)
+static lh_ws carve(void *ws, uint32_t m, uint32_t node_cap, uint64_t cap2, uint32_t slots)
 {
     const uint32_t tiles = (node_cap + LH_TILE - 1) / LH_TILE + 1;
     char *w = (char *)ws;
     lh_ws L;
     L.tri = (float4 *)w;
     w += align256((size_t)m * 48);
-    L.rays4 = (float4 *)w;
-    w += align256((size_t)rays * 32);
+    L.hs = carve_hit_slots(w, slots);
+    w += hit_slots_bytes(slots);
     L.tsph = (float4 *)w;
     w += align256((size_t)m * 16);
     L.cnt = (uint32_t *)w;
@@ -73,10 +73,10 @@ static lh_ws carve(void *ws, uint32_t m, uint32_t node_cap, uint64_t cap2, uint3
     return L;
 }
 
-size_t leaf_hit_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t cap2, uint32_t rays)
+size_t leaf_hit_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t cap2, uint32_t slots)
 {
     const uint32_t tiles = (node_cap + LH_TILE - 1) / LH_TILE + 1;
-    return align256((size_t)m * 48) + align256((size_t)rays * 32) + align256((size_t)m * 16) +
+    return align256((size_t)m * 48) + hit_slots_bytes(slots) + align256((size_t)m * 16) +
            align256((size_t)node_cap * 4 + 4) * 2 + align256((size_t)node_cap * 8 + 8) +
            align256((size_t)node_cap * 4 + 4) + align256((size_t)tiles * 16) + align256(16) +
            align256((size_t)cap2 * 4 + 4);
@@ -414,17 +414,18 @@ crsh_status leaf_hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids,
         set_error("crsh_leaf_hit: incomplete node arrays");
         return CRSH_ERR_INVALID;
     }
-    const size_t need = leaf_hit_ws_bytes(scene->m, nodes->capacity, level2->capacity, sorted->capacity);
+    const uint32_t slots = hit_slots(sorted->capacity, bd != nullptr);
+    const size_t need = leaf_hit_ws_bytes(scene->m, nodes->capacity, level2->capacity, slots);
     if (ws_bytes < need) {
         set_error("crsh_leaf_hit: workspace too small (%zu < %zu)", ws_bytes, need);
         return CRSH_ERR_INVALID;
     }
-    const lh_ws L = carve(ws, scene->m, nodes->capacity, level2->capacity, sorted->capacity);
+    const lh_ws L = carve(ws, scene->m, nodes->capacity, level2->capacity, slots);
     const batch_dev b = bd ? *bd : batch_dev{};
     hit_prep_launch(scene, L.tri, stream);
     tri_spheres_launch(scene, 0, scene->m, L.tsph, stream);
     // level-1 pairs stored by a top-level pass at level 1
-    hit_pairs_launch(sorted, L.tri, L.rays4, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream);
+    hit_pairs_launch(sorted, L.tri, L.hs, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream);
 
     const uint64_t cap2 = level2->capacity;
     const uint32_t ncap = nodes->capacity;
@@ -465,7 +466,7 @@ crsh_status leaf_hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids,
         }
 #undef CRSH_LH
     }
-    hit_final_launch(sorted, sorted_ids, L.tri, scene, t_min, hits, meta, bd, stream);
+    hit_final_launch(sorted, sorted_ids, L.tri, L.hs, bundle, scene, t_min, hits, meta, bd, stream);
     return hip_check(hipGetLastError(), "crsh_leaf_hit launch");
 }
 
