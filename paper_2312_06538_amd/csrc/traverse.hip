@@ -377,26 +377,49 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
     const uint64_t ntiles = (nin + LEVEL_TILE - 1) / LEVEL_TILE;
     const uint32_t offp = meta->level_off[parent_level - 1];
     const uint32_t np = meta->level_cnt[parent_level - 1];
+    // Software pipeline over the block's tiles: the pass mask, survivor
+    // count and output offset of the next tile are loaded while the current
+    // tile is compacted, and a tile's parent pairs are requested before its
+    // scan, so no tile waits for two dependent round trips to memory.
+    uint32_t mask_n = 0, cnt_n = 0;
+    uint64_t off_n = 0;
+    if (blockIdx.x < ntiles) {
+        mask_n = S.mask[(uint64_t)blockIdx.x * LEVEL_THREADS + threadIdx.x];
+        cnt_n = S.cnt[blockIdx.x];
+        off_n = S.off[blockIdx.x];
+    }
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        if (S.cnt[tile] == 0) continue;          // uniform over the block
-        const uint32_t mask = S.mask[tile * LEVEL_THREADS + threadIdx.x];
+        const uint32_t mask = mask_n, cnt = cnt_n;
+        const uint64_t base = off_n;
+        const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
+        uint32_t tri[PPT], par[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const bool live = ((mask >> (k * NF)) & ((1u << NF) - 1u)) != 0u && q0 + k < nin;
+            tri[k] = live ? in.tri[q0 + k] : 0u;
+            par[k] = live ? in.node[q0 + k] : 0u;
+        }
+        const uint64_t nt = tile + gridDim.x;
+        if (nt < ntiles) {
+            mask_n = S.mask[nt * LEVEL_THREADS + threadIdx.x];
+            cnt_n = S.cnt[nt];
+            off_n = S.off[nt];
+        }
+        if (cnt == 0) continue;                  // uniform over the block
         uint32_t total;
         const uint32_t ex = block_excl_scan<uint32_t, LEVEL_THREADS / WAVE>((uint32_t)__popc(mask), s_scan, total);
         if (mask) {
-            const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
             uint32_t at = ex;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (((mask >> (k * NF)) & ((1u << NF) - 1u)) == 0u) continue;
-                const uint32_t tri = in.tri[q0 + k];
-                const uint32_t par = in.node[q0 + k];
-                uint32_t first = par * F;
-                if constexpr (BATCH) first = par < np ? bd.node_first[offp + par] : 0u;
+                uint32_t first = par[k] * F;
+                if constexpr (BATCH) first = par[k] < np ? bd.node_first[offp + par[k]] : 0u;
 #pragma unroll
                 for (int j = 0; j < NF; ++j) {
                     if (!((mask >> (k * NF + j)) & 1u)) continue;
                     if (at < TILE_OUT) {
-                        s_tri[at] = tri;
+                        s_tri[at] = tri[k];
                         s_node[at] = first + (uint32_t)j;
                     }
                     ++at;
@@ -404,7 +427,6 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
             }
         }
         __syncthreads();
-        const uint64_t base = S.off[tile];
         const uint32_t n_out = min(total, TILE_OUT);
         for (uint32_t i = threadIdx.x; i < n_out; i += LEVEL_THREADS) {
             const uint64_t at = base + i;
