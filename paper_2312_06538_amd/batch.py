@@ -34,7 +34,7 @@ class DeviceBatch:
     (B, F, levels); hit_block is the workgroup size of the final tests."""
 
     def __init__(self, wls, B, F, levels, hit_block=256, pair_capacity=1 << 22, keep_levels=False,
-                 leaf_hit=False, device="cuda"):
+                 leaf_hit=False, ray_capacity=None, device="cuda"):
         if not 1 <= len(wls) <= X.MAX_FRAMES:
             raise ValueError(f"a batch holds 1..{X.MAX_FRAMES} frames")
         dev = torch.device(device)
@@ -85,6 +85,8 @@ class DeviceBatch:
             tri += sc.m
             mesh += sc.n_mesh
             mat += len(sc.mat_flags)
+        if ray_capacity is not None:     # room beyond the frames' most rays
+            self.cap = max(self.cap, int(ray_capacity))
         if self.cap >= 1 << 30 or tri >= 1 << 32:
             raise ValueError("batch too large")
         self.n_frames, self.n_pix, self.m, self.n_mesh = len(wls), pix, tri, mesh

@@ -9,7 +9,7 @@
 //                 is the same for every key; it also routes the remaining
 //                 passes through the output / alternate buffers so that the
 //                 last pass writes the output;
-//   k_sort_pass   one launch per digit: 4096-key tiles ranked in LDS with
+//   k_sort_pass   one launch per digit: 8192-key tiles ranked in LDS with
 //                 wave ballots (stable), a decoupled look-back across tiles
 //                 per digit, then a coalesced scatter staged through LDS.
 #include "common.hpp"
@@ -17,9 +17,15 @@
 namespace crsh {
 
 constexpr uint32_t SORT_THREADS = 256;
-constexpr uint32_t SORT_WAVES = SORT_THREADS / WAVE;
-constexpr uint32_t SORT_ITEMS = SORT_TILE / SORT_THREADS;   // 16 keys per thread
-constexpr uint32_t SORT_ROUNDS = SORT_ITEMS;                 // 64 keys per wave round
+#ifndef CRSH_SORT_PASS_THREADS
+#define CRSH_SORT_PASS_THREADS 512
+#endif
+#ifndef CRSH_SORT_PASS_ITEMS
+#define CRSH_SORT_PASS_ITEMS 16
+#endif
+constexpr uint32_t PASS_THREADS = CRSH_SORT_PASS_THREADS;  // threads of a pass tile
+constexpr uint32_t PASS_ITEMS = CRSH_SORT_PASS_ITEMS;      // keys per thread
+constexpr uint32_t PASS_TILE = PASS_THREADS * PASS_ITEMS;  // keys per pass tile (8192)
 
 // look-back words: flag in bits 31-30 (1 tile count, 2 inclusive prefix)
 constexpr uint32_t SLB_AGG = 1u << 30;
@@ -138,26 +144,81 @@ __device__ __forceinline__ uint32_t *pick_dst(const sort_bufs &b, uint32_t code,
     return key ? b.kalt : b.valt;
 }
 
+// Digit of element r of a thread for this pass: a key byte, or the frame of
+// the ray (read through the value) for the frame pass.
 template <bool FRAME>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(sort_bufs bufs, const uint32_t *offsets,
-                                                            sort_ctl *ctl, uint32_t *flags, uint32_t pass,
-                                                            uint32_t tiles_cap, const uint32_t *frame_of)
+__device__ __forceinline__ uint32_t pass_digit(uint32_t key, uint32_t val, bool ok, uint32_t shift,
+                                               const uint32_t *frame_of)
 {
-    __shared__ uint32_t s_keys[SORT_TILE];
-    __shared__ uint32_t s_vals[SORT_TILE];
-    __shared__ uint32_t s_wcnt[SORT_WAVES * 256];
+    return FRAME ? (ok ? frame_of[val] & 255u : 0u) : (key >> shift) & 255u;
+}
+
+// Stable rank of a tile inside each wave: rounds in order, lanes in order.
+// Element r of the thread gets its rank among the wave's elements of equal
+// digit (slot[r]); s_wcnt[w * 256 + d] ends as wave w's count of digit d.
+// Peers of equal digit are found with one ballot per digit bit; the lowest
+// peer adds the group's count.
+template <bool FRAME, uint32_t ITEMS>
+__device__ __forceinline__ void rank_tile(const uint32_t *key, const uint32_t *val, uint32_t base, uint32_t n,
+                                          uint32_t shift, const uint32_t *frame_of, uint32_t *s_wcnt,
+                                          uint32_t *slot)
+{
+    const uint32_t w = threadIdx.x / WAVE;
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (uint32_t r = 0; r < ITEMS; ++r) {
+        const uint32_t g = base + r * WAVE + l;
+        const bool ok = g < n;
+        const uint32_t d = pass_digit<FRAME>(key[r], val[r], ok, shift, frame_of);
+        uint64_t peers = ballot(ok);
+#pragma unroll
+        for (uint32_t b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t before = rank_below(peers);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        const uint32_t leader = (uint32_t)__builtin_ctzll(peers | (1ull << 63));
+        const uint32_t wbase = ok ? s_wcnt[w * 256 + d] : 0u;
+        slot[r] = wbase + before;
+        if (ok && l == leader) s_wcnt[w * 256 + d] = wbase + cnt;
+    }
+}
+
+// One radix pass over tiles of THREADS * ITEMS keys.  A tile counts its
+// digits and publishes the counts for the decoupled look-back first, then
+// ranks its keys stably in registers and LDS (while its predecessors publish
+// theirs), reads its global digit offsets from the look-back, and writes out
+// through one LDS buffer in two phases (the array the digit comes from first,
+// then the other), so each phase's stores are runs of consecutive positions
+// per digit.  The run length per digit grows with the tile, and with it the
+// efficiency of the scattered writes.
+template <bool FRAME, uint32_t THREADS, uint32_t ITEMS>
+__global__ __launch_bounds__(THREADS) void k_sort_pass(sort_bufs bufs, const uint32_t *offsets, sort_ctl *ctl,
+                                                       uint32_t *flags, uint32_t pass, uint32_t tiles_cap,
+                                                       const uint32_t *frame_of)
+{
+    constexpr uint32_t TILE = THREADS * ITEMS;
+    constexpr uint32_t WAVES = THREADS / WAVE;
+    static_assert(THREADS >= 256 && THREADS % 256 == 0, "one thread per digit");
+    static_assert(TILE % SORT_TILE == 0, "look-back words are sized for SORT_TILE tiles");
+    __shared__ uint32_t s_buf[TILE];
+    __shared__ uint32_t s_wcnt[WAVES * 256];
+    __shared__ uint32_t s_hist[256];
     __shared__ uint32_t s_base[256];
     __shared__ uint32_t s_start[256];
-    __shared__ uint32_t s_scan[SORT_WAVES];
+    __shared__ uint32_t s_scan[256 / WAVE];
     __shared__ uint32_t s_tile;
 
     const uint32_t src = ctl->src[pass];
     if (src == BUF_SKIP) return;
     const uint32_t dst = ctl->dst[pass];
     const uint32_t n = ctl->n;
-    const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    const uint32_t ntiles = (n + TILE - 1) / TILE;
     if (threadIdx.x == 0) s_tile = atomicAdd(&ctl->tile_ctr[pass], 1u);
-    for (uint32_t i = threadIdx.x; i < SORT_WAVES * 256; i += SORT_THREADS) s_wcnt[i] = 0;
+    for (uint32_t i = threadIdx.x; i < WAVES * 256; i += THREADS) s_wcnt[i] = 0;
+    if (threadIdx.x < 256) s_hist[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     if (tile >= ntiles) return;
@@ -167,99 +228,117 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_pass(sort_bufs bufs, cons
     const uint32_t w = threadIdx.x / WAVE;
     const uint32_t l = lane_id();
     const uint32_t shift = 8 * (pass & 3u);
-    const uint32_t base = tile * SORT_TILE + w * (WAVE * SORT_ROUNDS);
+    const uint32_t base = tile * TILE + w * (WAVE * ITEMS);
+    const uint32_t d = threadIdx.x;
+    uint32_t *fl = flags + ((size_t)pass * tiles_cap) * 256;
 
-    uint32_t key[SORT_ROUNDS], val[SORT_ROUNDS], rank[SORT_ROUNDS];
+    uint32_t key[ITEMS], val[ITEMS], slot[ITEMS];
 #pragma unroll
-    for (uint32_t r = 0; r < SORT_ROUNDS; ++r) {
+    for (uint32_t r = 0; r < ITEMS; ++r) {
         uint32_t g = base + r * WAVE + l;
         bool ok = g < n;
         key[r] = ok ? kin[g] : 0xFFFFFFFFu;
         val[r] = ok ? vin[g] : 0u;
     }
-    // stable rank inside the wave: rounds in order, lanes in order
+    // the tile's digit counts, published before the ranking: the ranking
+    // then overlaps the wait for the predecessors' counts
 #pragma unroll
-    for (uint32_t r = 0; r < SORT_ROUNDS; ++r) {
+    for (uint32_t r = 0; r < ITEMS; ++r) {
         uint32_t g = base + r * WAVE + l;
-        bool ok = g < n;
-        uint32_t d = FRAME ? (ok ? frame_of[val[r]] & 255u : 0u) : (key[r] >> shift) & 255u;
-        uint64_t peers = ballot(ok);
-#pragma unroll
-        for (uint32_t b = 0; b < 8; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t m = ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        uint32_t before = rank_below(peers);
-        uint32_t cnt = (uint32_t)__popcll(peers);
-        uint32_t leader = (uint32_t)__builtin_ctzll(peers | (1ull << 63));
-        uint32_t wbase = ok ? s_wcnt[w * 256 + d] : 0u;
-        rank[r] = wbase + before;
-        if (ok && l == leader) s_wcnt[w * 256 + d] = wbase + cnt;
+        if (g < n) atomicAdd(&s_hist[pass_digit<FRAME>(key[r], val[r], true, shift, frame_of)], 1u);
     }
     __syncthreads();
-    // per digit: offsets of the waves, tile count, tile-local digit start
-    const uint32_t d = threadIdx.x;
     uint32_t run = 0;
-#pragma unroll
-    for (uint32_t ww = 0; ww < SORT_WAVES; ++ww) {
-        uint32_t c = s_wcnt[ww * 256 + d];
-        s_wcnt[ww * 256 + d] = run;
-        run += c;
-    }
-    uint32_t total;
-    uint32_t start = block_excl_scan<uint32_t, SORT_WAVES>(run, s_scan, total);
-    // look-back over the tiles for digit d
-    uint32_t *fl = flags + ((size_t)pass * tiles_cap) * 256;
-    uint32_t excl = 0;
-    if (tile == 0) {
-        __hip_atomic_store(&fl[d], SLB_INC | run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        __hip_atomic_store(&fl[(size_t)tile * 256 + d], SLB_AGG | run, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        int32_t j = (int32_t)tile - 1;
-        while (j >= 0) {
-            uint32_t f = __hip_atomic_load(&fl[(size_t)j * 256 + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t fl2 = f & ~SLB_MASK;
-            if (fl2 == 0) {
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            excl += f & SLB_MASK;
-            if (fl2 == SLB_INC) break;
-            --j;
-        }
-        __hip_atomic_store(&fl[(size_t)tile * 256 + d], SLB_INC | (excl + run), __ATOMIC_RELAXED,
+    if (d < 256) {
+        run = s_hist[d];
+        __hip_atomic_store(&fl[(size_t)tile * 256 + d], (tile == 0 ? SLB_INC : SLB_AGG) | run, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    // global position of tile-local sorted slot q of digit d is s_base[d] + q
-    s_base[d] = offsets[pass * 256 + d] + excl - start;
-    s_start[d] = start;
+    rank_tile<FRAME, ITEMS>(key, val, base, n, shift, frame_of, s_wcnt, slot);
     __syncthreads();
+    // per digit (threads 0..255): offsets of the waves, tile-local digit
+    // start, and the look-back for the tile's global offset of the digit
+    if (d < 256) {
+        uint32_t acc = 0;
 #pragma unroll
-    for (uint32_t r = 0; r < SORT_ROUNDS; ++r) {
+        for (uint32_t ww = 0; ww < WAVES; ++ww) {
+            uint32_t c = s_wcnt[ww * 256 + d];
+            s_wcnt[ww * 256 + d] = acc;
+            acc += c;
+        }
+        const uint32_t inc = wave_incl_scan(run);
+        if (l == WAVE - 1) s_scan[w] = inc;
+    }
+    __syncthreads();
+    if (d < 256) {
+        uint32_t before = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < 256 / WAVE; ++i)
+            if (i < w) before += s_scan[i];
+        const uint32_t start = before + wave_incl_scan(run) - run;
+        uint32_t excl = 0;
+        if (tile > 0) {
+            int32_t j = (int32_t)tile - 1;
+            while (j >= 0) {
+                uint32_t f = __hip_atomic_load(&fl[(size_t)j * 256 + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t fl2 = f & ~SLB_MASK;
+                if (fl2 == 0) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += f & SLB_MASK;
+                if (fl2 == SLB_INC) break;
+                --j;
+            }
+            __hip_atomic_store(&fl[(size_t)tile * 256 + d], SLB_INC | (excl + run), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // global position of tile-local sorted slot q of digit d is s_base[d] + q
+        s_base[d] = offsets[pass * 256 + d] + excl - start;
+        s_start[d] = start;
+    }
+    __syncthreads();
+    // phase 1: the array the digit is read from (keys; values for the frame
+    // digit) into LDS at its tile-local sorted slot, then out; each slot's
+    // global position is kept for phase 2
+#pragma unroll
+    for (uint32_t r = 0; r < ITEMS; ++r) {
         uint32_t g = base + r * WAVE + l;
         if (g < n) {
-            uint32_t dd = FRAME ? frame_of[val[r]] & 255u : (key[r] >> shift) & 255u;
-            uint32_t q = s_start[dd] + s_wcnt[w * 256 + dd] + rank[r];
-            if (q < SORT_TILE) {
-                s_keys[q] = key[r];
-                s_vals[q] = val[r];
-            }
+            uint32_t dd = pass_digit<FRAME>(key[r], val[r], true, shift, frame_of);
+            slot[r] += s_start[dd] + s_wcnt[w * 256 + dd];
+            if (slot[r] < TILE) s_buf[slot[r]] = FRAME ? val[r] : key[r];
         }
     }
     __syncthreads();
     uint32_t *kout = pick_dst(bufs, dst, true);
     uint32_t *vout = pick_dst(bufs, dst, false);
-    const uint32_t tile_n = min(SORT_TILE, n - tile * SORT_TILE);
-    for (uint32_t q = threadIdx.x; q < tile_n; q += SORT_THREADS) {
-        uint32_t k = s_keys[q];
-        uint32_t vq = s_vals[q];
-        uint32_t pos = s_base[FRAME ? frame_of[vq] & 255u : (k >> shift) & 255u] + q;
-        if (pos < n) {
-            kout[pos] = k;
-            vout[pos] = vq;
+    uint32_t *out1 = FRAME ? vout : kout;
+    uint32_t *out2 = FRAME ? kout : vout;
+    const uint32_t tile_n = min(TILE, n - tile * TILE);
+    uint32_t pos[ITEMS];
+#pragma unroll
+    for (uint32_t j = 0; j < ITEMS; ++j) {
+        const uint32_t q = threadIdx.x + j * THREADS;
+        pos[j] = 0xFFFFFFFFu;
+        if (q < tile_n) {
+            const uint32_t x = s_buf[q];
+            pos[j] = s_base[FRAME ? frame_of[x] & 255u : (x >> shift) & 255u] + q;
+            if (pos[j] < n) out1[pos[j]] = x;
         }
+    }
+    __syncthreads();
+    // phase 2: the other array through the same slots
+#pragma unroll
+    for (uint32_t r = 0; r < ITEMS; ++r) {
+        uint32_t g = base + r * WAVE + l;
+        if (g < n && slot[r] < TILE) s_buf[slot[r]] = FRAME ? key[r] : val[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < ITEMS; ++j) {
+        const uint32_t q = threadIdx.x + j * THREADS;
+        if (q < tile_n && pos[j] < n) out2[pos[j]] = s_buf[q];
     }
 }
 
@@ -321,12 +400,15 @@ crsh_status sort_launch(const uint32_t *keys_in, const uint32_t *ids_in, const u
     }
     k_sort_plan<<<1, 256, 0, stream>>>(hist, ctl, meta, capacity, passes);
     sort_bufs b{keys_in, ids_in, keys_out, ids_out, kalt, valt};
+    const uint32_t pass_tiles = (capacity + PASS_TILE - 1) / PASS_TILE;
     for (uint32_t p = 0; p < passes; ++p) {
         prof_scope ps("k_sort_pass", stream);
         if (p < SORT_PASSES)
-            k_sort_pass<false><<<tiles_cap, SORT_THREADS, 0, stream>>>(b, hist, ctl, flags, p, tiles_cap, nullptr);
+            k_sort_pass<false, PASS_THREADS, PASS_ITEMS><<<pass_tiles, PASS_THREADS, 0, stream>>>(
+                b, hist, ctl, flags, p, tiles_cap, nullptr);
         else
-            k_sort_pass<true><<<tiles_cap, SORT_THREADS, 0, stream>>>(b, hist, ctl, flags, p, tiles_cap, frame_of);
+            k_sort_pass<true, PASS_THREADS, PASS_ITEMS><<<pass_tiles, PASS_THREADS, 0, stream>>>(
+                b, hist, ctl, flags, p, tiles_cap, frame_of);
     }
     k_sort_copy<<<256, 256, 0, stream>>>(keys_in, ids_in, keys_out, ids_out, ctl);
     return hip_check(hipGetLastError(), "crsh_sort launch");

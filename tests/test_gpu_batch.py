@@ -138,6 +138,19 @@ def test_batch_matches_oracle_per_frame(hit_block):
         assert int(m.hits[lv - 1]) == v, lv
 
 
+def test_batch_large_ray_capacity_matches_oracle():
+    """A ray capacity of several million slots: every launch (the sort's
+    frame-digit pass included) is sized for the capacity while the frames
+    stay small."""
+    from paper_2312_06538_amd.batch import DeviceBatch
+    wls = frames()
+    db = DeviceBatch(wls, B, F, N, pair_capacity=1 << 20, leaf_hit=False, ray_capacity=(1 << 22) + 777)
+    m = db.run_with_retry()
+    for f, (r, wl) in enumerate(zip(db.frame_results(m), wls)):
+        print(f"[batch large capacity] frame {f}: {r['n']} rays", flush=True)
+        check_frame(r, wl, oracle_of(wl), all_levels=False)
+
+
 def test_batch_fused_last_level_matches_oracle():
     """The batch with the last level fused with the final tests: closest
     hits per frame and the counters summed over frames."""

@@ -55,15 +55,20 @@ def test_hash_bit_exact(name):
     assert _same(g["rays"]["pix"], o["rays"]["pix"])
 
 
-@pytest.mark.parametrize("n,span", [(0, 7), (1, 7), (4095, 1 << 32), (4096, 3), (4097, 1 << 20),
-                                    (50000, 1 << 32), (123457, 97), (300001, 1 << 16)])
-def test_sort_bit_exact(n, span):
-    print(f"[sort] n={n} span={span}", flush=True)
+@pytest.mark.parametrize("n,span,cap", [(0, 7, None), (1, 7, None), (4095, 1 << 32, None), (4096, 3, None),
+                                        (4097, 1 << 20, None), (8191, 1 << 32, None), (8192, 5, None),
+                                        (8193, 1 << 20, None), (50000, 1 << 32, None), (123457, 97, None),
+                                        (300001, 1 << 16, None),
+                                        # several million keys; capacity well above the keys
+                                        ((1 << 22) + 4097, 1 << 32, None), (5000001, 193, None),
+                                        (100000, 1 << 32, 1 << 22), (0, 7, 1 << 22)])
+def test_sort_bit_exact(n, span, cap):
+    print(f"[sort] n={n} span={span} cap={cap}", flush=True)
     rng = np.random.default_rng(n + span % 1000)
     keys = rng.integers(0, span, size=n, dtype=np.uint64).astype(np.uint32)
     ids = np.arange(n, dtype=np.uint32)
     ok, oi = O.sort_rays(keys, ids)
-    gk, gi = _gu().gpu_sort(keys, ids, capacity=n + 1000)
+    gk, gi = _gu().gpu_sort(keys, ids, capacity=cap if cap is not None else n + 1000)
     assert _same(gk, ok) and _same(gi, oi)
 
 
