@@ -190,12 +190,14 @@ def main():
     roof = kern.get(dom)
     other = {k: v for k, v in kern.items() if k != dom}
     # HBM kernels: algorithmic bytes per launch.  Sort pass: key + id read
-    # and written (16 B per key).  Level emit: the 4-byte pass mask of every
-    # two parent pairs, each parent pair with a survivor read (8 B, at most
-    # min(in, out) of them) and every output pair written (8 B).
+    # and written (16 B per key).  Level emit: the pass bits of every parent
+    # pair (one per child slot: the merge factor rounded up to a power of
+    # two), each parent pair with a survivor read (8 B, at most min(in, out)
+    # of them) and every output pair written (8 B).
     n_in = int(m.hits[1]) if nl >= 2 else 0
     n_out = int(m.hits[0])
-    hbm_bytes = {"k_sort_pass": 16 * n, "k_level_emit": 2 * n_in + 8 * min(n_in, n_out) + 8 * n_out}
+    nf = 1 << (wl.F - 1).bit_length()
+    hbm_bytes = {"k_sort_pass": 16 * n, "k_level_emit": n_in * nf // 8 + 8 * min(n_in, n_out) + 8 * n_out}
     hbm = {}
     for name, nbytes in hbm_bytes.items():
         if durs.get(name) and nbytes:

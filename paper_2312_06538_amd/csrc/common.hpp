@@ -192,10 +192,19 @@ constexpr uint32_t SORT_PASSES = 4;       // 8-bit digits of a 32-bit key
 constexpr uint32_t HASH_BLOCK = 256;      // pixels per hash block
 constexpr uint32_t LEVEL_THREADS = 256;   // threads of a traversal tile
 #ifndef CRSH_LEVEL_PPT
-#define CRSH_LEVEL_PPT 2
+#define CRSH_LEVEL_PPT 1
 #endif
-constexpr uint32_t LEVEL_PPT = CRSH_LEVEL_PPT;   // parent pairs per thread
-constexpr uint32_t LEVEL_TILE = LEVEL_THREADS * LEVEL_PPT;   // parent pairs per tile
+#ifndef CRSH_EMIT_PPT
+#define CRSH_EMIT_PPT 2
+#endif
+constexpr uint32_t LEVEL_PPT = CRSH_LEVEL_PPT;   // parent pairs per thread of the count pass
+constexpr uint32_t LEVEL_TILE = LEVEL_THREADS * LEVEL_PPT;   // parent pairs per count tile
+constexpr uint32_t EMIT_PPT = CRSH_EMIT_PPT;     // parent pairs per thread of the emit pass
+constexpr uint32_t EMIT_TILE = LEVEL_THREADS * EMIT_PPT;     // parent pairs per emit tile
+static_assert(EMIT_PPT % LEVEL_PPT == 0, "an emit tile covers whole count tiles");
+// parent pairs per emit thread for NF children per parent: the thread's pass
+// bits (NF per pair) must fit one 32-bit mask word
+constexpr int emit_ppt(int nf) { return (int)EMIT_PPT * nf <= 32 ? (int)EMIT_PPT : 32 / nf; }
 constexpr uint32_t SCAN_TILE_ITEMS = 4096;                 // counts per scan tile
 
 __host__ __device__ constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

@@ -335,7 +335,15 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
         const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
         const uint32_t mask = level_tile_mask<NF, PPT, BATCH>(q0, nin, in, F, nk, offk, na, nb, ns, tsph, m,
                                                               pfirst, pinfo, np, tri, par, tests);
-        S.mask[tile * LEVEL_THREADS + threadIdx.x] = mask;
+        // pass masks packed at NF bits per parent pair: the G threads of a
+        // 32-bit word combine their bits (groups are aligned in the wave)
+        {
+            constexpr uint32_t G = 32 / (PPT * NF);
+            uint32_t word = mask << ((threadIdx.x % G) * PPT * NF);
+#pragma unroll
+            for (uint32_t o = 1; o < G; o <<= 1) word |= __shfl_xor(word, o, WAVE);
+            if (threadIdx.x % G == 0) S.mask[(tile * LEVEL_THREADS + threadIdx.x) / G] = word;
+        }
         const uint32_t c = wave_sum((uint32_t)__popc(mask));
         if (lane_id() == 0) s_red32[threadIdx.x / WAVE] = c;
         __syncthreads();
@@ -359,11 +367,18 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
 // Survivors of a tile are first placed in LDS at their tile-local offsets
 // and then copied out with consecutive lanes writing consecutive pairs, so
 // the stores are coalesced whatever the pass masks.
+// Emit pass: PPT parent pairs per thread, EMIT_TILE per block iteration,
+// covering EMIT_PPT / LEVEL_PPT count tiles (their masks, survivor counts and
+// the first one's output offset).
 template <int NF, int PPT, bool BATCH>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_level, uint32_t F, pair_levels P,
                                                               trav_scratch S, const crsh_meta *meta, batch_dev bd)
 {
-    constexpr uint32_t TILE_OUT = LEVEL_TILE * NF;
+    static_assert(PPT * NF <= 32, "one bit per child");
+    constexpr uint32_t TILE = LEVEL_THREADS * PPT;
+    constexpr uint32_t TILE_OUT = TILE * NF;
+    constexpr uint32_t R = PPT / LEVEL_PPT;    // count tiles per emit tile
+    static_assert(PPT % LEVEL_PPT == 0, "whole count tiles");
     __shared__ uint32_t s_scan[LEVEL_THREADS / WAVE];
     __shared__ uint32_t s_tri[TILE_OUT];
     __shared__ uint32_t s_node[TILE_OUT];
@@ -374,24 +389,38 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
     if (in.tri == nullptr || out.tri == nullptr) return;
     uint64_t nin = meta->pairs[parent_level - 1];
     nin = nin < in.cap ? nin : in.cap;
-    const uint64_t ntiles = (nin + LEVEL_TILE - 1) / LEVEL_TILE;
+    const uint64_t ctiles = (nin + LEVEL_TILE - 1) / LEVEL_TILE;
+    const uint64_t ntiles = (nin + TILE - 1) / TILE;
     const uint32_t offp = meta->level_off[parent_level - 1];
     const uint32_t np = meta->level_cnt[parent_level - 1];
+    // pass mask (NF bits per parent pair, PPT pairs: bits of one packed
+    // word), survivor count and output offset of emit tile T
+    auto tile_head = [&](uint64_t T, uint32_t &mask, uint32_t &cnt, uint64_t &off) {
+        constexpr uint32_t BITS = PPT * NF;
+        const uint64_t p0 = T * TILE + (uint64_t)threadIdx.x * PPT;
+        mask = 0;
+        if (p0 < nin) {
+            const uint64_t bit = p0 * NF;
+            const uint32_t w = S.mask[bit / 32];
+            mask = BITS == 32 ? w : (w >> (uint32_t)(bit % 32)) & ((1u << (BITS % 32)) - 1u);
+        }
+        cnt = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r)
+            if (T * R + r < ctiles) cnt += S.cnt[T * R + r];
+        off = S.off[T * R];
+    };
     // Software pipeline over the block's tiles: the pass mask, survivor
     // count and output offset of the next tile are loaded while the current
     // tile is compacted, and a tile's parent pairs are requested before its
     // scan, so no tile waits for two dependent round trips to memory.
     uint32_t mask_n = 0, cnt_n = 0;
     uint64_t off_n = 0;
-    if (blockIdx.x < ntiles) {
-        mask_n = S.mask[(uint64_t)blockIdx.x * LEVEL_THREADS + threadIdx.x];
-        cnt_n = S.cnt[blockIdx.x];
-        off_n = S.off[blockIdx.x];
-    }
+    if (blockIdx.x < ntiles) tile_head(blockIdx.x, mask_n, cnt_n, off_n);
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint32_t mask = mask_n, cnt = cnt_n;
         const uint64_t base = off_n;
-        const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
+        const uint64_t q0 = tile * TILE + (uint64_t)threadIdx.x * PPT;
         uint32_t tri[PPT], par[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -400,11 +429,7 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
             par[k] = live ? in.node[q0 + k] : 0u;
         }
         const uint64_t nt = tile + gridDim.x;
-        if (nt < ntiles) {
-            mask_n = S.mask[nt * LEVEL_THREADS + threadIdx.x];
-            cnt_n = S.cnt[nt];
-            off_n = S.off[nt];
-        }
+        if (nt < ntiles) tile_head(nt, mask_n, cnt_n, off_n);
         if (cnt == 0) continue;                  // uniform over the block
         uint32_t total;
         const uint32_t ex = block_excl_scan<uint32_t, LEVEL_THREADS / WAVE>((uint32_t)__popc(mask), s_scan, total);
@@ -709,7 +734,8 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
     auto level_pass_launch = [&](int L) {
         const uint64_t tiles = (pairs[L - 1].capacity + LEVEL_TILE - 1) / LEVEL_TILE;
         uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096);
-#define CRSH_EMIT(NF, BT) k_level_emit<NF, LEVEL_PPT, BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta, b)
+#define CRSH_EMIT(NF, BT)                                                                                  \
+    k_level_emit<NF, emit_ppt(NF), BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta, b)
         level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream);
         k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
