@@ -243,22 +243,29 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
 // ----------------------------------------------------------- lower levels
 // Children of a parent: plain, par * F + [0, F) below nk; batch, the range
 // (pfirst[par], count) recorded by the build.
-template <int NF, int PPT, bool BATCH>
-__device__ __forceinline__ uint32_t level_tile_mask(uint64_t q0, uint64_t nin, const pairs_dev &in, uint32_t F,
-                                                    uint32_t nk, uint32_t offk, const float4 *__restrict__ na,
-                                                    const float4 *__restrict__ nb, const float *__restrict__ ns,
-                                                    const float4 *__restrict__ tsph, uint32_t m,
-                                                    const uint32_t *__restrict__ pfirst,
-                                                    const uint32_t *__restrict__ pinfo, uint32_t np, uint32_t *tri,
-                                                    uint32_t *par, uint64_t &tests)
+template <int PPT>
+__device__ __forceinline__ void load_tile_pairs(uint64_t q0, uint64_t nin, const pairs_dev &in, uint32_t *tri,
+                                                uint32_t *par)
 {
-    float4 sp[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const bool ok = q0 + k < nin;
         tri[k] = ok ? in.tri[q0 + k] : 0u;
         par[k] = ok ? in.node[q0 + k] : 0xFFFFFFFFu;
     }
+}
+
+// Eq. 9 tests of a thread's PPT parent pairs (tri, par; par = ~0 for none)
+// against their children: one bit per (pair, child) that passes.
+template <int NF, int PPT, bool BATCH>
+__device__ __forceinline__ uint32_t level_tile_mask(uint32_t F, uint32_t nk, uint32_t offk,
+                                                    const float4 *__restrict__ na, const float4 *__restrict__ nb,
+                                                    const float *__restrict__ ns, const float4 *__restrict__ tsph,
+                                                    uint32_t m, const uint32_t *__restrict__ pfirst,
+                                                    const uint32_t *__restrict__ pinfo, uint32_t np,
+                                                    const uint32_t *tri, const uint32_t *par, uint64_t &tests)
+{
+    float4 sp[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) sp[k] = tsph[tri[k] < m ? tri[k] : 0u];
     uint32_t cfirst[PPT], ccount[PPT];
@@ -313,7 +320,7 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
 {
     static_assert(NF * PPT <= 32, "one bit per child test");
     static_assert(LEVEL_THREADS * PPT == LEVEL_TILE, "tile size");
-    __shared__ uint32_t s_red32[LEVEL_THREADS / WAVE];
+    __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
     __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
     const uint32_t nl = meta->n_levels;
     if ((uint32_t)parent_level > nl) return;
@@ -330,11 +337,28 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     const uint32_t *pfirst = BATCH ? bd.node_first + offp : nullptr;
     const uint32_t *pinfo = BATCH ? bd.node_info + offp : nullptr;
     uint64_t tests = 0;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // the next tile's parent pairs are loaded while this tile is tested
+    uint32_t tri_n[PPT], par_n[PPT];
+    if (CRSH_COUNT_PREFETCH && blockIdx.x < ntiles)
+        load_tile_pairs<PPT>((uint64_t)blockIdx.x * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri_n, par_n);
+    uint32_t parity = 0;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
         uint32_t tri[PPT], par[PPT];
         const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
-        const uint32_t mask = level_tile_mask<NF, PPT, BATCH>(q0, nin, in, F, nk, offk, na, nb, ns, tsph, m,
-                                                              pfirst, pinfo, np, tri, par, tests);
+        if (CRSH_COUNT_PREFETCH) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                tri[k] = tri_n[k];
+                par[k] = par_n[k];
+            }
+            if (tile + gridDim.x < ntiles)
+                load_tile_pairs<PPT>((tile + gridDim.x) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri_n,
+                                     par_n);
+        } else {
+            load_tile_pairs<PPT>(q0, nin, in, tri, par);
+        }
+        const uint32_t mask = level_tile_mask<NF, PPT, BATCH>(F, nk, offk, na, nb, ns, tsph, m, pfirst, pinfo, np,
+                                                              tri, par, tests);
         // pass masks packed at NF bits per parent pair: the G threads of a
         // 32-bit word combine their bits (groups are aligned in the wave)
         {
@@ -344,15 +368,17 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
             for (uint32_t o = 1; o < G; o <<= 1) word |= __shfl_xor(word, o, WAVE);
             if (threadIdx.x % G == 0) S.mask[(tile * LEVEL_THREADS + threadIdx.x) / G] = word;
         }
+        // survivors of the tile: wave sums in alternating LDS slots, so one
+        // barrier per tile suffices (a slot is reused two tiles later, after
+        // the next tile's barrier)
         const uint32_t c = wave_sum((uint32_t)__popc(mask));
-        if (lane_id() == 0) s_red32[threadIdx.x / WAVE] = c;
+        if (lane_id() == 0) s_red32[parity][threadIdx.x / WAVE] = c;
         __syncthreads();
         if (threadIdx.x == 0) {
             uint32_t t = 0;
-            for (int w = 0; w < LEVEL_THREADS / WAVE; ++w) t += s_red32[w];
+            for (int w = 0; w < LEVEL_THREADS / WAVE; ++w) t += s_red32[parity][w];
             S.cnt[tile] = t;
         }
-        __syncthreads();
     }
     tests = wave_sum(tests);
     if (lane_id() == 0) s_red[threadIdx.x / WAVE] = tests;
