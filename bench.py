@@ -35,6 +35,43 @@ NODE_OPS = 30
 HBM_PEAK_GBS = 8000.0
 
 
+# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE; calibrated against a copy of known size).
+# The summary records a hash of the kernel's source files; a figure taken
+# before the sources changed is not reported.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_hit_hbm_traffic_refl_1024.md")
+TRAFFIC_SOURCES = {"k_hit": ["paper_2312_06538_amd/csrc/hit.hip", "paper_2312_06538_amd/csrc/intersect.hpp",
+                             "paper_2312_06538_amd/csrc/batch.hpp", "paper_2312_06538_amd/csrc/common.hpp",
+                             "include/crsh.h"]}
+
+
+def sources_sha256(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES[kernel]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """(bytes per launch, note) from the traffic summary, or (None, why)."""
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return None, "no traffic summary"
+    for ln in lines:
+        if not ln.startswith("bench-traffic:"):
+            continue
+        kv = dict(f.split("=", 1) for f in ln.split()[1:])
+        if kv.get("kernel") != kernel or kv.get("workload") != workload:
+            continue
+        if kv.get("sources") != sources_sha256(kernel):
+            return None, "counters predate the kernel's current sources"
+        return int(kv["bytes"]), f"rocprofv3 FETCH_SIZE + WRITE_SIZE, {os.path.basename(TRAFFIC_PROFILE)}"
+    return None, "no counters for this kernel and workload"
+
+
 def hip():
     return ctypes.CDLL("libamdhip64.so.7")
 
@@ -188,6 +225,9 @@ def main():
                           "launches_timed": len(durs[name])}
     dom = max(kern, key=lambda k: kern[k]["kernel_ms"]) if kern else None
     roof = kern.get(dom)
+    if roof is not None and dom in TRAFFIC_SOURCES:
+        roof["traffic"], roof["traffic_source"] = measured_traffic(dom, args.workload + ("" if args.variant == "crsh"
+                                                                                           else "_" + args.variant))
     other = {k: v for k, v in kern.items() if k != dom}
     # HBM kernels: algorithmic bytes per launch.  Sort pass: key + id read
     # and written (16 B per key).  Level emit: the pass bits of every parent
