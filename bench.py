@@ -136,7 +136,7 @@ def cpu_baseline(wl, n_sample_top=16):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="refl_1024",
                     choices=["shadow_128", "refl_1024", "mixed_1080p", "adjoint_512", "batch_64"])

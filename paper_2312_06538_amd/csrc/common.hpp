@@ -202,9 +202,6 @@ constexpr uint32_t LEVEL_TILE = LEVEL_THREADS * LEVEL_PPT;   // parent pairs per
 constexpr uint32_t EMIT_PPT = CRSH_EMIT_PPT;     // parent pairs per thread of the emit pass
 constexpr uint32_t EMIT_TILE = LEVEL_THREADS * EMIT_PPT;     // parent pairs per emit tile
 static_assert(EMIT_PPT % LEVEL_PPT == 0, "an emit tile covers whole count tiles");
-#ifndef CRSH_COUNT_PREFETCH
-#define CRSH_COUNT_PREFETCH 1
-#endif
 // parent pairs per emit thread for NF children per parent: the thread's pass
 // bits (NF per pair) must fit one 32-bit mask word
 constexpr int emit_ppt(int nf) { return (int)EMIT_PPT * nf <= 32 ? (int)EMIT_PPT : 32 / nf; }

@@ -62,24 +62,37 @@ __global__ void k_sort_clear(uint32_t *hist, sort_ctl *ctl, uint32_t *flags, con
     if (g < sizeof(sort_ctl) / 4) ((uint32_t *)ctl)[g] = 0;
 }
 
+// The digit histograms of every pass in one read of the keys: a block's
+// keys are all loaded before any is counted (the counting is LDS atomics;
+// the loads must not wait on them one by one).
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t *keys, const uint32_t *vals,
                                                             const uint32_t *frame_of, const crsh_meta *meta,
                                                             uint32_t *hist, uint32_t cap)
 {
+    constexpr uint32_t PER = SORT_TILE / SORT_THREADS;
     __shared__ uint32_t h[MAX_PASSES * 256];
     uint32_t n = min(meta->n_rays, cap);
     uint32_t base = blockIdx.x * SORT_TILE;
     if (base >= n) return;
     for (uint32_t i = threadIdx.x; i < MAX_PASSES * 256; i += SORT_THREADS) h[i] = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < SORT_TILE; i += SORT_THREADS) {
-        uint32_t g = base + i;
-        if (g < n) {
-            uint32_t k = keys[g];
+    uint32_t k[PER], f[PER];
 #pragma unroll
-            for (uint32_t p = 0; p < SORT_PASSES; ++p) atomicAdd(&h[p * 256 + ((k >> (8 * p)) & 255u)], 1u);
-            if (frame_of) atomicAdd(&h[SORT_PASSES * 256 + (frame_of[vals[g]] & 255u)], 1u);
-        }
+    for (uint32_t r = 0; r < PER; ++r) {
+        const uint32_t g = base + r * SORT_THREADS + threadIdx.x;
+        k[r] = g < n ? keys[g] : 0u;
+        f[r] = (frame_of && g < n) ? vals[g] : 0u;
+    }
+    if (frame_of) {
+#pragma unroll
+        for (uint32_t r = 0; r < PER; ++r) f[r] = base + r * SORT_THREADS + threadIdx.x < n ? frame_of[f[r]] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t r = 0; r < PER; ++r) {
+        if (base + r * SORT_THREADS + threadIdx.x >= n) continue;
+#pragma unroll
+        for (uint32_t p = 0; p < SORT_PASSES; ++p) atomicAdd(&h[p * 256 + ((k[r] >> (8 * p)) & 255u)], 1u);
+        if (frame_of) atomicAdd(&h[SORT_PASSES * 256 + (f[r] & 255u)], 1u);
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < MAX_PASSES * 256; i += SORT_THREADS)

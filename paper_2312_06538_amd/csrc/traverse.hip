@@ -256,54 +256,63 @@ __device__ __forceinline__ void load_tile_pairs(uint64_t q0, uint64_t nin, const
 }
 
 // Eq. 9 tests of a thread's PPT parent pairs (tri, par; par = ~0 for none)
-// against their children: one bit per (pair, child) that passes.
-template <int NF, int PPT, bool BATCH>
-__device__ __forceinline__ uint32_t level_tile_mask(uint32_t F, uint32_t nk, uint32_t offk,
-                                                    const float4 *__restrict__ na, const float4 *__restrict__ nb,
-                                                    const float *__restrict__ ns, const float4 *__restrict__ tsph,
-                                                    uint32_t m, const uint32_t *__restrict__ pfirst,
-                                                    const uint32_t *__restrict__ pinfo, uint32_t np,
-                                                    const uint32_t *tri, const uint32_t *par, uint64_t &tests)
-{
+// against their children, in two steps for a pipeline over tiles: the loads
+// of a tile's triangle spheres and child nodes are issued one iteration
+// before the tests that use them (one bit per (pair, child) that passes).
+template <int NF, int PPT>
+struct child_set {
     float4 sp[PPT];
+    float4 A[PPT][NF], Bv[PPT][NF];
+    float Sg[PPT][NF];
+    uint32_t okm;                          // bit k * NF + j: child j of pair k exists
+};
+
+template <int NF, int PPT, bool BATCH>
+__device__ __forceinline__ void load_children(child_set<NF, PPT> &c, uint32_t F, uint32_t nk, uint32_t offk,
+                                              const float4 *__restrict__ na, const float4 *__restrict__ nb,
+                                              const float *__restrict__ ns, const float4 *__restrict__ tsph,
+                                              uint32_t m, const uint32_t *__restrict__ pfirst,
+                                              const uint32_t *__restrict__ pinfo, uint32_t np, const uint32_t *tri,
+                                              const uint32_t *par)
+{
+    c.okm = 0;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) sp[k] = tsph[tri[k] < m ? tri[k] : 0u];
-    uint32_t cfirst[PPT], ccount[PPT];
-    if constexpr (BATCH) {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
+    for (int k = 0; k < PPT; ++k) {
+        c.sp[k] = tsph[tri[k] < m ? tri[k] : 0u];
+        uint32_t cfirst, ccount;
+        if constexpr (BATCH) {
             const bool ok = par[k] < np;
-            cfirst[k] = ok ? pfirst[par[k]] : 0u;
-            ccount[k] = ok ? pinfo[par[k]] & INFO_COUNT_MASK : 0u;
+            cfirst = ok ? pfirst[par[k]] : 0u;
+            ccount = ok ? pinfo[par[k]] & INFO_COUNT_MASK : 0u;
+        } else {
+            cfirst = par[k] * F;
+            ccount = par[k] != 0xFFFFFFFFu ? F : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < NF; ++j) {
+            const uint32_t ch = cfirst + (uint32_t)j;
+            const bool ok = (uint32_t)j < ccount && ch < nk;
+            if (ok) c.okm |= 1u << (k * NF + j);
+            const uint32_t g = offk + (ok ? ch : 0u);
+            c.A[k][j] = na[g];
+            c.Bv[k][j] = nb[g];
+            c.Sg[k][j] = ns[g];
         }
     }
+}
+
+template <int NF, int PPT>
+__device__ __forceinline__ uint32_t test_children(const child_set<NF, PPT> &c, uint64_t &tests)
+{
     uint32_t mask = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        float4 A[NF], Bv[NF];
-        float Sg[NF];
-        bool ok[NF];
+        const f3 Pc = mk(c.sp[k].x, c.sp[k].y, c.sp[k].z);
 #pragma unroll
         for (int j = 0; j < NF; ++j) {
-            uint32_t ch;
-            if constexpr (BATCH) {
-                ch = cfirst[k] + (uint32_t)j;
-                ok[j] = (uint32_t)j < ccount[k] && ch < nk;
-            } else {
-                ch = par[k] * F + (uint32_t)j;
-                ok[j] = par[k] != 0xFFFFFFFFu && (uint32_t)j < F && ch < nk;
-            }
-            const uint32_t g = offk + (ok[j] ? ch : 0u);
-            A[j] = na[g];
-            Bv[j] = nb[g];
-            Sg[j] = ns[g];
-        }
-        const f3 Pc = mk(sp[k].x, sp[k].y, sp[k].z);
-#pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            if (!ok[j]) continue;
+            if (!((c.okm >> (k * NF + j)) & 1u)) continue;
             ++tests;
-            if (packed_meets(A[j], Bv[j], Sg[j], Pc, sp[k].w)) mask |= 1u << (k * NF + j);
+            if (packed_meets(c.A[k][j], c.Bv[k][j], c.Sg[k][j], Pc, c.sp[k].w)) mask |= 1u << (k * NF + j);
         }
     }
     return mask;
@@ -337,28 +346,30 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     const uint32_t *pfirst = BATCH ? bd.node_first + offp : nullptr;
     const uint32_t *pinfo = BATCH ? bd.node_info + offp : nullptr;
     uint64_t tests = 0;
-    // the next tile's parent pairs are loaded while this tile is tested
+    // two-stage pipeline: tile i is tested with the child nodes loaded
+    // during tile i - 1, while tile i + 1's children and tile i + 2's parent
+    // pairs are requested
     uint32_t tri_n[PPT], par_n[PPT];
-    if (CRSH_COUNT_PREFETCH && blockIdx.x < ntiles)
-        load_tile_pairs<PPT>((uint64_t)blockIdx.x * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri_n, par_n);
+    child_set<NF, PPT> cs;
+    const uint64_t stride = gridDim.x;
+    if (blockIdx.x < ntiles) {
+        uint32_t tri0[PPT], par0[PPT];
+        load_tile_pairs<PPT>((uint64_t)blockIdx.x * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri0, par0);
+        load_children<NF, PPT, BATCH>(cs, F, nk, offk, na, nb, ns, tsph, m, pfirst, pinfo, np, tri0, par0);
+        if (blockIdx.x + stride < ntiles)
+            load_tile_pairs<PPT>((blockIdx.x + stride) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri_n,
+                                 par_n);
+    }
     uint32_t parity = 0;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
-        uint32_t tri[PPT], par[PPT];
-        const uint64_t q0 = tile * LEVEL_TILE + (uint64_t)threadIdx.x * PPT;
-        if (CRSH_COUNT_PREFETCH) {
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                tri[k] = tri_n[k];
-                par[k] = par_n[k];
-            }
-            if (tile + gridDim.x < ntiles)
-                load_tile_pairs<PPT>((tile + gridDim.x) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri_n,
-                                     par_n);
-        } else {
-            load_tile_pairs<PPT>(q0, nin, in, tri, par);
+        const child_set<NF, PPT> cur = cs;
+        if (tile + stride < ntiles) {
+            load_children<NF, PPT, BATCH>(cs, F, nk, offk, na, nb, ns, tsph, m, pfirst, pinfo, np, tri_n, par_n);
+            if (tile + 2 * stride < ntiles)
+                load_tile_pairs<PPT>((tile + 2 * stride) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in,
+                                     tri_n, par_n);
         }
-        const uint32_t mask = level_tile_mask<NF, PPT, BATCH>(F, nk, offk, na, nb, ns, tsph, m, pfirst, pinfo, np,
-                                                              tri, par, tests);
+        const uint32_t mask = test_children<NF, PPT>(cur, tests);
         // pass masks packed at NF bits per parent pair: the G threads of a
         // 32-bit word combine their bits (groups are aligned in the wave)
         {
@@ -705,8 +716,6 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
     w += align256((items / SCAN_TILE + 2) * 8);
     S.scan_ctr = (uint32_t *)w;
 
-    node_arrays nd{nodes->cx, nodes->cy, nodes->cz, nodes->r, nodes->ax, nodes->ay, nodes->az,
-                   nodes->c, nodes->tan, nodes->sec};
     int nf = 2;
     while (nf < merge) nf *= 2;
     pair_levels P;
