@@ -140,6 +140,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="refl_1024",
                     choices=["shadow_128", "refl_1024", "mixed_1080p", "adjoint_512", "batch_64"])
+    ap.add_argument("--pairs", default="arrays", choices=["arrays", "packed"],
+                    help="pair storage: two uint32 arrays, or one packed word per pair over triangle batches of "
+                         "at most 2^14 triangles (crsh_traverse_packed)")
     ap.add_argument("--variant", default="crsh", choices=["crsh", "unsorted"],
                     help="unsorted: the comparison hierarchy without ray sorting, whole-mesh culling or a "
                          "level cap, on the same inputs")
@@ -179,11 +182,12 @@ def main():
           f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
     fr = P.DeviceFrame(wl)
     bf = P.Buffers(fr, 1 << 24, keep_levels=False)
-    bf, m = P.run_with_retry(fr, bf)
+    packed = args.pairs == "packed"
+    bf, m = P.run_with_retry(fr, bf, packed=packed)
     print(f"[bench] sized: N={m.n_rays} levels={m.n_levels} pair capacity={bf.pair_capacity}",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        P.run_frame(fr, bf)
+        P.run_frame(fr, bf, packed=packed)
     torch.cuda.synchronize()
     ev = HipEvents(args.steps)
     # kernels timed on alternate steps: the two heaviest (the final tests and
@@ -196,14 +200,15 @@ def main():
     for k in range(args.steps):
         a, b = ev.pair(k)
         name, occ = probes[k % len(probes)]
-        X.crsh_profile_next(name, occ, a, b)
-        P.run_frame(fr, bf)
+        if not packed:           # packed: one launch per triangle batch, no single kernel to time
+            X.crsh_profile_next(name, occ, a, b)
+        P.run_frame(fr, bf, packed=packed)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     m, st = P.read_meta(bf)
     assert st == X.OK, X.last_error()
     durs = {}
-    for k in range(args.steps):
+    for k in range(0 if packed else args.steps):
         v = ev.ms(k)
         if v is not None:
             durs.setdefault(probes[k % len(probes)][0], []).append(v)
@@ -256,7 +261,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl.W}x{wl.H} shadow+reflection, "
                                f"{wl.scene.n_mesh} meshes, {wl.scene.m} triangles, B={wl.B} F={wl.F} n={wl.n}",
-                   "rays": n, "triangles": wl.scene.m, "seed": args.seed, "variant": args.variant},
+                   "rays": n, "triangles": wl.scene.m, "seed": args.seed, "variant": args.variant,
+                   "pairs": args.pairs},
         "tests": {"node_tests": node_tests, "final_ray_tri_tests": final, "total": node_tests + final,
                   "brute_force": brute, "frac_of_brute": round((node_tests + final) / brute, 5),
                   "mesh_tests": int(m.mesh_tests), "levels": nl},

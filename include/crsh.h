@@ -58,6 +58,8 @@ typedef enum crsh_status {
 #define CRSH_OVERFLOW_PAIRS 4u   /* a pair level exceeded its crsh_pairs.capacity */
 #define CRSH_OVERFLOW_ITEMS 8u   /* batched form: more top-level (node, mesh) items than
                                     crsh_batch.top_item_capacity */
+#define CRSH_OVERFLOW_PACKED 16u /* packed pairs: a level has more nodes than
+                                    CRSH_PACKED_MAX_NODES (its pairs are not valid) */
 
 /* ray-type bits of crsh_raygen.ray_types */
 #define CRSH_RAY_SHADOW 1u
@@ -162,6 +164,18 @@ typedef struct crsh_pairs {
     uint64_t capacity;
 } crsh_pairs;
 
+/* The same pairs packed into one 32-bit word each, as Sec. 3.3.7 stores them:
+ * node id (local to its level) in bits 31-14, triangle id minus the first
+ * triangle of the batch in bits 13-0.  A triangle batch therefore holds at
+ * most 2^14 triangles and a level at most 2^18 nodes. */
+#define CRSH_PACKED_TRI_BITS 14
+#define CRSH_PACKED_MAX_TRIS (1u << CRSH_PACKED_TRI_BITS)
+#define CRSH_PACKED_MAX_NODES (1u << (32 - CRSH_PACKED_TRI_BITS))
+typedef struct crsh_packed_pairs {
+    uint32_t *pair;
+    uint64_t capacity;
+} crsh_packed_pairs;
+
 /* Closest hits.  tkey is scratch in SORTED order (one 64-bit word per sorted
  * ray: float bits of t above the triangle id); tri/t/u/v are the results by
  * ray id: triangle (-1 on a miss), distance and barycentrics (0 on a miss). */
@@ -251,6 +265,20 @@ crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *scene,
                           const crsh_pairs pairs[CRSH_MAX_LEVELS], crsh_meta *meta,
                           void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Stage 4 with packed pairs (Sec. 3.3.7's encoding) for one triangle batch
+ * [tri_begin, tri_end) of at most CRSH_PACKED_MAX_TRIS triangles: the same
+ * tests, counters and pair order as crsh_traverse over the same batch, every
+ * pair stored as one crsh_packed_pairs word (4 bytes instead of 8).
+ * Errors: CRSH_ERR_INVALID for a batch over CRSH_PACKED_MAX_TRIS triangles
+ * (nothing launched); a hierarchy level with more than CRSH_PACKED_MAX_NODES
+ * nodes sets CRSH_OVERFLOW_PACKED in meta->status on the device, and the
+ * pairs of that call are then not valid.  Workspace: crsh_workspace_size. */
+crsh_status crsh_traverse_packed(const crsh_nodes *nodes, const crsh_scene *scene,
+                                 uint32_t tri_begin, uint32_t tri_end,
+                                 int32_t bundle, int32_t merge,
+                                 const crsh_packed_pairs pairs[CRSH_MAX_LEVELS], crsh_meta *meta,
+                                 void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Stage 4 without its last level pass: as crsh_traverse, but the level-1
  * pairs that descend from level 2 are not formed; crsh_leaf_hit forms and
  * consumes them on chip.  pairs[0] still needs storage: a hierarchy whose top
@@ -275,6 +303,16 @@ crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t *sorted_ids
                              const crsh_scene *scene, float t_min,
                              crsh_hits *hits, crsh_meta *meta,
                              void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Stage 5 on the packed level-1 pairs of crsh_traverse_packed: tri_begin is
+ * that call's first triangle.  Same results as crsh_closest_hit on the
+ * unpacked pairs; results merge across triangle batches through hits->tkey
+ * (clear it with crsh_hits_reset before the first batch). */
+crsh_status crsh_closest_hit_packed(const crsh_rays *sorted, const uint32_t *sorted_ids,
+                                    int32_t bundle, const crsh_packed_pairs *level1, uint32_t tri_begin,
+                                    const crsh_scene *scene, float t_min,
+                                    crsh_hits *hits, crsh_meta *meta,
+                                    void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Stages 4 (level 1, Eq. 9) and 5 (Sec. 3.3.8) fused, after
  * crsh_traverse_upper: the level-2 pairs pairs[1] are grouped by node; for

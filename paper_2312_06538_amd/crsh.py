@@ -19,7 +19,10 @@ MAX_MERGE = 16
 MAX_FRAMES = 256
 
 OK, ERR_INVALID, ERR_CAPACITY, ERR_HIP = 0, 1, 2, 3
-OVERFLOW_RAYS, OVERFLOW_NODES, OVERFLOW_PAIRS, OVERFLOW_ITEMS = 1, 2, 4, 8
+OVERFLOW_RAYS, OVERFLOW_NODES, OVERFLOW_PAIRS, OVERFLOW_ITEMS, OVERFLOW_PACKED = 1, 2, 4, 8, 16
+PACKED_TRI_BITS = 14
+PACKED_MAX_TRIS = 1 << PACKED_TRI_BITS
+PACKED_MAX_NODES = 1 << (32 - PACKED_TRI_BITS)
 RAY_SHADOW, RAY_REFLECT, RAY_REFRACT = 1, 2, 4
 KEY_TYPE_ONLY = 0x100
 KEY_SPHERICAL = 0x200
@@ -74,11 +77,16 @@ class Pairs(C.Structure):
     _fields_ = [("tri", vp), ("node", vp), ("capacity", C.c_uint64)]
 
 
+class PackedPairs(C.Structure):
+    _fields_ = [("pair", vp), ("capacity", C.c_uint64)]
+
+
 class Hits(C.Structure):
     _fields_ = [("tkey", vp), ("tri", vp), ("t", vp), ("u", vp), ("v", vp), ("capacity", C.c_uint32)]
 
 
 PairTable = Pairs * MAX_LEVELS
+PackedPairTable = PackedPairs * MAX_LEVELS
 
 
 class Frame(C.Structure):
@@ -146,6 +154,12 @@ def lib():
         L.crsh_traverse.restype = st
         L.crsh_traverse.argtypes = [C.POINTER(Nodes), C.POINTER(Scene), C.c_uint32, C.c_uint32, C.c_int32,
                                     C.c_int32, PairTable, vp, vp, C.c_size_t, vp]
+        L.crsh_traverse_packed.restype = st
+        L.crsh_traverse_packed.argtypes = [C.POINTER(Nodes), C.POINTER(Scene), C.c_uint32, C.c_uint32, C.c_int32,
+                                           C.c_int32, PackedPairTable, vp, vp, C.c_size_t, vp]
+        L.crsh_closest_hit_packed.restype = st
+        L.crsh_closest_hit_packed.argtypes = [C.POINTER(Rays), vp, C.c_int32, C.POINTER(PackedPairs), C.c_uint32,
+                                              C.POINTER(Scene), C.c_float, C.POINTER(Hits), vp, vp, C.c_size_t, vp]
         L.crsh_traverse_upper.restype = st
         L.crsh_traverse_upper.argtypes = [C.POINTER(Nodes), C.POINTER(Scene), C.c_uint32, C.c_uint32, C.c_int32,
                                           C.c_int32, PairTable, vp, vp, C.c_size_t, vp]
@@ -234,6 +248,18 @@ def crsh_build(rays, sorted_ids, bundle, merge, levels, nodes, sorted_rays, meta
 def crsh_traverse(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, stream):
     return _check(lib().crsh_traverse(C.byref(nodes), C.byref(scene), tri_begin, tri_end, bundle, merge, pairs,
                                       meta, ws, ws_bytes, stream))
+
+
+def crsh_traverse_packed(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, stream):
+    return _check(lib().crsh_traverse_packed(C.byref(nodes), C.byref(scene), tri_begin, tri_end, bundle, merge,
+                                             pairs, meta, ws, ws_bytes, stream))
+
+
+def crsh_closest_hit_packed(sorted_rays, sorted_ids, bundle, level1, tri_begin, scene, t_min, hits, meta, ws,
+                            ws_bytes, stream):
+    return _check(lib().crsh_closest_hit_packed(C.byref(sorted_rays), sorted_ids, bundle, C.byref(level1),
+                                                tri_begin, C.byref(scene), t_min, C.byref(hits), meta, ws,
+                                                ws_bytes, stream))
 
 
 def crsh_traverse_upper(nodes, scene, tri_begin, tri_end, bundle, merge, pairs, meta, ws, ws_bytes, stream):

@@ -255,7 +255,7 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
 crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
                        const crsh_pairs *level1, const crsh_scene *scene, float t_min, crsh_hits *hits,
                        crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t hit_block,
-                       hipStream_t stream);
+                       hipStream_t stream, bool packed = false, uint32_t tri_base = 0);
 crsh_status leaf_hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle, int32_t merge,
                             const crsh_nodes *nodes, const crsh_pairs *level1, const crsh_pairs *level2,
                             const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, void *ws,
@@ -267,7 +267,8 @@ crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32
 void hit_prep_launch(const crsh_scene *scene, float4 *tri, hipStream_t stream);
 void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level1,
                       int32_t bundle, const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta,
-                      const batch_dev *bd, int32_t hit_block, hipStream_t stream);
+                      const batch_dev *bd, int32_t hit_block, hipStream_t stream, bool packed = false,
+                      uint32_t tri_base = 0);
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
                       const hit_slots_ws &hs, int32_t bundle, const crsh_scene *scene, float t_min,
                       crsh_hits *hits, crsh_meta *meta, const batch_dev *bd, hipStream_t stream);

@@ -104,12 +104,14 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
     }
 }
 
-// Slots in use: the plain form's sorted rays, or B per level-1 node.
-template <bool BATCH>
+// Slots in use: the plain form's sorted rays, or B per level-1 node.  PACKED:
+// the level-1 pairs are packed words in ptri (node above the low
+// CRSH_PACKED_TRI_BITS, triangle minus tri_base below; pnode unused).
+template <bool BATCH, bool PACKED>
 __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const float4 *__restrict__ tri,
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
                                              uint64_t cap1, uint32_t B, uint32_t log2G, unsigned long long *keys,
-                                             crsh_meta *meta, uint32_t slot_cap, uint32_t m)
+                                             crsh_meta *meta, uint32_t slot_cap, uint32_t m, uint32_t tri_base)
 {
     __shared__ uint64_t s_red[256 / WAVE];
     const uint32_t ns = BATCH ? batch_slots(meta, B, slot_cap) : min(meta->n_rays, slot_cap);
@@ -142,8 +144,15 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
             for (int k = 0; k < HIT_UNROLL; ++k) {
                 const uint64_t q = q0 + slot + k * per_wave;
                 ok[k] = lane_ok && q < c1;
-                t[k] = ok[k] ? ptri[q] : 0u;
-                const uint32_t leaf = ok[k] ? pnode[q] : 0u;
+                uint32_t leaf;
+                if constexpr (PACKED) {
+                    const uint32_t w = ok[k] ? ptri[q] : 0u;
+                    t[k] = tri_base + (w & ((1u << CRSH_PACKED_TRI_BITS) - 1u));
+                    leaf = w >> CRSH_PACKED_TRI_BITS;
+                } else {
+                    t[k] = ok[k] ? ptri[q] : 0u;
+                    leaf = ok[k] ? pnode[q] : 0u;
+                }
                 s[k] = leaf * B + j;
                 ok[k] = ok[k] && s[k] < ns && t[k] < m;
             }
@@ -264,7 +273,7 @@ void hit_prep_launch(const crsh_scene *scene, float4 *tri, hipStream_t stream)
 
 void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level1,
                       int32_t bundle, const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta,
-                      const batch_dev *bd, int32_t hit_block, hipStream_t stream)
+                      const batch_dev *bd, int32_t hit_block, hipStream_t stream, bool packed, uint32_t tri_base)
 {
     const uint32_t g = std::max<uint32_t>(std::min<uint32_t>((hs.slots + 255) / 256, 4096), 1);
     sorted_rays S{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
@@ -278,12 +287,17 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
     const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
     prof_scope ps("k_hit", stream);
     if (bd)
-        k_hit<true><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, level1->node, level1->capacity,
-                                                    (uint32_t)bundle, log2G, hs.keys, meta, hs.slots, scene->m);
+        k_hit<true, false><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, level1->node,
+                                                           level1->capacity, (uint32_t)bundle, log2G, hs.keys, meta,
+                                                           hs.slots, scene->m, 0u);
+    else if (packed)
+        k_hit<false, true><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, nullptr, level1->capacity,
+                                                           (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
+                                                           scene->m, tri_base);
     else
-        k_hit<false><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, level1->node, level1->capacity,
-                                                     (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
-                                                     scene->m);
+        k_hit<false, false><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, level1->node,
+                                                            level1->capacity, (uint32_t)bundle, log2G, hits->tkey,
+                                                            meta, hs.slots, scene->m, 0u);
 }
 
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
@@ -341,7 +355,7 @@ crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32
 crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
                        const crsh_pairs *level1, const crsh_scene *scene, float t_min, crsh_hits *hits,
                        crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t hit_block,
-                       hipStream_t stream)
+                       hipStream_t stream, bool packed, uint32_t tri_base)
 {
     crsh_status st = hit_check(sorted, sorted_ids, bundle, level1, scene, hits, meta, ws, hit_block,
                                "crsh_closest_hit");
@@ -354,7 +368,8 @@ crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int3
     float4 *tri = (float4 *)ws;
     const hit_slots_ws hs = carve_hit_slots((char *)ws + align256((size_t)scene->m * 48), slots);
     hit_prep_launch(scene, tri, stream);
-    hit_pairs_launch(sorted, tri, hs, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream);
+    hit_pairs_launch(sorted, tri, hs, level1, bundle, scene, t_min, hits, meta, bd, hit_block, stream, packed,
+                     tri_base);
     hit_final_launch(sorted, sorted_ids, tri, hs, bundle, scene, t_min, hits, meta, bd, stream);
     return hip_check(hipGetLastError(), "crsh_closest_hit launch");
 }
@@ -367,5 +382,24 @@ extern "C" crsh_status crsh_closest_hit(const crsh_rays *sorted, const uint32_t 
                                         hipStream_t stream)
 {
     return hit_launch(sorted, sorted_ids, bundle, level1, scene, t_min, hits, meta, ws, ws_bytes, nullptr, 256,
-                      stream);
+                      stream, false, 0u);
+}
+
+extern "C" crsh_status crsh_closest_hit_packed(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle,
+                                               const crsh_packed_pairs *level1, uint32_t tri_begin,
+                                               const crsh_scene *scene, float t_min, crsh_hits *hits,
+                                               crsh_meta *meta, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!level1) {
+        set_error("crsh_closest_hit_packed: NULL argument");
+        return CRSH_ERR_INVALID;
+    }
+    if (level1->capacity && !level1->pair) {
+        set_error("crsh_closest_hit_packed: incomplete arrays");
+        return CRSH_ERR_INVALID;
+    }
+    // the packed words travel in the triangle array; no node array
+    crsh_pairs p{level1->pair, level1->pair, level1->capacity};
+    return hit_launch(sorted, sorted_ids, bundle, &p, scene, t_min, hits, meta, ws, ws_bytes, nullptr, 256, stream,
+                      true, tri_begin);
 }

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void k_top_count(const float4 *__restrict__ na
     }
 }
 
-template <bool BATCH>
+template <bool BATCH, bool PACKED = false>
 __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na, const float4 *__restrict__ nb,
                                                   const float *__restrict__ ns, const float4 *__restrict__ tsph,
                                                   const uint32_t *__restrict__ mesh_first,
@@ -232,8 +232,7 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
             const uint64_t mask = ballot(ok);
             const uint64_t at = pos + rank_below(mask);
             if (ok && at < out.cap) {
-                out.tri[at] = t;
-                out.node[at] = i;
+                pair_put<PACKED>(out, at, t, i);
             }
             pos += (uint32_t)__popcll(mask);
         }
@@ -243,15 +242,15 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
 // ----------------------------------------------------------- lower levels
 // Children of a parent: plain, par * F + [0, F) below nk; batch, the range
 // (pfirst[par], count) recorded by the build.
-template <int PPT>
+template <int PPT, bool PACKED>
 __device__ __forceinline__ void load_tile_pairs(uint64_t q0, uint64_t nin, const pairs_dev &in, uint32_t *tri,
                                                 uint32_t *par)
 {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const bool ok = q0 + k < nin;
-        tri[k] = ok ? in.tri[q0 + k] : 0u;
-        par[k] = ok ? in.node[q0 + k] : 0xFFFFFFFFu;
+        tri[k] = 0u;
+        par[k] = 0xFFFFFFFFu;
+        if (q0 + k < nin) pair_get<PACKED>(in, q0 + k, tri[k], par[k]);
     }
 }
 
@@ -318,7 +317,7 @@ __device__ __forceinline__ uint32_t test_children(const child_set<NF, PPT> &c, u
     return mask;
 }
 
-template <int NF, int PPT, bool BATCH>
+template <int NF, int PPT, bool BATCH, bool PACKED = false>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_level, uint32_t F,
                                                                const float4 *__restrict__ na,
                                                                const float4 *__restrict__ nb,
@@ -354,10 +353,10 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     const uint64_t stride = gridDim.x;
     if (blockIdx.x < ntiles) {
         uint32_t tri0[PPT], par0[PPT];
-        load_tile_pairs<PPT>((uint64_t)blockIdx.x * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri0, par0);
+        load_tile_pairs<PPT, PACKED>((uint64_t)blockIdx.x * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri0, par0);
         load_children<NF, PPT, BATCH>(cs, F, nk, offk, na, nb, ns, tsph, m, pfirst, pinfo, np, tri0, par0);
         if (blockIdx.x + stride < ntiles)
-            load_tile_pairs<PPT>((blockIdx.x + stride) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri_n,
+            load_tile_pairs<PPT, PACKED>((blockIdx.x + stride) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri_n,
                                  par_n);
     }
     uint32_t parity = 0;
@@ -366,7 +365,7 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
         if (tile + stride < ntiles) {
             load_children<NF, PPT, BATCH>(cs, F, nk, offk, na, nb, ns, tsph, m, pfirst, pinfo, np, tri_n, par_n);
             if (tile + 2 * stride < ntiles)
-                load_tile_pairs<PPT>((tile + 2 * stride) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in,
+                load_tile_pairs<PPT, PACKED>((tile + 2 * stride) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in,
                                      tri_n, par_n);
         }
         const uint32_t mask = test_children<NF, PPT>(cur, tests);
@@ -407,7 +406,7 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
 // Emit pass: PPT parent pairs per thread, EMIT_TILE per block iteration,
 // covering EMIT_PPT / LEVEL_PPT count tiles (their masks, survivor counts and
 // the first one's output offset).
-template <int NF, int PPT, bool BATCH>
+template <int NF, int PPT, bool BATCH, bool PACKED = false>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_level, uint32_t F, pair_levels P,
                                                               trav_scratch S, const crsh_meta *meta, batch_dev bd)
 {
@@ -462,8 +461,9 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const bool live = ((mask >> (k * NF)) & ((1u << NF) - 1u)) != 0u && q0 + k < nin;
-            tri[k] = live ? in.tri[q0 + k] : 0u;
-            par[k] = live ? in.node[q0 + k] : 0u;
+            tri[k] = 0u;
+            par[k] = 0u;
+            if (live) pair_get<PACKED>(in, q0 + k, tri[k], par[k]);
         }
         const uint64_t nt = tile + gridDim.x;
         if (nt < ntiles) tile_head(nt, mask_n, cnt_n, off_n);
@@ -492,10 +492,7 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
         const uint32_t n_out = min(total, TILE_OUT);
         for (uint32_t i = threadIdx.x; i < n_out; i += LEVEL_THREADS) {
             const uint64_t at = base + i;
-            if (at < out.cap) {
-                out.tri[at] = s_tri[i];
-                out.node[at] = s_node[i];
-            }
+            if (at < out.cap) pair_put<PACKED>(out, at, s_tri[i], s_node[i]);
         }
         __syncthreads();                         // LDS is reused by the next tile
     }
@@ -603,7 +600,7 @@ void node_pack_launch(const crsh_nodes *nodes, crsh_meta *meta, float4 *na, floa
 
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
-                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream)
+                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed)
 {
     const batch_dev b = bd ? *bd : batch_dev{};
     const uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), 4096);
@@ -611,24 +608,24 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     const int L = parent_level;
     int nf = 2;
     while (nf < merge) nf *= 2;
-#define CRSH_COUNT(NF, BT)                                                                                   \
-    k_level_count<NF, LEVEL_PPT, BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta, b)
+#define CRSH_COUNT(NF, BT, PK)                                                                               \
+    k_level_count<NF, LEVEL_PPT, BT, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta, b)
+#define CRSH_COUNT_NF(BT, PK)                                                                                \
+    switch (nf) {                                                                                            \
+    case 2: CRSH_COUNT(2, BT, PK); break;                                                                    \
+    case 4: CRSH_COUNT(4, BT, PK); break;                                                                    \
+    case 8: CRSH_COUNT(8, BT, PK); break;                                                                    \
+    default: CRSH_COUNT(16, BT, PK); break;                                                                  \
+    }
     prof_scope ps("k_level", stream);
     if (bd) {
-        switch (nf) {
-        case 2: CRSH_COUNT(2, true); break;
-        case 4: CRSH_COUNT(4, true); break;
-        case 8: CRSH_COUNT(8, true); break;
-        default: CRSH_COUNT(16, true); break;
-        }
+        CRSH_COUNT_NF(true, false)
+    } else if (packed) {
+        CRSH_COUNT_NF(false, true)
     } else {
-        switch (nf) {
-        case 2: CRSH_COUNT(2, false); break;
-        case 4: CRSH_COUNT(4, false); break;
-        case 8: CRSH_COUNT(8, false); break;
-        default: CRSH_COUNT(16, false); break;
-        }
+        CRSH_COUNT_NF(false, false)
     }
+#undef CRSH_COUNT_NF
 #undef CRSH_COUNT
 }
 
@@ -643,12 +640,14 @@ void tri_spheres_launch(const crsh_scene *scene, uint32_t b, uint32_t e, float4 
 
 // lowest: the lowest level produced (1, or 2 when crsh_leaf_hit forms the
 // level-1 pairs itself); a top-level pass always writes its own level.
-crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin, uint32_t tri_end,
-                            int32_t bundle, int32_t merge, const crsh_pairs pairs[CRSH_MAX_LEVELS],
-                            crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t batch_levels,
-                            uint64_t batch_top_items, int32_t lowest, hipStream_t stream)
+// P: the pair storage of `levels` consecutive levels (largest capacity
+// max_pairs), unpacked or packed.
+static crsh_status traverse_run(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin,
+                                uint32_t tri_end, int32_t bundle, int32_t merge, const pair_levels &P, int levels,
+                                uint64_t max_pairs, crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd,
+                                int32_t batch_levels, uint64_t batch_top_items, int32_t lowest, hipStream_t stream)
 {
-    if (!nodes || !scene || !pairs || !meta || !ws) {
+    if (!nodes || !scene || !meta || !ws) {
         set_error("crsh_traverse: NULL argument");
         return CRSH_ERR_INVALID;
     }
@@ -673,19 +672,17 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
         set_error("crsh_traverse: lowest level must be 1 or 2");
         return CRSH_ERR_INVALID;
     }
-    // levels present in the pair table: consecutive entries with storage
-    int levels = 0;
-    uint64_t max_pairs = 0;
-    while (levels < CRSH_MAX_LEVELS && pairs[levels].tri && pairs[levels].node) {
-        max_pairs = std::max(max_pairs, pairs[levels].capacity);
-        ++levels;
-    }
     if (levels == 0) {
         set_error("crsh_traverse: no pair storage");
         return CRSH_ERR_INVALID;
     }
     if (bd && levels < batch_levels) {
         set_error("crsh_batch: pair storage for %d levels, %d needed", levels, batch_levels);
+        return CRSH_ERR_INVALID;
+    }
+    const bool packed = P.p[0].packed != 0;
+    if (packed && bd) {
+        set_error("crsh_batch: packed pairs are not supported in the batched form");
         return CRSH_ERR_INVALID;
     }
     const uint64_t top_items = bd ? batch_top_items : (uint64_t)nodes->capacity * scene->n_mesh;
@@ -718,12 +715,6 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
 
     int nf = 2;
     while (nf < merge) nf *= 2;
-    pair_levels P;
-    for (int k = 0; k < CRSH_MAX_LEVELS; ++k) {
-        P.p[k].tri = k < levels ? pairs[k].tri : nullptr;
-        P.p[k].node = k < levels ? pairs[k].node : nullptr;
-        P.p[k].cap = k < levels ? pairs[k].capacity : 0;
-    }
     const batch_dev b = bd ? *bd : batch_dev{};
     tri_spheres_launch(scene, tri_begin, tri_end, tsph, stream);
     node_pack_launch(nodes, meta, na, nb, ns, true, stream);
@@ -759,38 +750,44 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
             k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(0, scene->n_mesh, P, S, meta, 0, nullptr);
             {
                 prof_scope ps("k_top_emit", stream);
-                k_top_emit<false><<<top_grid, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first,
-                                                                scene->mesh_count, scene->msph, scene->n_mesh,
-                                                                tri_begin, tri_end, P, S, meta, b, 0);
+                if (packed)
+                    k_top_emit<false, true><<<top_grid, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first,
+                                                                          scene->mesh_count, scene->msph,
+                                                                          scene->n_mesh, tri_begin, tri_end, P, S,
+                                                                          meta, b, 0);
+                else
+                    k_top_emit<false><<<top_grid, 256, 0, stream>>>(na, nb, ns, tsph, scene->mesh_first,
+                                                                    scene->mesh_count, scene->msph, scene->n_mesh,
+                                                                    tri_begin, tri_end, P, S, meta, b, 0);
             }
         }
     };
     // one level pass: pairs of level L (1-based parent) -> level L - 1
     auto level_pass_launch = [&](int L) {
-        const uint64_t tiles = (pairs[L - 1].capacity + LEVEL_TILE - 1) / LEVEL_TILE;
+        const uint64_t tiles = (P.p[L - 1].cap + LEVEL_TILE - 1) / LEVEL_TILE;
         uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096);
-#define CRSH_EMIT(NF, BT)                                                                                  \
-    k_level_emit<NF, emit_ppt(NF), BT><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta, b)
-        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream);
+#define CRSH_EMIT(NF, BT, PK)                                                                              \
+    k_level_emit<NF, emit_ppt(NF), BT, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, P, S, meta, b)
+#define CRSH_EMIT_NF(BT, PK)                                                                               \
+    switch (nf) {                                                                                          \
+    case 2: CRSH_EMIT(2, BT, PK); break;                                                                   \
+    case 4: CRSH_EMIT(4, BT, PK); break;                                                                   \
+    case 8: CRSH_EMIT(8, BT, PK); break;                                                                   \
+    default: CRSH_EMIT(16, BT, PK); break;                                                                 \
+    }
+        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream, packed);
         k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
             prof_scope ps("k_level_emit", stream);
             if (bd) {
-                switch (nf) {
-                case 2: CRSH_EMIT(2, true); break;
-                case 4: CRSH_EMIT(4, true); break;
-                case 8: CRSH_EMIT(8, true); break;
-                default: CRSH_EMIT(16, true); break;
-                }
+                CRSH_EMIT_NF(true, false)
+            } else if (packed) {
+                CRSH_EMIT_NF(false, true)
             } else {
-                switch (nf) {
-                case 2: CRSH_EMIT(2, false); break;
-                case 4: CRSH_EMIT(4, false); break;
-                case 8: CRSH_EMIT(8, false); break;
-                default: CRSH_EMIT(16, false); break;
-                }
+                CRSH_EMIT_NF(false, false)
             }
         }
+#undef CRSH_EMIT_NF
 #undef CRSH_EMIT
     };
     if (bd) {
@@ -805,7 +802,72 @@ crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, ui
     return hip_check(hipGetLastError(), "crsh_traverse launch");
 }
 
+crsh_status traverse_launch(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin, uint32_t tri_end,
+                            int32_t bundle, int32_t merge, const crsh_pairs pairs[CRSH_MAX_LEVELS],
+                            crsh_meta *meta, void *ws, size_t ws_bytes, const batch_dev *bd, int32_t batch_levels,
+                            uint64_t batch_top_items, int32_t lowest, hipStream_t stream)
+{
+    if (!pairs) {
+        set_error("crsh_traverse: NULL argument");
+        return CRSH_ERR_INVALID;
+    }
+    // levels present in the pair table: consecutive entries with storage
+    pair_levels P{};
+    int levels = 0;
+    uint64_t max_pairs = 0;
+    while (levels < CRSH_MAX_LEVELS && pairs[levels].tri && pairs[levels].node) {
+        P.p[levels].tri = pairs[levels].tri;
+        P.p[levels].node = pairs[levels].node;
+        P.p[levels].cap = pairs[levels].capacity;
+        max_pairs = std::max(max_pairs, pairs[levels].capacity);
+        ++levels;
+    }
+    return traverse_run(nodes, scene, tri_begin, tri_end, bundle, merge, P, levels, max_pairs, meta, ws, ws_bytes,
+                        bd, batch_levels, batch_top_items, lowest, stream);
+}
+
+// packed pairs need every level's node ids below 2^(32 - CRSH_PACKED_TRI_BITS)
+__global__ void k_packed_check(crsh_meta *meta)
+{
+    const uint32_t nl = min(meta->n_levels, (uint32_t)CRSH_MAX_LEVELS);
+    for (uint32_t k = 0; k < nl; ++k)
+        if (meta->level_cnt[k] > CRSH_PACKED_MAX_NODES) atomicOr(&meta->status, CRSH_OVERFLOW_PACKED);
+}
+
 }  // namespace crsh
+
+extern "C" crsh_status crsh_traverse_packed(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin,
+                                            uint32_t tri_end, int32_t bundle, int32_t merge,
+                                            const crsh_packed_pairs pairs[CRSH_MAX_LEVELS], crsh_meta *meta,
+                                            void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!pairs || !meta) {
+        set_error("crsh_traverse_packed: NULL argument");
+        return CRSH_ERR_INVALID;
+    }
+    if (tri_begin > tri_end || tri_end - tri_begin > CRSH_PACKED_MAX_TRIS) {
+        set_error("crsh_traverse_packed: a triangle batch holds at most %u triangles (got [%u, %u))",
+                  CRSH_PACKED_MAX_TRIS, tri_begin, tri_end);
+        return CRSH_ERR_INVALID;
+    }
+    pair_levels P{};
+    int levels = 0;
+    uint64_t max_pairs = 0;
+    while (levels < CRSH_MAX_LEVELS && pairs[levels].pair) {
+        P.p[levels].tri = pairs[levels].pair;
+        P.p[levels].node = nullptr;
+        P.p[levels].cap = pairs[levels].capacity;
+        P.p[levels].packed = 1;
+        P.p[levels].tri_base = tri_begin;
+        max_pairs = std::max(max_pairs, pairs[levels].capacity);
+        ++levels;
+    }
+    crsh_status st = traverse_run(nodes, scene, tri_begin, tri_end, bundle, merge, P, levels, max_pairs, meta, ws,
+                                  ws_bytes, nullptr, 0, 0, 1, stream);
+    if (st != CRSH_OK) return st;
+    k_packed_check<<<1, 1, 0, stream>>>(meta);
+    return hip_check(hipGetLastError(), "crsh_traverse_packed launch");
+}
 
 extern "C" crsh_status crsh_traverse(const crsh_nodes *nodes, const crsh_scene *scene, uint32_t tri_begin,
                                      uint32_t tri_end, int32_t bundle, int32_t merge,

@@ -6,10 +6,42 @@
 
 namespace crsh {
 
+// One level's pairs: two arrays (triangle, node), or one packed word per
+// pair -- node in the high bits, triangle minus tri_base in the low
+// CRSH_PACKED_TRI_BITS (Sec. 3.3.7's 32-bit pair encoding; node == nullptr).
 struct pairs_dev {
     uint32_t *tri, *node;
     uint64_t cap;
+    uint32_t packed;       // 1: packed words in `tri`
+    uint32_t tri_base;     // first triangle of the batch (packed form)
 };
+
+// PACKED is a compile-time choice so that the two-array kernels are the
+// same code as without packed support.
+template <bool PACKED>
+__device__ __forceinline__ void pair_get(const pairs_dev &p, uint64_t q, uint32_t &tri, uint32_t &node)
+{
+    if constexpr (PACKED) {
+        const uint32_t w = p.tri[q];
+        tri = p.tri_base + (w & ((1u << CRSH_PACKED_TRI_BITS) - 1u));
+        node = w >> CRSH_PACKED_TRI_BITS;
+    } else {
+        tri = p.tri[q];
+        node = p.node[q];
+    }
+}
+
+template <bool PACKED>
+__device__ __forceinline__ void pair_put(const pairs_dev &p, uint64_t at, uint32_t tri, uint32_t node)
+{
+    if constexpr (PACKED) {
+        p.tri[at] = (node << CRSH_PACKED_TRI_BITS) | (tri - p.tri_base);
+    } else {
+        p.tri[at] = tri;
+        p.node[at] = node;
+    }
+}
+
 struct pair_levels {
     pairs_dev p[CRSH_MAX_LEVELS];
 };
@@ -37,6 +69,6 @@ void node_pack_launch(const crsh_nodes *nodes, crsh_meta *meta, float4 *na, floa
 // node tests added to meta)
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
-                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream);
+                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed = false);
 
 }  // namespace crsh

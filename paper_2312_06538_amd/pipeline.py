@@ -118,16 +118,27 @@ class Buffers:
             b = self.level_buf(lv)
             self.c_pairs[lv - 1] = X.Pairs(_p(b[0]), _p(b[1]), self.pair_capacity)
         self.c_hits = X.Hits(_p(self.tkey), _p(self.hit_tri), _p(self.hit_t), _p(self.hit_u), _p(self.hit_v), cap)
+        # packed pairs (one word each) reuse the triangle array of every level
+        self.c_packed = X.PackedPairTable()
+        for lv in range(1, fr.n + 1):
+            self.c_packed[lv - 1] = X.PackedPairs(_p(self.level_buf(lv)[0]), self.pair_capacity)
 
     def level_buf(self, lv):
         return self.pair_bufs[lv - 1] if self.keep_levels else self.pair_bufs[lv % len(self.pair_bufs)]
 
 
-def run_frame(fr, bf, stream=None, tri_batches=None, leaf_hit=False, parent=None):
+def packed_batches(m):
+    """Triangle batches of at most PACKED_MAX_TRIS triangles covering [0, m)."""
+    return [(b, min(b + X.PACKED_MAX_TRIS, m)) for b in range(0, max(m, 1), X.PACKED_MAX_TRIS)]
+
+
+def run_frame(fr, bf, stream=None, tri_batches=None, leaf_hit=False, parent=None, packed=False):
     """Chain hash -> sort -> build -> traverse -> closest hit on one stream.
     leaf_hit: the last traversal level runs fused with the final tests
     (crsh_traverse_upper + crsh_leaf_hit); otherwise every level-1 pair is
-    stored (crsh_traverse + crsh_closest_hit).  parent: the Buffers of the
+    stored (crsh_traverse + crsh_closest_hit).  packed: pairs stored one
+    32-bit word each (crsh_traverse_packed + crsh_closest_hit_packed), over
+    triangle batches of at most PACKED_MAX_TRIS.  parent: the Buffers of the
     previous generation; the rays then come from its closest hits
     (crsh_bounce) instead of the primary-hit buffer."""
     s = stream_handle(stream)
@@ -142,8 +153,14 @@ def run_frame(fr, bf, stream=None, tri_batches=None, leaf_hit=False, parent=None
     X.crsh_build(bf.c_rays, _p(bf.sids), fr.B, fr.F, fr.n, bf.c_nodes, bf.c_srays, meta, s)
     X.crsh_hits_reset(bf.c_hits, s)
     fuse = leaf_hit and fr.n >= 2
+    if packed and tri_batches is None:
+        tri_batches = packed_batches(fr.m)
     for (b, e) in (tri_batches or [(0, fr.m)]):
-        if fuse:
+        if packed:
+            X.crsh_traverse_packed(bf.c_nodes, fr.scene, b, e, fr.B, fr.F, bf.c_packed, meta, ws, wsb, s)
+            X.crsh_closest_hit_packed(bf.c_srays, _p(bf.sids), fr.B, bf.c_packed[0], b, fr.scene, fr.t_min,
+                                      bf.c_hits, meta, ws, wsb, s)
+        elif fuse:
             X.crsh_traverse_upper(bf.c_nodes, fr.scene, b, e, fr.B, fr.F, bf.c_pairs, meta, ws, wsb, s)
             X.crsh_leaf_hit(bf.c_srays, _p(bf.sids), fr.B, fr.F, bf.c_nodes, bf.c_pairs, fr.scene, fr.t_min,
                             bf.c_hits, meta, ws, wsb, s)
@@ -158,14 +175,15 @@ def read_meta(bf, stream=None):
     return m, st
 
 
-def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12, leaf_hit=False, parent=None):
+def run_with_retry(fr, bf, stream=None, tri_batches=None, grow=1.25, max_tries=12, leaf_hit=False, parent=None,
+                   packed=False):
     """Run a frame; if a pair level overflowed, regrow the pair arrays and run
     again (the ray arrays likewise for a bounce generation that outgrew
     them).  An overflowing level truncates the levels below it, so their
     reported sizes are lower bounds: grow to at least twice the capacity.
     Returns (buffers, meta)."""
     for _ in range(max_tries):
-        run_frame(fr, bf, stream, tri_batches, leaf_hit=leaf_hit, parent=parent)
+        run_frame(fr, bf, stream, tri_batches, leaf_hit=leaf_hit, parent=parent, packed=packed)
         m, st = read_meta(bf, stream)
         if st == X.OK:
             return bf, m

@@ -188,13 +188,22 @@ def gpu_closest_hit(rays, sorted_ids, B, pairs1, sc, t_min):
     return (tri[:n].cpu().numpy(), tt[:n].cpu().numpy(), uu[:n].cpu().numpy(), vv[:n].cpu().numpy()), m
 
 
-def run_pipeline(wl, pair_capacity=1 << 20, keep_levels=True, tri_batches=None, leaf_hit=False):
+def run_pipeline(wl, pair_capacity=1 << 20, keep_levels=True, tri_batches=None, leaf_hit=False, packed=False):
     """The whole path; leaf_hit=False stores every pair level (for
-    inspection), True runs the last level fused with the final tests."""
+    inspection), True runs the last level fused with the final tests.
+    packed: pairs as packed words (results' pairs hold the words in place of
+    the triangle ids; decode with decode_packed)."""
     fr = P.DeviceFrame(wl)
     bf = P.Buffers(fr, pair_capacity, keep_levels=keep_levels)
-    bf, m = P.run_with_retry(fr, bf, tri_batches=tri_batches, leaf_hit=leaf_hit)
+    bf, m = P.run_with_retry(fr, bf, tri_batches=tri_batches, leaf_hit=leaf_hit, packed=packed)
     return P.results(fr, bf, m)
+
+
+def decode_packed(words, tri_begin):
+    """(triangle ids, node ids) of packed pairs of the batch starting at tri_begin."""
+    w = np.asarray(words).astype(np.uint32)
+    low = w & np.uint32(X.PACKED_MAX_TRIS - 1)
+    return (low + np.uint32(tri_begin)).astype(np.uint32), (w >> np.uint32(X.PACKED_TRI_BITS)).astype(np.uint32)
 
 
 def pair_keys(t, n):

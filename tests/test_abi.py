@@ -46,6 +46,7 @@ int main(void) {
   S(crsh_nodes) O(crsh_nodes, sec) O(crsh_nodes, capacity)
   S(crsh_scene) O(crsh_scene, m) O(crsh_scene, msph) O(crsh_scene, n_mesh)
   S(crsh_pairs) O(crsh_pairs, capacity)
+  S(crsh_packed_pairs) O(crsh_packed_pairs, capacity)
   S(crsh_hits) O(crsh_hits, v) O(crsh_hits, capacity)
   S(crsh_frame) O(crsh_frame, n_lights) O(crsh_frame, lights) O(crsh_frame, eye) O(crsh_frame, t_min)
   O(crsh_frame, inv_ext)
@@ -66,7 +67,8 @@ def test_ctypes_layouts_match_header(tmp_path):
                            "-I", "/opt/rocm/include", str(c), "-o", str(exe)])
     got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
     mirror = {"crsh_meta": X.Meta, "crsh_gbuf": X.Gbuf, "crsh_raygen": X.Raygen, "crsh_rays": X.Rays,
-              "crsh_nodes": X.Nodes, "crsh_scene": X.Scene, "crsh_pairs": X.Pairs, "crsh_hits": X.Hits,
+              "crsh_nodes": X.Nodes, "crsh_scene": X.Scene, "crsh_pairs": X.Pairs,
+              "crsh_packed_pairs": X.PackedPairs, "crsh_hits": X.Hits,
               "crsh_frame": X.Frame, "crsh_frame_meta": X.FrameMeta, "crsh_batch": X.Batch}
     for key, val in got.items():
         if "." in key:
@@ -104,6 +106,18 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert L.crsh_traverse(ctypes.byref(n), ctypes.byref(sc), 5, 11, 8, 4, pt, 1, 1, 1 << 30, None) == \
         X.ERR_INVALID
     assert "batch" in X.last_error()
+    # packed pairs: a triangle batch over 2^14 triangles, a batch outside the scene
+    big = X.Scene((X.vp * 9)(*([1] * 9)), 1 << 20, 1, 1, 1, 1)
+    pp = X.PackedPairTable()
+    pp[0] = X.PackedPairs(1, 10)
+    assert L.crsh_traverse_packed(ctypes.byref(n), ctypes.byref(big), 0, X.PACKED_MAX_TRIS + 1, 8, 4, pp, 1, 1,
+                                  1 << 30, None) == X.ERR_INVALID
+    assert "at most" in X.last_error()
+    assert L.crsh_traverse_packed(ctypes.byref(n), ctypes.byref(sc), 5, 11, 8, 4, pp, 1, 1, 1 << 30, None) == \
+        X.ERR_INVALID
+    assert "batch" in X.last_error()
+    assert L.crsh_closest_hit_packed(ctypes.byref(r), 1, 8, None, 0, ctypes.byref(sc), ctypes.c_float(1e-4),
+                                     None, 1, 1, 1 << 30, None) == X.ERR_INVALID
     # closest hit: bundle out of range
     h = X.Hits(1, 1, 1, 1, 1, 100)
     assert L.crsh_closest_hit(ctypes.byref(r), 1, 0, ctypes.byref(pt[0]), ctypes.byref(sc), ctypes.c_float(1e-4),

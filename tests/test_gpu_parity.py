@@ -381,6 +381,57 @@ def test_leaf_hit_triangle_batches():
         assert _same(a, b)
 
 
+def test_packed_pairs_bit_exact_per_triangle_batch():
+    """Pairs packed one 32-bit word each (node above 14 bits of triangle
+    offset, Sec. 3.3.7) over triangle batches of at most 2^14 triangles:
+    every level of every batch decodes to the oracle's pairs of that batch,
+    in order, with the same counters; over all batches the closest hits are
+    the oracle's."""
+    from paper_2312_06538_amd import pipeline as P
+    gu = _gu()
+    base, kw = small("refl_96")
+    wl = workload(base, **kw)
+    batches = P.packed_batches(wl.scene.m)
+    assert len(batches) > 1 and all(e - b <= 1 << 14 for b, e in batches)
+    o = O.run_pipeline(wl, tri_batches=batches)
+    for i, (b, e) in enumerate(batches):
+        print(f"[packed] batch [{b}, {e})", flush=True)
+        g = gu.run_pipeline(wl, pair_capacity=1 << 20, keep_levels=True, tri_batches=[(b, e)], packed=True)
+        tr = o["trav"][i]
+        for lv, (t, nd) in tr["pairs"].items():
+            pt, pn = gu.decode_packed(g["pairs"][lv][0], b)
+            assert np.array_equal(pt, t) and np.array_equal(pn, nd), (b, lv)
+        assert g["tests"] == {lv: int(v) for lv, v in tr["tests"].items()}
+        assert g["final_tests"] == tr["final_tests"] and g["mesh_tests"] == tr["mesh_tests"]
+    g = gu.run_pipeline(wl, pair_capacity=1 << 20, keep_levels=False, packed=True)
+    assert g["final_tests"] == sum(t["final_tests"] for t in o["trav"])
+    assert np.array_equal(g["hit"][0], o["hits"][0])
+    for a, b in zip(g["hit"][1:], o["hits"][1:]):
+        assert _same(a, b)
+
+
+def test_packed_pairs_reject_levels_over_2_18_nodes():
+    """A level of more than 2^18 nodes cannot be packed: the traversal flags
+    it on the device (the pairs of that call are not valid)."""
+    import dataclasses
+    from paper_2312_06538_amd import crsh as X
+    from paper_2312_06538_amd import pipeline as P
+    wl = dataclasses.replace(workload("refl_1024", W=400, H=400), B=1, F=4, n=2)
+    fr = P.DeviceFrame(wl)
+    bf = P.Buffers(fr, 1 << 22, keep_levels=False)
+    P.run_frame(fr, bf, tri_batches=[(0, 1 << 14)], packed=True)
+    m, st = P.read_meta(bf)
+    assert int(m.level_cnt[0]) > X.PACKED_MAX_NODES
+    assert st != X.OK and m.status & X.OVERFLOW_PACKED
+    # within the limit (one level of at most 2^18 nodes) the flag stays clear
+    wl = dataclasses.replace(workload("refl_1024", W=96, H=96), B=1, F=4, n=2)
+    fr = P.DeviceFrame(wl)
+    bf = P.Buffers(fr, 1 << 22, keep_levels=False)
+    P.run_frame(fr, bf, tri_batches=[(0, 1 << 14)], packed=True)
+    m, st = P.read_meta(bf)
+    assert not m.status & X.OVERFLOW_PACKED
+
+
 def test_pipeline_is_deterministic():
     base, kw = small("refl_96")
     wl = workload(base, **kw)
