@@ -465,6 +465,17 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
             par[k] = 0u;
             if (live) pair_get<PACKED>(in, q0 + k, tri[k], par[k]);
         }
+        // first child of each parent: p * F, or (batched form) the build's
+        // record, requested here so that its latency overlaps the scan
+        uint32_t first[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            first[k] = par[k] * F;
+            if constexpr (BATCH) {
+                const bool live = ((mask >> (k * NF)) & ((1u << NF) - 1u)) != 0u && par[k] < np;
+                first[k] = live ? bd.node_first[offp + par[k]] : 0u;
+            }
+        }
         const uint64_t nt = tile + gridDim.x;
         if (nt < ntiles) tile_head(nt, mask_n, cnt_n, off_n);
         if (cnt == 0) continue;                  // uniform over the block
@@ -475,14 +486,12 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (((mask >> (k * NF)) & ((1u << NF) - 1u)) == 0u) continue;
-                uint32_t first = par[k] * F;
-                if constexpr (BATCH) first = par[k] < np ? bd.node_first[offp + par[k]] : 0u;
 #pragma unroll
                 for (int j = 0; j < NF; ++j) {
                     if (!((mask >> (k * NF + j)) & 1u)) continue;
                     if (at < TILE_OUT) {
                         s_tri[at] = tri[k];
-                        s_node[at] = first + (uint32_t)j;
+                        s_node[at] = first[k] + (uint32_t)j;
                     }
                     ++at;
                 }
