@@ -159,8 +159,8 @@ def main():
                     help="after timing, one device copy of this size: calibrates HBM counters under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs the single-GPU path only (asked for {args.gpus} GPUs); the multi-GPU split of "
-              "the path is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the split of the path over several "
+              "GPUs (rays sharded by image band or frame, scene replicated) is not built", file=sys.stderr)
         return 2
 
     if args.sort_sweep:

@@ -2,15 +2,19 @@
 //
 // Every level is produced in three launches with no wait between blocks:
 //   count  each work item (top level: one (top node, mesh) pair per wave;
-//          lower levels: a tile of 512 parent pairs, 2 per thread, every
-//          child unrolled) runs its Eq. 9 tests and records how many pass
-//          (lower levels also keep each thread's pass mask);
+//          lower levels: a tile of 256 parent pairs, one per thread, every
+//          child unrolled, pipelined over the block's tiles) runs its Eq. 9
+//          tests and records how many pass (lower levels also keep the pass
+//          bits, one per child slot, packed in 32-bit words);
 //   scan   exclusive scan of the counts -> output offset of every item;
 //   emit   each item writes its survivors at its offset, in (parent pair,
-//          child) order -- at the top level (node, mesh, triangle) order.
+//          child) order -- at the top level (node, mesh, triangle) order;
+//          lower levels in tiles of two count tiles, staged through LDS.
 // The pair arrays therefore come out trimmed (Fig. 4) and in the order of a
 // sequential traversal, so they are deterministic.  Work is spread with
-// grid-stride loops; nothing depends on which blocks are resident.
+// grid-stride loops; nothing depends on which blocks are resident.  Pairs are
+// two arrays (triangle, node) or, for crsh_traverse_packed, one 32-bit word
+// each (Sec. 3.3.7's encoding), a compile-time choice of every kernel.
 //
 // Batched form: frames have their own top levels, so levels are produced from
 // the highest down; on each level the pairs that descend from the level above
