@@ -197,9 +197,10 @@ class DeviceBatch:
         raw = self.frame_meta.cpu().numpy().tobytes()
         return (X.FrameMeta * self.n_frames).from_buffer_copy(raw)
 
-    def frame_results(self, m):
+    def frame_results(self, m, with_pairs=True):
         """Per-frame host copies of every product, in the frame's own ids and
-        node numbering (comparable with a plain run of the frame)."""
+        node numbering (comparable with a plain run of the frame); without
+        the pair levels when with_pairs is False."""
         fm = self.frame_meta_host()
         n = int(m.n_rays)
         host = {
@@ -215,7 +216,7 @@ class DeviceBatch:
         tot = int(sum(m.level_cnt[k] for k in range(nl)))
         nodes = {k: self.nodes[k][:tot].cpu().numpy() for k in NODE_KEYS}
         pairs = {}
-        for lv in range(1, nl + 1):
+        for lv in range(1, nl + 1 if with_pairs else 1):
             if self.keep_levels or lv == 1:
                 c = int(min(m.pairs[lv - 1], self.pair_capacity))
                 t, nd = self.level_buf(lv)

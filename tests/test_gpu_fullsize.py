@@ -75,7 +75,7 @@ def test_full_size_frame(name, n_top, n_brute):
     for a, c in zip(g["hit"][1:], b[1:]):
         assert np.allclose(a[rs], c, rtol=1e-5, atol=0)
     print(f"[fullsize] {name}: ok ({g['n']} rays, {len(t1)} level-1 pairs)", flush=True)
-    # the fused last level (the configuration bench.py times): the same
+    # the last level fused with the final tests (crsh_leaf_hit): the same
     # closest hits and counters as the stored-pair path above
     print(f"[fullsize] {name}: fused last level", flush=True)
     f = gu.run_pipeline(wl, pair_capacity=1 << 26, keep_levels=False, leaf_hit=True)
@@ -85,3 +85,43 @@ def test_full_size_frame(name, n_top, n_brute):
         assert f[k] == g[k], k
     for lv in range(1, nl + 1):
         assert f["tests"][lv] == g["tests"][lv] and f["hits"][lv] == g["hits"][lv], lv
+
+
+def test_batch_64_full_size():
+    """The batched form at full size (64 frames, ~14 M rays, ~3.2 M
+    triangles) in the configuration bench.py times (B=16, F=4, n=5,
+    hit_block=256): keys, sorted order, nodes and closest hits of the three
+    smallest frames against the oracle, and in every frame the closest hits
+    of a random ray sample against naive ray tracing."""
+    import dataclasses
+    from workloads.scenes import make_batch
+    from paper_2312_06538_amd.batch import DeviceBatch
+    print("[batch fullsize] building 64 frames", flush=True)
+    wls = [dataclasses.replace(w, B=16, F=4, n=5) for w in make_batch(0, 64)]
+    db = DeviceBatch(wls, 16, 4, 5, 256, pair_capacity=1 << 24)
+    m = db.run_with_retry()
+    print(f"[batch fullsize] {int(m.n_rays)} rays", flush=True)
+    res = db.frame_results(m, with_pairs=False)
+    order = sorted(range(len(wls)), key=lambda f: res[f]["n"] * wls[f].scene.m)
+    for f in order[:3]:
+        wl, r = wls[f], res[f]
+        print(f"[batch fullsize] frame {f}: {r['n']} rays, {wl.scene.m} triangles, oracle", flush=True)
+        o = O.run_pipeline(wl)
+        assert r["n"] == o["hash"]["n"]
+        assert np.array_equal(r["keys"], o["hash"]["keys"])
+        assert np.array_equal(r["sorted_ids"], o["sorted_ids"])
+        for k in O.NODE_FIELDS:
+            assert np.array_equal(_bits(r["nodes"][k]), _bits(o["tree"]["nodes"][k])), k
+        assert np.array_equal(r["hit"][0], o["hits"][0])
+        for a, b in zip(r["hit"][1:], o["hits"][1:]):
+            assert np.array_equal(_bits(a), _bits(b))
+    rng = np.random.default_rng(5)
+    for f, (wl, r) in enumerate(zip(wls, res)):
+        if r["n"] == 0:
+            continue
+        rs = rng.choice(r["n"], min(16, r["n"]), replace=False)
+        b = O.brute_closest_hit(r["rays"], rs, wl.scene, wl.t_min)
+        assert np.array_equal(r["hit"][0][rs], b[0]), f
+        for a, c in zip(r["hit"][1:], b[1:]):
+            assert np.allclose(a[rs], c, rtol=1e-5, atol=0), f
+    print("[batch fullsize] ok", flush=True)
