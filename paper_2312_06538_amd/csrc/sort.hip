@@ -26,6 +26,10 @@ constexpr uint32_t SORT_THREADS = 256;
 constexpr uint32_t PASS_THREADS = CRSH_SORT_PASS_THREADS;  // threads of a pass tile
 constexpr uint32_t PASS_ITEMS = CRSH_SORT_PASS_ITEMS;      // keys per thread
 constexpr uint32_t PASS_TILE = PASS_THREADS * PASS_ITEMS;  // keys per pass tile (8192)
+#ifndef CRSH_SORT_HIST_BLOCKS
+#define CRSH_SORT_HIST_BLOCKS 1024
+#endif
+constexpr uint32_t SORT_HIST_BLOCKS = CRSH_SORT_HIST_BLOCKS;  // most blocks of the histogram kernel
 
 // look-back words: flag in bits 31-30 (1 tile count, 2 inclusive prefix)
 constexpr uint32_t SLB_AGG = 1u << 30;
@@ -62,37 +66,43 @@ __global__ void k_sort_clear(uint32_t *hist, sort_ctl *ctl, uint32_t *flags, con
     if (g < sizeof(sort_ctl) / 4) ((uint32_t *)ctl)[g] = 0;
 }
 
-// The digit histograms of every pass in one read of the keys: a block's
-// keys are all loaded before any is counted (the counting is LDS atomics;
-// the loads must not wait on them one by one).
+// The digit histograms of every pass in one read of the keys.  Blocks walk
+// tiles of SORT_TILE keys (grid-stride), counting in LDS, and add their
+// counts to the global histograms once at the end: one global atomic per
+// bin per block, not per tile (every block's atomics go to the same few
+// cache lines).  A tile's keys are all loaded before any is counted.
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint32_t *keys, const uint32_t *vals,
                                                             const uint32_t *frame_of, const crsh_meta *meta,
                                                             uint32_t *hist, uint32_t cap)
 {
     constexpr uint32_t PER = SORT_TILE / SORT_THREADS;
     __shared__ uint32_t h[MAX_PASSES * 256];
-    uint32_t n = min(meta->n_rays, cap);
-    uint32_t base = blockIdx.x * SORT_TILE;
-    if (base >= n) return;
+    const uint32_t n = min(meta->n_rays, cap);
+    const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+    if (blockIdx.x >= ntiles) return;
     for (uint32_t i = threadIdx.x; i < MAX_PASSES * 256; i += SORT_THREADS) h[i] = 0;
-    uint32_t k[PER], f[PER];
-#pragma unroll
-    for (uint32_t r = 0; r < PER; ++r) {
-        const uint32_t g = base + r * SORT_THREADS + threadIdx.x;
-        k[r] = g < n ? keys[g] : 0u;
-        f[r] = (frame_of && g < n) ? vals[g] : 0u;
-    }
-    if (frame_of) {
-#pragma unroll
-        for (uint32_t r = 0; r < PER; ++r) f[r] = base + r * SORT_THREADS + threadIdx.x < n ? frame_of[f[r]] : 0u;
-    }
     __syncthreads();
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t base = tile * SORT_TILE;
+        uint32_t k[PER], f[PER];
 #pragma unroll
-    for (uint32_t r = 0; r < PER; ++r) {
-        if (base + r * SORT_THREADS + threadIdx.x >= n) continue;
+        for (uint32_t r = 0; r < PER; ++r) {
+            const uint32_t g = base + r * SORT_THREADS + threadIdx.x;
+            k[r] = g < n ? keys[g] : 0u;
+            f[r] = (frame_of && g < n) ? vals[g] : 0u;
+        }
+        if (frame_of) {
 #pragma unroll
-        for (uint32_t p = 0; p < SORT_PASSES; ++p) atomicAdd(&h[p * 256 + ((k[r] >> (8 * p)) & 255u)], 1u);
-        if (frame_of) atomicAdd(&h[SORT_PASSES * 256 + (f[r] & 255u)], 1u);
+            for (uint32_t r = 0; r < PER; ++r)
+                f[r] = base + r * SORT_THREADS + threadIdx.x < n ? frame_of[f[r]] : 0u;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < PER; ++r) {
+            if (base + r * SORT_THREADS + threadIdx.x >= n) continue;
+#pragma unroll
+            for (uint32_t p = 0; p < SORT_PASSES; ++p) atomicAdd(&h[p * 256 + ((k[r] >> (8 * p)) & 255u)], 1u);
+            if (frame_of) atomicAdd(&h[SORT_PASSES * 256 + (f[r] & 255u)], 1u);
+        }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < MAX_PASSES * 256; i += SORT_THREADS)
@@ -409,7 +419,8 @@ crsh_status sort_launch(const uint32_t *keys_in, const uint32_t *ids_in, const u
     k_sort_clear<<<1024, 256, 0, stream>>>(hist, ctl, flags, meta, tiles_cap, capacity);
     {
         prof_scope ps("k_sort_hist", stream);
-        k_sort_hist<<<tiles_cap, SORT_THREADS, 0, stream>>>(keys_in, ids_in, frame_of, meta, hist, capacity);
+        k_sort_hist<<<std::min<uint32_t>(tiles_cap, SORT_HIST_BLOCKS), SORT_THREADS, 0, stream>>>(
+            keys_in, ids_in, frame_of, meta, hist, capacity);
     }
     k_sort_plan<<<1, 256, 0, stream>>>(hist, ctl, meta, capacity, passes);
     sort_bufs b{keys_in, ids_in, keys_out, ids_out, kalt, valt};
