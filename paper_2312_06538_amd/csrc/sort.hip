@@ -178,34 +178,41 @@ __device__ __forceinline__ uint32_t pass_digit(uint32_t key, uint32_t val, bool 
 
 // Stable rank of a tile inside each wave: rounds in order, lanes in order.
 // Element r of the thread gets its rank among the wave's elements of equal
-// digit (slot[r]); s_wcnt[w * 256 + d] ends as wave w's count of digit d.
-// Peers of equal digit are found with one ballot per digit bit; the lowest
-// peer adds the group's count.
+// digit, with the digit in the high half (slot[r] = d << 16 | rank);
+// s_wcnt[w * 256 + d] ends as wave w's count of digit d.  Peers of equal
+// digit are found with one ballot per digit bit: a lane keeps the ballot
+// where its own bit is set and the complement where it is clear: the lanes
+// whose bit is clear, XOR the lane's bit spread over a word, folded into the
+// running AND as one three-input bit operation (every lane of the wave is
+// active here).  The last peer adds the group's count.
 template <bool FRAME, uint32_t ITEMS>
 __device__ __forceinline__ void rank_tile(const uint32_t *key, const uint32_t *val, uint32_t base, uint32_t n,
                                           uint32_t shift, const uint32_t *frame_of, uint32_t *s_wcnt,
                                           uint32_t *slot)
 {
+    // truth table of a & (b ^ c) over the operand patterns 0xF0, 0xCC, 0xAA
+    constexpr uint32_t AND_XOR = 0xF0u & (0xCCu ^ 0xAAu);
     const uint32_t w = threadIdx.x / WAVE;
     const uint32_t l = lane_id();
 #pragma unroll
     for (uint32_t r = 0; r < ITEMS; ++r) {
-        const uint32_t g = base + r * WAVE + l;
-        const bool ok = g < n;
+        const bool ok = base + r * WAVE + l < n;
         const uint32_t d = pass_digit<FRAME>(key[r], val[r], ok, shift, frame_of);
-        uint64_t peers = ballot(ok);
+        const uint64_t live = ballot(ok);
+        uint32_t plo = (uint32_t)live, phi = (uint32_t)(live >> 32);
 #pragma unroll
         for (uint32_t b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = ballot(bit);
-            peers &= bit ? m : ~m;
+            const uint32_t sb = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1u);    // 0 or ~0
+            const uint64_t nm = __builtin_amdgcn_uicmp(sb, 0u, 32);    // lanes whose bit b is clear (32: equal)
+            plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)nm, sb, AND_XOR);
+            phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(nm >> 32), sb, AND_XOR);
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t before = rank_below(peers);
         const uint32_t cnt = (uint32_t)__popcll(peers);
-        const uint32_t leader = (uint32_t)__builtin_ctzll(peers | (1ull << 63));
         const uint32_t wbase = ok ? s_wcnt[w * 256 + d] : 0u;
-        slot[r] = wbase + before;
-        if (ok && l == leader) s_wcnt[w * 256 + d] = wbase + cnt;
+        slot[r] = (d << 16) | (wbase + before);
+        if (ok && before + 1u == cnt) s_wcnt[w * 256 + d] = wbase + cnt;
     }
 }
 
@@ -217,88 +224,72 @@ __device__ __forceinline__ void rank_tile(const uint32_t *key, const uint32_t *v
 // then the other), so each phase's stores are runs of consecutive positions
 // per digit.  The run length per digit grows with the tile, and with it the
 // efficiency of the scattered writes.
+template <uint32_t THREADS, uint32_t ITEMS>
+struct pass_lds {
+    uint32_t buf[THREADS * ITEMS];         // the tile, at its sorted slots
+    uint32_t wcnt[THREADS / WAVE * 256];   // per wave and digit: count, then tile-local start
+    uint32_t hist[256];
+    uint32_t base[256];
+    uint32_t scan[256 / WAVE];
+    uint32_t tile;
+};
+
 template <bool FRAME, uint32_t THREADS, uint32_t ITEMS>
-__global__ __launch_bounds__(THREADS) void k_sort_pass(sort_bufs bufs, const uint32_t *offsets, sort_ctl *ctl,
-                                                       uint32_t *flags, uint32_t pass, uint32_t tiles_cap,
-                                                       const uint32_t *frame_of)
+__device__ __forceinline__ void sort_tile(pass_lds<THREADS, ITEMS> &S, const uint32_t *kin, const uint32_t *vin,
+                                          uint32_t *kout, uint32_t *vout, const uint32_t *offsets, uint32_t *fl,
+                                          uint32_t pass, uint32_t n, uint32_t tile, const uint32_t *frame_of)
 {
     constexpr uint32_t TILE = THREADS * ITEMS;
     constexpr uint32_t WAVES = THREADS / WAVE;
-    static_assert(THREADS >= 256 && THREADS % 256 == 0, "one thread per digit");
-    static_assert(TILE % SORT_TILE == 0, "look-back words are sized for SORT_TILE tiles");
-    __shared__ uint32_t s_buf[TILE];
-    __shared__ uint32_t s_wcnt[WAVES * 256];
-    __shared__ uint32_t s_hist[256];
-    __shared__ uint32_t s_base[256];
-    __shared__ uint32_t s_start[256];
-    __shared__ uint32_t s_scan[256 / WAVE];
-    __shared__ uint32_t s_tile;
-
-    const uint32_t src = ctl->src[pass];
-    if (src == BUF_SKIP) return;
-    const uint32_t dst = ctl->dst[pass];
-    const uint32_t n = ctl->n;
-    const uint32_t ntiles = (n + TILE - 1) / TILE;
-    if (threadIdx.x == 0) s_tile = atomicAdd(&ctl->tile_ctr[pass], 1u);
-    for (uint32_t i = threadIdx.x; i < WAVES * 256; i += THREADS) s_wcnt[i] = 0;
-    if (threadIdx.x < 256) s_hist[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    if (tile >= ntiles) return;
-
-    const uint32_t *kin = pick_src(bufs, src, true);
-    const uint32_t *vin = pick_src(bufs, src, false);
     const uint32_t w = threadIdx.x / WAVE;
     const uint32_t l = lane_id();
     const uint32_t shift = 8 * (pass & 3u);
     const uint32_t base = tile * TILE + w * (WAVE * ITEMS);
     const uint32_t d = threadIdx.x;
-    uint32_t *fl = flags + ((size_t)pass * tiles_cap) * 256;
 
     uint32_t key[ITEMS], val[ITEMS], slot[ITEMS];
 #pragma unroll
     for (uint32_t r = 0; r < ITEMS; ++r) {
-        uint32_t g = base + r * WAVE + l;
-        bool ok = g < n;
+        const uint32_t g = base + r * WAVE + l;
+        const bool ok = g < n;
         key[r] = ok ? kin[g] : 0xFFFFFFFFu;
         val[r] = ok ? vin[g] : 0u;
     }
     // the tile's digit counts, published before the ranking: the ranking
     // then overlaps the wait for the predecessors' counts
 #pragma unroll
-    for (uint32_t r = 0; r < ITEMS; ++r) {
-        uint32_t g = base + r * WAVE + l;
-        if (g < n) atomicAdd(&s_hist[pass_digit<FRAME>(key[r], val[r], true, shift, frame_of)], 1u);
-    }
+    for (uint32_t r = 0; r < ITEMS; ++r)
+        if (base + r * WAVE + l < n)
+            atomicAdd(&S.hist[pass_digit<FRAME>(key[r], val[r], true, shift, frame_of)], 1u);
     __syncthreads();
     uint32_t run = 0;
     if (d < 256) {
-        run = s_hist[d];
+        run = S.hist[d];
         __hip_atomic_store(&fl[(size_t)tile * 256 + d], (tile == 0 ? SLB_INC : SLB_AGG) | run, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
     }
-    rank_tile<FRAME, ITEMS>(key, val, base, n, shift, frame_of, s_wcnt, slot);
-    __syncthreads();
-    // per digit (threads 0..255): offsets of the waves, tile-local digit
-    // start, and the look-back for the tile's global offset of the digit
+    rank_tile<FRAME, ITEMS>(key, val, base, n, shift, frame_of, S.wcnt, slot);
+    // tile-local start of each digit (scan of the tile's counts)
     if (d < 256) {
-        uint32_t acc = 0;
-#pragma unroll
-        for (uint32_t ww = 0; ww < WAVES; ++ww) {
-            uint32_t c = s_wcnt[ww * 256 + d];
-            s_wcnt[ww * 256 + d] = acc;
-            acc += c;
-        }
         const uint32_t inc = wave_incl_scan(run);
-        if (l == WAVE - 1) s_scan[w] = inc;
+        if (l == WAVE - 1) S.scan[w] = inc;
     }
     __syncthreads();
+    // per digit (threads 0..255): the tile-local start of the digit's slots
+    // of each wave, and the look-back for the tile's global digit offset
     if (d < 256) {
         uint32_t before = 0;
 #pragma unroll
         for (uint32_t i = 0; i < 256 / WAVE; ++i)
-            if (i < w) before += s_scan[i];
+            if (i < w) before += S.scan[i];
         const uint32_t start = before + wave_incl_scan(run) - run;
+        uint32_t acc = start;
+#pragma unroll
+        for (uint32_t ww = 0; ww < WAVES; ++ww) {
+            const uint32_t c = S.wcnt[ww * 256 + d];
+            S.wcnt[ww * 256 + d] = acc;
+            acc += c;
+        }
         uint32_t excl = 0;
         if (tile > 0) {
             int32_t j = (int32_t)tile - 1;
@@ -316,9 +307,8 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(sort_bufs bufs, const uin
             __hip_atomic_store(&fl[(size_t)tile * 256 + d], SLB_INC | (excl + run), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
-        // global position of tile-local sorted slot q of digit d is s_base[d] + q
-        s_base[d] = offsets[pass * 256 + d] + excl - start;
-        s_start[d] = start;
+        // global position of tile-local sorted slot q of digit d is base[d] + q
+        S.base[d] = offsets[pass * 256 + d] + excl - start;
     }
     __syncthreads();
     // phase 1: the array the digit is read from (keys; values for the frame
@@ -326,16 +316,12 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(sort_bufs bufs, const uin
     // global position is kept for phase 2
 #pragma unroll
     for (uint32_t r = 0; r < ITEMS; ++r) {
-        uint32_t g = base + r * WAVE + l;
-        if (g < n) {
-            uint32_t dd = pass_digit<FRAME>(key[r], val[r], true, shift, frame_of);
-            slot[r] += s_start[dd] + s_wcnt[w * 256 + dd];
-            if (slot[r] < TILE) s_buf[slot[r]] = FRAME ? val[r] : key[r];
+        if (base + r * WAVE + l < n) {
+            slot[r] = (slot[r] & 0xFFFFu) + S.wcnt[w * 256 + (slot[r] >> 16)];
+            if (slot[r] < TILE) S.buf[slot[r]] = FRAME ? val[r] : key[r];
         }
     }
     __syncthreads();
-    uint32_t *kout = pick_dst(bufs, dst, true);
-    uint32_t *vout = pick_dst(bufs, dst, false);
     uint32_t *out1 = FRAME ? vout : kout;
     uint32_t *out2 = FRAME ? kout : vout;
     const uint32_t tile_n = min(TILE, n - tile * TILE);
@@ -345,24 +331,51 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(sort_bufs bufs, const uin
         const uint32_t q = threadIdx.x + j * THREADS;
         pos[j] = 0xFFFFFFFFu;
         if (q < tile_n) {
-            const uint32_t x = s_buf[q];
-            pos[j] = s_base[FRAME ? frame_of[x] & 255u : (x >> shift) & 255u] + q;
+            const uint32_t x = S.buf[q];
+            pos[j] = S.base[FRAME ? frame_of[x] & 255u : (x >> shift) & 255u] + q;
             if (pos[j] < n) out1[pos[j]] = x;
         }
     }
     __syncthreads();
     // phase 2: the other array through the same slots
 #pragma unroll
-    for (uint32_t r = 0; r < ITEMS; ++r) {
-        uint32_t g = base + r * WAVE + l;
-        if (g < n && slot[r] < TILE) s_buf[slot[r]] = FRAME ? key[r] : val[r];
-    }
+    for (uint32_t r = 0; r < ITEMS; ++r)
+        if (base + r * WAVE + l < n && slot[r] < TILE) S.buf[slot[r]] = FRAME ? key[r] : val[r];
     __syncthreads();
 #pragma unroll
     for (uint32_t j = 0; j < ITEMS; ++j) {
         const uint32_t q = threadIdx.x + j * THREADS;
-        if (q < tile_n && pos[j] < n) out2[pos[j]] = s_buf[q];
+        if (q < tile_n && pos[j] < n) out2[pos[j]] = S.buf[q];
     }
+}
+
+template <bool FRAME, uint32_t THREADS, uint32_t ITEMS>
+__global__ __launch_bounds__(THREADS) void k_sort_pass(sort_bufs bufs, const uint32_t *offsets, sort_ctl *ctl,
+                                                       uint32_t *flags, uint32_t pass, uint32_t tiles_cap,
+                                                       const uint32_t *frame_of)
+{
+    constexpr uint32_t TILE = THREADS * ITEMS;
+    static_assert(THREADS >= 256 && THREADS % 256 == 0, "one thread per digit");
+    static_assert(TILE % SORT_TILE == 0, "look-back words are sized for SORT_TILE tiles");
+    __shared__ pass_lds<THREADS, ITEMS> S;
+
+    const uint32_t src = ctl->src[pass];
+    if (src == BUF_SKIP) return;
+    const uint32_t dst = ctl->dst[pass];
+    const uint32_t n = ctl->n;
+    const uint32_t ntiles = (n + TILE - 1) / TILE;
+    if (threadIdx.x == 0) S.tile = atomicAdd(&ctl->tile_ctr[pass], 1u);
+    for (uint32_t i = threadIdx.x; i < THREADS / WAVE * 256; i += THREADS) S.wcnt[i] = 0;
+    if (threadIdx.x < 256) S.hist[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t tile = S.tile;
+    if (tile >= ntiles) return;
+    const uint32_t *kin = pick_src(bufs, src, true);
+    const uint32_t *vin = pick_src(bufs, src, false);
+    uint32_t *kout = pick_dst(bufs, dst, true);
+    uint32_t *vout = pick_dst(bufs, dst, false);
+    uint32_t *fl = flags + ((size_t)pass * tiles_cap) * 256;
+    sort_tile<FRAME, THREADS, ITEMS>(S, kin, vin, kout, vout, offsets, fl, pass, n, tile, frame_of);
 }
 
 __global__ void k_sort_copy(const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
