@@ -3,9 +3,11 @@
 // Every level is produced in three launches with no wait between blocks:
 //   count  each work item (top level: one (top node, mesh) pair per wave;
 //          lower levels: a tile of 256 parent pairs, one per thread, every
-//          child unrolled, pipelined over the block's tiles) runs its Eq. 9
-//          tests and records how many pass (lower levels also keep the pass
-//          bits, one per child slot, packed in 32-bit words);
+//          child unrolled, pipelined over the block's tiles -- or, for the
+//          pass forming level 1 of the plain form, one (parent, child) test
+//          per lane) runs its Eq. 9 tests and records how many pass (lower
+//          levels also keep the pass bits, one per child slot, packed in
+//          32-bit words);
 //   scan   exclusive scan of the counts -> output offset of every item;
 //   emit   each item writes its survivors at its offset, in (parent pair,
 //          child) order -- at the top level (node, mesh, triangle) order;
@@ -404,6 +406,97 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     }
 }
 
+// Count pass of the plain form with one (parent pair, child) test per lane:
+// the NF lanes of a parent load its NF consecutive child nodes, so a wave's
+// node loads are contiguous (with a parent per thread, each load instruction
+// strides NF nodes across the lanes and the NF loads touch the same lines NF
+// times).  A round covers LEVEL_THREADS / NF parents; NF rounds make the
+// count tile of LEVEL_TILE parents.  A wave's ballot is the pass bits of its
+// 64 / NF parents in the mask layout of the count pass (NF bits per parent,
+// parent-major), stored as two words.  Used for the pass that forms level 1,
+// whose children are the leaves (the largest node level, past one L2); at
+// the upper levels, whose nodes stay cached, the pipelined parent-per-thread
+// count is faster.
+template <int NF, bool PACKED>
+__global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t parent_level, uint32_t F,
+                                                                     const float4 *__restrict__ na,
+                                                                     const float4 *__restrict__ nb,
+                                                                     const float *__restrict__ ns,
+                                                                     const float4 *__restrict__ tsph, uint32_t m,
+                                                                     pair_levels P, trav_scratch S, crsh_meta *meta)
+{
+    static_assert(LEVEL_PPT == 1 && WAVE % NF == 0, "whole parents per wave");
+    constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per round
+    constexpr uint32_t ROUNDS = NF;               // PR * ROUNDS = LEVEL_TILE
+    __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
+    __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
+    const uint32_t nl = meta->n_levels;
+    if ((uint32_t)parent_level > nl) return;
+    const uint64_t ntiles = level_items(meta, parent_level, 0, P);
+    clear_scan(S, ntiles);                  // the scan that follows reads these
+    const pairs_dev in = P.p[parent_level - 1];
+    if (in.tri == nullptr || P.p[parent_level - 2].tri == nullptr) return;
+    uint64_t nin = meta->pairs[parent_level - 1];
+    nin = nin < in.cap ? nin : in.cap;
+    const uint32_t nk = meta->level_cnt[parent_level - 2];
+    const uint32_t offk = meta->level_off[parent_level - 2];
+    const uint32_t j = threadIdx.x % NF;
+    const uint32_t w = threadIdx.x / WAVE;
+    uint64_t tests = 0;
+    uint32_t parity = 0;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
+        float4 sp[ROUNDS], A[ROUNDS], Bv[ROUNDS];
+        float Sg[ROUNDS];
+        uint32_t okm = 0;                  // bit r: this lane tests a child in round r
+#pragma unroll
+        for (uint32_t r = 0; r < ROUNDS; ++r) {
+            const uint64_t q = tile * LEVEL_TILE + r * PR + threadIdx.x / NF;
+            uint32_t tri = 0u, par = 0xFFFFFFFFu;
+            if (q < nin) pair_get<PACKED>(in, q, tri, par);
+            const uint32_t ch = par * F + j;
+            const bool ok = par != 0xFFFFFFFFu && j < F && ch < nk;
+            if (ok) okm |= 1u << r;
+            const uint32_t g = offk + (ok ? ch : 0u);
+            sp[r] = tsph[tri < m ? tri : 0u];
+            A[r] = na[g];
+            Bv[r] = nb[g];
+            Sg[r] = ns[g];
+        }
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < ROUNDS; ++r) {
+            bool pass = false;
+            if ((okm >> r) & 1u) {
+                ++tests;
+                pass = packed_meets(A[r], Bv[r], Sg[r], mk(sp[r].x, sp[r].y, sp[r].z), sp[r].w);
+            }
+            const uint64_t bal = ballot(pass);
+            if (lane_id() == 0) {
+                const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + w * (WAVE / NF)) * NF;   // a multiple of 64
+                *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal, (uint32_t)(bal >> 32));
+            }
+            c += (uint32_t)__popcll(bal);
+        }
+        // survivors of the tile: wave sums in alternating LDS slots (one
+        // barrier per tile)
+        if (lane_id() == 0) s_red32[parity][w] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) t += s_red32[parity][ww];
+            S.cnt[tile] = t;
+        }
+    }
+    tests = wave_sum(tests);
+    if (lane_id() == 0) s_red[threadIdx.x / WAVE] = tests;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t tt = 0;
+        for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) tt += s_red[ww];
+        if (tt) atomicAdd((unsigned long long *)&meta->tests[parent_level - 2], (unsigned long long)tt);
+    }
+}
+
 // Survivors of a tile are first placed in LDS at their tile-local offsets
 // and then copied out with consecutive lanes writing consecutive pairs, so
 // the stores are coalesced whatever the pass masks.
@@ -631,13 +724,27 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     default: CRSH_COUNT(16, BT, PK); break;                                                                  \
     }
     prof_scope ps("k_level", stream);
-    if (bd) {
+#define CRSH_COUNT_LANES_NF(PK)                                                                              \
+    switch (nf) {                                                                                            \
+    case 2: k_level_count_lanes<2, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
+    case 4: k_level_count_lanes<4, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
+    case 8: k_level_count_lanes<8, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
+    default: k_level_count_lanes<16, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
+    }
+    if (CRSH_COUNT_LANES && !bd && LEVEL_PPT == 1 && L == 2) {
+        if (packed) {
+            CRSH_COUNT_LANES_NF(true)
+        } else {
+            CRSH_COUNT_LANES_NF(false)
+        }
+    } else if (bd) {
         CRSH_COUNT_NF(true, false)
     } else if (packed) {
         CRSH_COUNT_NF(false, true)
     } else {
         CRSH_COUNT_NF(false, false)
     }
+#undef CRSH_COUNT_LANES_NF
 #undef CRSH_COUNT_NF
 #undef CRSH_COUNT
 }
