@@ -197,9 +197,6 @@ constexpr uint32_t LEVEL_THREADS = 256;   // threads of a traversal tile
 #ifndef CRSH_EMIT_PPT
 #define CRSH_EMIT_PPT 2
 #endif
-#ifndef CRSH_COUNT_LANES
-#define CRSH_COUNT_LANES 1   // plain count pass forming level 1: one (parent, child) test per lane
-#endif
 constexpr uint32_t LEVEL_PPT = CRSH_LEVEL_PPT;   // parent pairs per thread of the count pass
 constexpr uint32_t LEVEL_TILE = LEVEL_THREADS * LEVEL_PPT;   // parent pairs per count tile
 constexpr uint32_t EMIT_PPT = CRSH_EMIT_PPT;     // parent pairs per thread of the emit pass

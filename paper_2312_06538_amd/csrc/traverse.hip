@@ -28,6 +28,10 @@
 #include "bounds.hpp"
 #include "traverse.hpp"
 
+#ifndef CRSH_COUNT_LANES
+#define CRSH_COUNT_LANES 1   // plain count pass forming level 1: one (parent, child) test per lane
+#endif
+
 namespace crsh {
 
 __global__ void k_tri_sph(const float *__restrict__ v0x, const float *__restrict__ v0y,
