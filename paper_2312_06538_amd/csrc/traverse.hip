@@ -414,7 +414,7 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
 // the NF lanes of a parent load its NF consecutive child nodes, so a wave's
 // node loads are contiguous (with a parent per thread, each load instruction
 // strides NF nodes across the lanes and the NF loads touch the same lines NF
-// times).  A round covers LEVEL_THREADS / NF parents; NF rounds make the
+// times).  A slice covers LEVEL_THREADS / NF parents; NF slices make the
 // count tile of LEVEL_TILE parents.  A wave's ballot is the pass bits of its
 // 64 / NF parents in the mask layout of the count pass (NF bits per parent,
 // parent-major), stored as two words.  Used for the pass that forms level 1,
@@ -430,8 +430,8 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
                                                                      pair_levels P, trav_scratch S, crsh_meta *meta)
 {
     static_assert(LEVEL_PPT == 1 && WAVE % NF == 0, "whole parents per wave");
-    constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per round
-    constexpr uint32_t ROUNDS = NF;               // PR * ROUNDS = LEVEL_TILE
+    constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per slice
+    constexpr uint32_t SLICES = NF;               // PR * SLICES = LEVEL_TILE
     __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
     __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
     const uint32_t nl = meta->n_levels;
@@ -449,11 +449,11 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
     uint64_t tests = 0;
     uint32_t parity = 0;
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
-        float4 sp[ROUNDS], A[ROUNDS], Bv[ROUNDS];
-        float Sg[ROUNDS];
-        uint32_t okm = 0;                  // bit r: this lane tests a child in round r
+        float4 sp[SLICES], A[SLICES], Bv[SLICES];
+        float Sg[SLICES];
+        uint32_t okm = 0;                  // bit r: this lane tests a child in slice r
 #pragma unroll
-        for (uint32_t r = 0; r < ROUNDS; ++r) {
+        for (uint32_t r = 0; r < SLICES; ++r) {
             const uint64_t q = tile * LEVEL_TILE + r * PR + threadIdx.x / NF;
             uint32_t tri = 0u, par = 0xFFFFFFFFu;
             if (q < nin) pair_get<PACKED>(in, q, tri, par);
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
         }
         uint32_t c = 0;
 #pragma unroll
-        for (uint32_t r = 0; r < ROUNDS; ++r) {
+        for (uint32_t r = 0; r < SLICES; ++r) {
             bool pass = false;
             if ((okm >> r) & 1u) {
                 ++tests;
