@@ -31,6 +31,9 @@
 #ifndef CRSH_COUNT_LANES
 #define CRSH_COUNT_LANES 1   // plain count pass forming level 1: one (parent, child) test per lane
 #endif
+#ifndef CRSH_COUNT_LANES_MIN_BUNDLE
+#define CRSH_COUNT_LANES_MIN_BUNDLE 16   // ... for bundles of at least this many rays
+#endif
 
 namespace crsh {
 
@@ -418,9 +421,10 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
 // count tile of LEVEL_TILE parents.  A wave's ballot is the pass bits of its
 // 64 / NF parents in the mask layout of the count pass (NF bits per parent,
 // parent-major), stored as two words.  Used for the pass that forms level 1,
-// whose children are the leaves (the largest node level, past one L2); at
-// the upper levels, whose nodes stay cached, the pipelined parent-per-thread
-// count is faster.
+// whose children are the leaves (the largest node level, past one L2), with
+// bundles of 16 rays or more: at the upper levels, whose nodes stay cached,
+// and with 4-ray bundles the pipelined parent-per-thread count measured
+// faster.
 template <int NF, bool PACKED>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t parent_level, uint32_t F,
                                                                      const float4 *__restrict__ na,
@@ -710,7 +714,7 @@ void node_pack_launch(const crsh_nodes *nodes, crsh_meta *meta, float4 *na, floa
 
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
-                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed)
+                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed, bool lanes)
 {
     const batch_dev b = bd ? *bd : batch_dev{};
     const uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), 4096);
@@ -735,7 +739,7 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     case 8: k_level_count_lanes<8, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
     default: k_level_count_lanes<16, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
     }
-    if (CRSH_COUNT_LANES && !bd && LEVEL_PPT == 1 && L == 2) {
+    if (CRSH_COUNT_LANES && lanes && !bd && LEVEL_PPT == 1 && L == 2) {
         if (packed) {
             CRSH_COUNT_LANES_NF(true)
         } else {
@@ -899,7 +903,8 @@ static crsh_status traverse_run(const crsh_nodes *nodes, const crsh_scene *scene
     case 8: CRSH_EMIT(8, BT, PK); break;                                                                   \
     default: CRSH_EMIT(16, BT, PK); break;                                                                 \
     }
-        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream, packed);
+        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream, packed,
+                           bundle >= CRSH_COUNT_LANES_MIN_BUNDLE);
         k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
             prof_scope ps("k_level_emit", stream);
