@@ -187,6 +187,28 @@ def test_traverse_bit_exact(name):
     assert g["mesh_hits"] == tr["mesh_hits"]
 
 
+@pytest.mark.parametrize("B,F,n", [(16, 2, 4), (16, 3, 3), (16, 8, 3), (32, 16, 2), (24, 4, 4), (8, 4, 4)])
+def test_traverse_shapes(B, F, n):
+    """Traversal pairs, node tests and survivors of every level for merge
+    factors 2..16 and bundles on both sides of 16 rays (the level-1 count
+    runs one (parent, child) test per lane from B = 16 on, with NF = the
+    merge factor rounded up to a power of two lanes per parent)."""
+    base, kw = small("refl_96")
+    print(f"[traverse-shape] B={B} F={F} n={n}", flush=True)
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    tree = O.build_tree(o["hash"]["rays"], o["sorted_ids"], B, F, n)
+    ot = O.traverse(tree, wl.scene, 0, wl.scene.m)
+    cap = max([len(t) for t, _ in ot["pairs"].values()] + [1]) + 4096
+    g = _gu().gpu_traverse(tree, wl.scene, B, F, capacity=cap)
+    assert g["status"] == 0
+    for lv in ot["pairs"]:
+        assert _same(g["pairs"][lv][0], ot["pairs"][lv][0]), lv
+        assert _same(g["pairs"][lv][1], ot["pairs"][lv][1]), lv
+        assert g["tests"][lv] == ot["tests"][lv], lv
+        assert g["hits"][lv] == ot["hits"][lv], lv
+
+
 def test_traverse_triangle_batches():
     base, kw = small("refl_96")
     wl = workload(base, **kw)
