@@ -216,14 +216,7 @@ __device__ __forceinline__ void rank_tile(const uint32_t *key, const uint32_t *v
     }
 }
 
-// One radix pass over tiles of THREADS * ITEMS keys.  A tile counts its
-// digits and publishes the counts for the decoupled look-back first, then
-// ranks its keys stably in registers and LDS (while its predecessors publish
-// theirs), reads its global digit offsets from the look-back, and writes out
-// through one LDS buffer in two phases (the array the digit comes from first,
-// then the other), so each phase's stores are runs of consecutive positions
-// per digit.  The run length per digit grows with the tile, and with it the
-// efficiency of the scattered writes.
+// LDS of one pass tile.
 template <uint32_t THREADS, uint32_t ITEMS>
 struct pass_lds {
     uint32_t buf[THREADS * ITEMS];         // the tile, at its sorted slots
@@ -234,6 +227,14 @@ struct pass_lds {
     uint32_t tile;
 };
 
+// One radix pass over tiles of THREADS * ITEMS keys.  A tile counts its
+// digits and publishes the counts for the decoupled look-back first, then
+// ranks its keys stably in registers and LDS (while its predecessors publish
+// theirs), reads its global digit offsets from the look-back, and writes out
+// through one LDS buffer in two phases (the array the digit comes from first,
+// then the other), so each phase's stores are runs of consecutive positions
+// per digit.  The run length per digit grows with the tile, and with it the
+// efficiency of the scattered writes.
 template <bool FRAME, uint32_t THREADS, uint32_t ITEMS>
 __device__ __forceinline__ void sort_tile(pass_lds<THREADS, ITEMS> &S, const uint32_t *kin, const uint32_t *vin,
                                           uint32_t *kout, uint32_t *vout, const uint32_t *offsets, uint32_t *fl,
