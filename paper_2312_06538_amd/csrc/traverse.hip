@@ -712,6 +712,21 @@ void node_pack_launch(const crsh_nodes *nodes, crsh_meta *meta, float4 *na, floa
     k_node_pack<<<g, 256, 0, stream>>>(nd, meta, na, nb, ns, clear_pairs);
 }
 
+// Blocks of a persistent grid-stride kernel that fit the device at once.  Its
+// blocks get equal shares of the tiles, so they finish in rounds of this many;
+// a grid of whole rounds leaves no round partly empty.  0 if unknown.
+template <typename K>
+static uint32_t resident_blocks(K kernel, uint32_t threads)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)threads, 0) != hipSuccess || cus < 1 ||
+        per_cu < 1)
+        return 0;
+    return (uint32_t)cus * (uint32_t)per_cu;
+}
+
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
                         const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed, bool lanes)
@@ -732,12 +747,18 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     default: CRSH_COUNT(16, BT, PK); break;                                                                  \
     }
     prof_scope ps("k_level", stream);
+#define CRSH_COUNT_LANES_ONE(NF, PK)                                                                         \
+    {                                                                                                        \
+        const uint32_t rb = resident_blocks(k_level_count_lanes<NF, PK>, LEVEL_THREADS);                     \
+        const uint32_t gl = rb ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), rb) : g;    \
+        k_level_count_lanes<NF, PK><<<gl, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); \
+    }
 #define CRSH_COUNT_LANES_NF(PK)                                                                              \
     switch (nf) {                                                                                            \
-    case 2: k_level_count_lanes<2, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
-    case 4: k_level_count_lanes<4, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
-    case 8: k_level_count_lanes<8, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
-    default: k_level_count_lanes<16, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); break; \
+    case 2: CRSH_COUNT_LANES_ONE(2, PK) break;                                                               \
+    case 4: CRSH_COUNT_LANES_ONE(4, PK) break;                                                               \
+    case 8: CRSH_COUNT_LANES_ONE(8, PK) break;                                                               \
+    default: CRSH_COUNT_LANES_ONE(16, PK) break;                                                             \
     }
     if (CRSH_COUNT_LANES && lanes && !bd && LEVEL_PPT == 1 && L == 2) {
         if (packed) {
@@ -753,6 +774,7 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
         CRSH_COUNT_NF(false, false)
     }
 #undef CRSH_COUNT_LANES_NF
+#undef CRSH_COUNT_LANES_ONE
 #undef CRSH_COUNT_NF
 #undef CRSH_COUNT
 }
