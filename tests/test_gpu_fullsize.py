@@ -2,11 +2,17 @@
 in two alternating arrays, capacity grown on overflow).
 
 Checked against the oracle: every key, the whole sorted order and every node
-(the oracle does those in seconds); level-1 pairs and counters restricted to
-an evenly spread sample of top-level sub-trees (sub-trees are independent);
-closest hits of every ray under the sampled sub-trees, and of a random ray
+(the oracle does those in seconds); every traversal counter, the level-1
+pairs of every top-level sub-tree (SHA-256 per sub-tree, in order) and the
+closest hit of every ray (SHA-256 of the triangle ids and of the t, u, v
+bits), against the values that tests/golden/make_fullsize.py wrote by
+running the oracle over the whole frame; the closest hits of a random ray
 sample against naive N x M ray tracing.
 """
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -14,6 +20,8 @@ from conftest import workload
 from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -28,9 +36,46 @@ def _bits(a):
     return a.view(np.uint32) if a.dtype == np.float32 else a
 
 
-@pytest.mark.parametrize("name,n_top,n_brute", [("refl_1024", 6, 512), ("mixed_1080p", 4, 192)])
-def test_full_size_frame(name, n_top, n_brute):
+def _sha(*arrays):
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a))
+    return h.hexdigest()
+
+
+def check_against_golden(g, gold, F):
+    """Counters, per-sub-tree level-1 pair digests and hit digests of a GPU
+    frame against the oracle's full-frame values."""
+    nl = gold["levels"]
+    assert g["n"] == gold["rays"] and g["n_levels"] == nl
+    assert [g["tests"][lv] for lv in range(1, nl + 1)] == gold["tests"]
+    assert [g["hits"][lv] for lv in range(1, nl + 1)] == gold["hits"]
+    for k in ("mesh_tests", "mesh_hits", "final_tests"):
+        assert g[k] == gold[k], k
+    t1, n1 = g["pairs"][1]
+    assert len(t1) == gold["hits"][0]
+    span = F ** (nl - 1)
+    top = n1 // np.uint32(span)
+    assert bool((top[1:] >= top[:-1]).all()), "level-1 pairs not grouped by top-level sub-tree"
+    bounds = np.searchsorted(top, np.arange(gold["top_nodes"] + 1, dtype=np.uint32))
+    del top
+    for i, p in enumerate(gold["per_top"]):
+        b, e = int(bounds[i]), int(bounds[i + 1])
+        assert e - b == p["n1"], ("level-1 pair count of sub-tree", i)
+        assert _sha(t1[b:e], n1[b:e]) == p["sha"], ("level-1 pairs of sub-tree", i)
+    tri, t, u, v = g["hit"]
+    assert int((tri >= 0).sum()) == gold["hit_count"]
+    assert _sha(tri.astype("<i4")) == gold["hit_tri_sha256"]
+    # t, u, v: the kernels repeat the oracle's operations in its order, so the
+    # bits agree (a stricter bar than the 1e-5 relative tolerance)
+    for a, k in ((t, "t"), (u, "u"), (v, "v")):
+        assert _sha(_bits(a).astype("<u4")) == gold[f"hit_{k}_sha256"], k
+
+
+@pytest.mark.parametrize("name,n_brute", [("refl_1024", 512), ("mixed_1080p", 192)])
+def test_full_size_frame(name, n_brute):
     import gpu_util as gu
+    gold = json.load(open(os.path.join(GOLDEN, f"fullsize_{name}.json")))
     print(f"[fullsize] {name}: building workload", flush=True)
     wl = workload(name)
     print(f"[fullsize] {name}: GPU frame", flush=True)
@@ -48,25 +93,9 @@ def test_full_size_frame(name, n_top, n_brute):
     for k in O.NODE_FIELDS:
         assert np.array_equal(_bits(g["nodes"][k]), _bits(tree["nodes"][k])), k
     nl = tree["n_levels"]
-    ntop = int(tree["level_cnt"][nl - 1])
-    assert g["mesh_tests"] == ntop * wl.scene.n_mesh
-    # sampled sub-trees: level-1 pairs, in order
-    sub = np.unique(np.linspace(0, ntop - 1, n_top).astype(np.uint32))
-    print(f"[fullsize] {name}: oracle traversal of top nodes {sub.tolist()}", flush=True)
-    tr = O.traverse(tree, wl.scene, top_subset=sub)
-    span = wl.F ** (nl - 1)
-    t1, n1 = g["pairs"][1]
-    keep = np.isin(n1.astype(np.int64) // span, sub.astype(np.int64))
-    assert np.array_equal(t1[keep], tr["pairs"][1][0])
-    assert np.array_equal(n1[keep], tr["pairs"][1][1])
-    # closest hits of every ray under the sampled sub-trees
-    hits = O.closest_hit(h["rays"], ids, wl.B, tr["pairs"][1], wl.scene, wl.t_min)
-    ray_span = wl.B * span
-    pos = np.concatenate([np.arange(int(s) * ray_span, min((int(s) + 1) * ray_span, h["n"])) for s in sub])
-    rid = ids[pos].astype(np.int64)
-    assert np.array_equal(g["hit"][0][rid], hits[0][rid])
-    for a, b in zip(g["hit"][1:], hits[1:]):
-        assert np.allclose(a[rid], b[rid], rtol=1e-5, atol=0)
+    assert int(tree["level_cnt"][nl - 1]) == gold["top_nodes"]
+    print(f"[fullsize] {name}: counters, level-1 pairs and hits against the oracle's full frame", flush=True)
+    check_against_golden(g, gold, wl.F)
     # a random ray sample against naive ray tracing
     print(f"[fullsize] {name}: brute force on {n_brute} rays", flush=True)
     rs = np.random.default_rng(3).choice(h["n"], n_brute, replace=False)
@@ -74,10 +103,11 @@ def test_full_size_frame(name, n_top, n_brute):
     assert np.array_equal(g["hit"][0][rs], b[0])
     for a, c in zip(g["hit"][1:], b[1:]):
         assert np.allclose(a[rs], c, rtol=1e-5, atol=0)
-    print(f"[fullsize] {name}: ok ({g['n']} rays, {len(t1)} level-1 pairs)", flush=True)
+    print(f"[fullsize] {name}: ok ({g['n']} rays, {len(g['pairs'][1][0])} level-1 pairs)", flush=True)
     # the last level fused with the final tests (crsh_leaf_hit): the same
     # closest hits and counters as the stored-pair path above
     print(f"[fullsize] {name}: fused last level", flush=True)
+    del g["pairs"]
     f = gu.run_pipeline(wl, pair_capacity=1 << 26, keep_levels=False, leaf_hit=True)
     for a, b in zip(f["hit"], g["hit"]):
         assert np.array_equal(_bits(a), _bits(b))

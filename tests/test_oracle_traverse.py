@@ -245,3 +245,29 @@ def test_top_subset_restricts_to_subtrees():
         want = np.sort((n[keep].astype(np.int64) << 32) | t[keep])
         ts, ns = tr["pairs"][lv]
         assert np.array_equal(np.sort((ns.astype(np.int64) << 32) | ts), want)
+
+
+@pytest.mark.parametrize("name", ["refl_1024", "mixed_1080p"])
+def test_fullsize_golden_is_self_consistent(name):
+    """The full-frame values written by tests/golden/make_fullsize.py (oracle
+    only) hang together: per-sub-tree level-1 pair counts sum to the level-1
+    count, the chained digest is that of the per-sub-tree digests, level k's
+    tests are the children of level k+1's pairs (R14 with full nodes except
+    ragged tails: at most F per parent pair), and the final tests are at most
+    B per level-1 pair."""
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"fullsize_{name}.json")
+    g = json.load(open(path))
+    assert g["written_by"].startswith("tests/golden/make_fullsize.py")
+    assert len(g["per_top"]) == g["top_nodes"]
+    assert sum(p["n1"] for p in g["per_top"]) == g["hits"][0]
+    chain = hashlib.sha256("".join(p["sha"] for p in g["per_top"]).encode()).hexdigest()
+    assert chain == g["pairs1_sha256"]
+    nl = g["levels"]
+    for k in range(nl - 1):
+        assert g["tests"][k] <= g["F"] * g["hits"][k + 1]
+        assert g["tests"][k] >= g["hits"][k]
+    assert g["final_tests"] <= g["B"] * g["hits"][0]
+    assert g["tests"][nl - 1] >= g["hits"][nl - 1]
+    assert g["mesh_hits"] <= g["mesh_tests"]
+    assert 0 < g["hit_count"] <= g["rays"]

@@ -317,5 +317,48 @@ def unsorted_variant(wl, levels=16):
 MAKERS = {"shadow_128": make_shadow_128, "refl_1024": make_refl_1024, "mixed_1080p": make_mixed_1080p, "adjoint_512": make_adjoint_512}
 
 
-def make_workload(name, seed=0, **kw):
-    return MAKERS[name](seed=seed, **kw)
+def _save(wl, path):
+    """Every array of a workload into one .npz (no pickled objects)."""
+    sc = wl.scene
+    a = {f"scene_{k}": getattr(sc, k) for k in ("tris", "mesh_first", "mesh_count", "mesh_sphere", "mesh_mat",
+                                                 "mat_flags", "mat_ior", "verts", "faces")
+         if getattr(sc, k) is not None}
+    a.update({f"gbuf_{k}": v for k, v in wl.gbuf.items()})
+    for k in ("eye", "look", "lights", "lo", "inv_ext"):
+        a[k] = getattr(wl, k)
+    a["ints"] = np.array([wl.seed, wl.W, wl.H, wl.B, wl.F, wl.n, wl.ray_types], np.int64)
+    a["floats"] = np.array([wl.vfov, wl.eps_off, wl.eps_shadow, wl.t_min], np.float64)
+    a["name"] = np.array(wl.name)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **a)
+    import os
+    os.replace(tmp, path)
+
+
+def _load(path):
+    with np.load(path, allow_pickle=False) as z:
+        g = {k: z[k] for k in z.files}
+    sc = Scene(**{k[6:]: v for k, v in g.items() if k.startswith("scene_")})
+    seed, W, H, B, F, n, types = (int(x) for x in g["ints"])
+    vfov, eps_off, eps_shadow, t_min = (float(x) for x in g["floats"])
+    return Workload(name=str(g["name"]), seed=seed, scene=sc, W=W, H=H, eye=g["eye"], look=g["look"], vfov=vfov,
+                    lights=g["lights"], gbuf={k[5:]: v for k, v in g.items() if k.startswith("gbuf_")}, B=B, F=F,
+                    n=n, ray_types=types, eps_off=eps_off, eps_shadow=eps_shadow, t_min=t_min, lo=g["lo"],
+                    inv_ext=g["inv_ext"])
+
+
+def make_workload(name, seed=0, cache_dir=None, **kw):
+    """Build a named workload.  With `cache_dir` (or the CRSH_WORKLOAD_CACHE
+    environment variable) the default-sized workload is kept there as an
+    .npz and reloaded by later calls with the same name and seed."""
+    import os
+    cache_dir = cache_dir or os.environ.get("CRSH_WORKLOAD_CACHE")
+    if not cache_dir or kw:
+        return MAKERS[name](seed=seed, **kw)
+    path = os.path.join(cache_dir, f"{name}_seed{seed}.npz")
+    if os.path.exists(path):
+        return _load(path)
+    wl = MAKERS[name](seed=seed)
+    os.makedirs(cache_dir, exist_ok=True)
+    _save(wl, path)
+    return wl
