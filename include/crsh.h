@@ -218,6 +218,22 @@ crsh_status crsh_hash(const crsh_gbuf *gbuf, const crsh_raygen *rg, crsh_rays *o
                       uint32_t *keys, uint32_t *ids, crsh_meta *meta,
                       void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* crsh_hash without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments (less ws / ws_bytes), kernels and results
+ * as crsh_hash.  Its scratch -- one 32-bit ray count per block of 256 pixels,
+ * 512.25 KiB -- is a static device array that each GPU holds from the first
+ * call on that GPU until the process ends; the call allocates nothing.
+ * Every call on one GPU shares that GPU's array, so calls that overlap on one
+ * GPU (concurrent streams or threads) race: serialise them.  The array needs
+ * no clearing between calls.  The stream must belong to the current device.
+ * Errors: CRSH_ERR_INVALID for more than CRSH_HASH_STATIC_MAX_PIXELS pixels
+ * (nothing launched) and for crsh_hash's argument errors; CRSH_ERR_HIP if the
+ * array's device address cannot be obtained. */
+#define CRSH_HASH_STATIC_MAX_PIXELS (1ull << 25)
+crsh_status crsh_hash_static(const crsh_gbuf *gbuf, const crsh_raygen *rg, crsh_rays *out,
+                             uint32_t *keys, uint32_t *ids, crsh_meta *meta, hipStream_t stream);
+
 /* Stage 2 -- ray sorting (Sec. 3.3.3-3.3.5).  Stable LSD radix sort of the
  * meta->n_rays (key, id) pairs by the 32-bit key; equal keys keep their input
  * order.  Inputs are not modified; outputs hold `capacity` entries.  Digit

@@ -141,6 +141,8 @@ def lib():
         L.crsh_hash.restype = st
         L.crsh_hash.argtypes = [C.POINTER(Gbuf), C.POINTER(Raygen), C.POINTER(Rays), vp, vp, vp, vp,
                                 C.c_size_t, vp]
+        L.crsh_hash_static.restype = st
+        L.crsh_hash_static.argtypes = [C.POINTER(Gbuf), C.POINTER(Raygen), C.POINTER(Rays), vp, vp, vp, vp]
         L.crsh_bounce.restype = st
         L.crsh_bounce.argtypes = [C.POINTER(Rays), vp, C.POINTER(Hits), vp, C.POINTER(Scene), vp, C.POINTER(Raygen),
                                   C.POINTER(Rays), vp, vp, vp, vp, C.c_size_t, vp]
@@ -223,6 +225,10 @@ def crsh_read_meta(meta, stream, allow_capacity=True):
 def crsh_hash(gbuf, raygen, rays, keys, ids, meta, ws, ws_bytes, stream):
     return _check(lib().crsh_hash(C.byref(gbuf), C.byref(raygen), C.byref(rays), keys, ids, meta, ws, ws_bytes,
                                   stream))
+
+
+def crsh_hash_static(gbuf, raygen, rays, keys, ids, meta, stream):
+    return _check(lib().crsh_hash_static(C.byref(gbuf), C.byref(raygen), C.byref(rays), keys, ids, meta, stream))
 
 
 def crsh_bounce(parents, parent_keys, hits, parent_meta, scene, tri_mat, raygen, out, keys, ids, meta, ws, ws_bytes,

@@ -190,6 +190,7 @@ __device__ __forceinline__ uint64_t lookback(uint64_t *flags, uint32_t tile, uin
 constexpr uint32_t SORT_TILE = 4096;      // keys per sort tile
 constexpr uint32_t SORT_PASSES = 4;       // 8-bit digits of a 32-bit key
 constexpr uint32_t HASH_BLOCK = 256;      // pixels per hash block
+constexpr uint64_t HASH_STATIC_MAX_PIXELS = CRSH_HASH_STATIC_MAX_PIXELS;  // crsh_hash_static
 constexpr uint32_t LEVEL_THREADS = 256;   // threads of a traversal tile
 #ifndef CRSH_LEVEL_PPT
 #define CRSH_LEVEL_PPT 1

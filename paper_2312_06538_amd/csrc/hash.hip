@@ -10,6 +10,8 @@
 // ids and the thread of a frame's first pixel records where they start.
 #include <float.h>
 
+#include <mutex>
+
 #include "batch.hpp"
 #include "raygen.hpp"
 
@@ -286,6 +288,76 @@ extern "C" crsh_status crsh_hash(const crsh_gbuf *gbuf, const crsh_raygen *rg, c
         return CRSH_ERR_INVALID;
     }
     return hash_launch(gbuf, rg, nullptr, out, keys, ids, nullptr, meta, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// crsh_hash_static: crsh_hash with its scratch (the per-block ray counts that
+// k_hash_count writes, k_hash_scan turns into offsets and k_hash_emit reads)
+// in a fixed device array instead of a caller workspace, for callers that
+// cannot allocate.  Every block's count is written before it is read, so the
+// array needs no clearing between calls.  In host code `scratch` names a
+// host-side shadow, not device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device and kept.
+namespace crsh {
+
+// one count per block of HASH_BLOCK pixels plus the scan's total, rounded up
+// to whole 256-byte lines as the workspace sizing rounds it
+static __device__ __align__(256) uint32_t scratch[(HASH_STATIC_MAX_PIXELS / HASH_BLOCK + 1 + 63) / 64 * 64];
+
+constexpr int STATIC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[STATIC_MAX_DEVICES];
+
+static crsh_status static_scratch(void **out, const char *who)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES) {
+        set_error("%s: no usable current device", who);
+        return CRSH_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("%s: hipGetSymbolAddress of the static scratch failed on device %d: %s", who, dev,
+                      hipGetErrorString(e));
+            return CRSH_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CRSH_OK;
+}
+
+}  // namespace crsh
+
+extern "C" crsh_status crsh_hash_static(const crsh_gbuf *gbuf, const crsh_raygen *rg, crsh_rays *out,
+                                        uint32_t *keys, uint32_t *ids, crsh_meta *meta, hipStream_t stream)
+{
+    if (!rg || !gbuf) {
+        set_error("crsh_hash_static: NULL argument");
+        return CRSH_ERR_INVALID;
+    }
+    const uint64_t npix = (uint64_t)(gbuf->w > 0 ? gbuf->w : 0) * (uint64_t)(gbuf->h > 0 ? gbuf->h : 0);
+    if (npix > HASH_STATIC_MAX_PIXELS) {
+        set_error("crsh_hash_static: %llu pixels exceed the static scratch's maximum of %llu",
+                  (unsigned long long)npix, (unsigned long long)HASH_STATIC_MAX_PIXELS);
+        return CRSH_ERR_INVALID;
+    }
+    if (stream) {   // the stream must belong to the current device, whose scratch the kernels get
+        hipDevice_t sd = -1;
+        int cur = -1;
+        if (hipStreamGetDevice(stream, &sd) != hipSuccess || hipGetDevice(&cur) != hipSuccess || sd != cur) {
+            set_error("crsh_hash_static: the stream does not belong to the current device");
+            return CRSH_ERR_INVALID;
+        }
+    }
+    void *ws = nullptr;
+    const crsh_status st = static_scratch(&ws, "crsh_hash_static");
+    if (st != CRSH_OK) return st;
+    return hash_launch(gbuf, rg, nullptr, out, keys, ids, nullptr, meta, ws, sizeof(scratch), stream);
 }
 
 namespace crsh {
