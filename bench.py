@@ -104,24 +104,29 @@ _CPU = {}
 
 def _cpu_subtrees(top_nodes):
     """Oracle traversal + final tests of the listed top-level sub-trees (one
-    worker's share).  Runs in a forked worker or in the calling process."""
+    task).  Runs in a forked worker or in the calling process; returns the
+    seconds it took."""
     from oracle import oracle as O
     import numpy as np
     wl, h, ids, tree, tsph = (_CPU[k] for k in ("wl", "h", "ids", "tree", "tsph"))
+    t0 = time.perf_counter()
     for i in top_nodes:
         tr = O.traverse(tree, wl.scene, top_subset=np.array([i], np.uint32), tsph=tsph)
         O.closest_hit(h["rays"], ids, wl.B, tr["pairs"][1], wl.scene, wl.t_min)
-    return len(top_nodes)
+    return time.perf_counter() - t0
 
 
-def cpu_baseline(wl, n_sample_top=64, n_sample_one=8, max_cores=16):
+def cpu_baseline(wl, n_sample_top=64, n_sample_one=4, max_cores=16):
     """The oracle as it stands (sequential C, never tuned) on the host's
     cores.  Hash, sort and build run over the whole frame in one process.
     Traversal and final tests -- by far the larger part -- run over an evenly
-    spread sample of top-level sub-trees, which are independent: once in a
-    pool of one forked process per core (at most `max_cores`, the share of
-    the host a single GPU gets), once in this process alone.  Each time is
-    scaled to the whole frame by the share of rays under the sample.  Must
+    spread sample of top-level sub-trees, which are independent, one
+    sub-tree per task in a pool of one forked process per core (at most
+    `max_cores`, the share of the host a single GPU gets); the pool's wall
+    time, scaled to the whole frame by the share of rays under the sample,
+    gives the multi-core rate.  The one-core rate adds up the sample's
+    per-task times instead, corrected by how much slower a few of its
+    sub-trees ran in the pool than alone in this process afterwards.  Must
     run before this process initialises the GPU (the pool forks)."""
     import multiprocessing as mp
     import numpy as np
@@ -149,24 +154,27 @@ def cpu_baseline(wl, n_sample_top=64, n_sample_one=8, max_cores=16):
     with mp.get_context("fork").Pool(cores) as pool:
         # one sub-tree per task, handed out as workers free up (sub-trees
         # differ in cost by two orders of magnitude)
-        pool.map(_cpu_subtrees, [[i] for i in sub], chunksize=1)
+        task_s = pool.map(_cpu_subtrees, [[i] for i in sub], chunksize=1)
     t["pool_sample"] = time.perf_counter() - t0
     scale = h["n"] / max(rays_under(sub), 1)
     frame_pool = hsb + t["pool_sample"] * scale
-    # one process: a smaller sample, spread the same way
-    one = [int(i) for i in np.unique(np.linspace(0, ntop - 1, min(n_sample_one, ntop)).astype(np.int64))]
-    t0 = time.perf_counter()
-    _cpu_subtrees(one)
-    t["one_sample"] = time.perf_counter() - t0
-    scale1 = h["n"] / max(rays_under(one), 1)
-    frame_one = hsb + t["one_sample"] * scale1
+    # one core: the same sample's task times, with the pool's slowdown
+    # measured on a few of its sub-trees (spread over the sample) run alone
+    pick = sorted(set(int(k) for k in np.linspace(0, len(sub) - 1, min(n_sample_one, len(sub))).astype(np.int64)))
+    alone = sum(_cpu_subtrees([sub[k]]) for k in pick)
+    in_pool = sum(task_s[k] for k in pick)
+    slowdown = in_pool / alone if alone > 0 else 1.0
+    t["one_sample"] = alone
+    t["sample_cpu"] = sum(task_s)
+    frame_one = hsb + sum(task_s) / slowdown * scale
     _CPU.clear()
     return {"value": round(h["n"] / frame_pool, 1), "unit": "secondary rays/s", "cores": cores, "kind": "oracle",
             "sample": (f"hash+sort+build of the whole frame ({h['n']} rays, one process), then traversal and final "
                        f"tests of {len(sub)} of {ntop} top-level sub-trees ({rays_under(sub)} rays) on {cores} "
                        f"forked processes, scaled by {scale:.2f} to the frame"),
             "one_core": {"value": round(h["n"] / frame_one, 1),
-                         "sample": f"{len(one)} of {ntop} sub-trees ({rays_under(one)} rays), scaled by {scale1:.2f}"},
+                         "sample": (f"the same {len(sub)} sub-trees' task times in the pool divided by the pool's "
+                                    f"slowdown {slowdown:.2f} (measured on {len(pick)} of them run alone)")},
             "seconds": {k: round(v, 3) for k, v in t.items()},
             "est_frame_s": round(frame_pool, 2), "est_frame_s_one_core": round(frame_one, 2)}
 
@@ -207,10 +215,10 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="batch_64: JSON cache of tuned points")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-top", type=int, default=64,
+    ap.add_argument("--cpu-sample-top", type=int, default=128,
                     help="top-level sub-trees the oracle traverses in the process pool")
-    ap.add_argument("--cpu-sample-one", type=int, default=8,
-                    help="top-level sub-trees the oracle traverses in one process")
+    ap.add_argument("--cpu-sample-one", type=int, default=4,
+                    help="sub-trees of the sample the oracle also traverses alone, for the one-core rate")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, one device copy of this size: calibrates HBM counters under rocprofv3 --pmc")
     args = ap.parse_args()
@@ -478,6 +486,19 @@ def bench_batch(args):
     ms_plain = ev.ms(0) / args.steps
     n_plain = sum(int(P.read_meta(bf)[0].n_rays) for _, bf in plain)
     assert n_plain == n
+    # the two forms must find the same closest hits: triangle ids and the
+    # bits of t, u, v, frame by frame
+    import numpy as np
+    batch_res = db.frame_results(m2, with_pairs=False)
+    same = True
+    for f, ((fr, bf), r) in enumerate(zip(plain, batch_res)):
+        pm, _ = P.read_meta(bf)
+        g = P.results(fr, bf, pm)
+        for a, b in zip(g["hit"], r["hit"]):
+            if not np.array_equal(np.asarray(a).view(np.uint32), np.asarray(b).view(np.uint32)):
+                same = False
+                log(f"[bench] frame {f}: batched and plain closest hits differ")
+                break
     tris = sum(wl.scene.m for wl in wls)
     out = {
         "metric": "secondary rays/sec (hash+sort+build+traverse+hit), batched frames",
@@ -493,12 +514,12 @@ def bench_batch(args):
                    "rays": n, "triangles": tris, "B": p["B"], "F": 4, "levels": p["levels"],
                    "hit_block": p["hit_block"], "params": tuned, "seed": args.seed},
         "per_frame_plain": {"ms_per_batch": round(ms_plain, 4), "value": round(n / (ms_plain * 1e-3), 1),
-                            "speedup_of_batch": round(ms_plain / ms_batch, 3)},
+                            "speedup_of_batch": round(ms_plain / ms_batch, 3), "same_closest_hits": same},
         "tests": {"final_ray_tri_tests": int(m2.final_tests),
                   "node_tests": sum(int(m2.tests[k]) for k in range(int(m2.n_levels)))},
     }
     print(json.dumps(out), flush=True)
-    return 0
+    return 0 if same else 1
 
 
 if __name__ == "__main__":

@@ -177,8 +177,10 @@ typedef struct crsh_packed_pairs {
 } crsh_packed_pairs;
 
 /* Closest hits.  tkey is scratch in SORTED order (one 64-bit word per sorted
- * ray: float bits of t above the triangle id); tri/t/u/v are the results by
- * ray id: triangle (-1 on a miss), distance and barycentrics (0 on a miss). */
+ * ray: the bits of t mapped to an order-preserving unsigned form -- negative
+ * values complemented, others with the sign bit set -- above the triangle
+ * id; all ones = no hit); tri/t/u/v are the results by ray id: triangle (-1
+ * on a miss), distance and barycentrics (0 on a miss). */
 typedef struct crsh_hits {
     unsigned long long *tkey;
     int32_t *tri;
@@ -380,6 +382,19 @@ crsh_status crsh_hash_rays(const crsh_rays *rays, uint32_t n, uint32_t type, uin
  * [0, n_verts) is written as all zeros (degenerate: never hit). */
 crsh_status crsh_gather_triangles(const float *verts, uint32_t n_verts, const int32_t *faces, uint32_t m,
                                   float *const v[9], hipStream_t stream);
+
+/* Enclosing sphere of every mesh (Sec. 3.3.1) from the current triangle
+ * arrays v[0..8] (crsh_scene layout): msph[4*i .. 4*i+3] = (cx, cy, cz, r)
+ * with the centre at the midpoint of the bounding box of mesh i's vertices
+ * and r the largest vertex distance from it, widened by 2^-20 of itself so
+ * that float32 rounding never leaves a vertex outside.  Meshes are the
+ * triangle ranges [mesh_first[i], +mesh_count[i]) (clamped to m); an empty
+ * mesh gets (0, 0, 0, 0).  For geometry that moves between frames (e.g.
+ * vertices being optimised): the traversal's whole-mesh culling is only
+ * conservative with spheres that hold the current vertices.  All pointers
+ * are device pointers. */
+crsh_status crsh_mesh_spheres(const float *const v[9], uint32_t m, const uint32_t *mesh_first,
+                              const uint32_t *mesh_count, uint32_t n_mesh, float *msph, hipStream_t stream);
 
 /* Adjoint of the closest hit (Sec. 3.3.8) with respect to the triangle
  * vertices and the ray, holding each ray's hit triangle fixed.  For ray i

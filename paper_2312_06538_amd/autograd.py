@@ -20,18 +20,21 @@ def _p(t):
 
 
 class RayScene:
-    """An indexed mesh with its mesh ranges and enclosing spheres, and the
-    hierarchy parameters, for closest hits of caller-given rays."""
+    """An indexed mesh with its mesh ranges, and the hierarchy parameters,
+    for closest hits of caller-given rays.  The vertices come with every
+    call; each call gathers the triangles and recomputes every mesh's
+    enclosing sphere from them (crsh_mesh_spheres), so whole-mesh culling
+    stays conservative while the vertices move."""
 
-    def __init__(self, faces, mesh_first, mesh_count, mesh_spheres, lo, inv_ext, B=16, F=4, levels=5,
+    def __init__(self, faces, mesh_first, mesh_count, lo, inv_ext, B=16, F=4, levels=5,
                  t_min=1e-4, ray_type=1, pair_capacity=1 << 22):
         dev = torch.device("cuda")
         self.faces = torch.as_tensor(np.ascontiguousarray(faces, np.int32)).to(dev)
         self.m = int(self.faces.shape[0])
         self.mesh_first = torch.as_tensor(np.asarray(mesh_first, np.uint32).view(np.int32)).to(dev)
         self.mesh_count = torch.as_tensor(np.asarray(mesh_count, np.uint32).view(np.int32)).to(dev)
-        self.msph = torch.as_tensor(np.ascontiguousarray(mesh_spheres, np.float32).reshape(-1)).to(dev)
         self.n_mesh = int(self.mesh_first.shape[0])
+        self.msph = torch.empty(4 * max(self.n_mesh, 1), dtype=torch.float32, device=dev)
         self.lo = [float(x) for x in lo]
         self.inv_ext = [float(x) for x in inv_ext]
         self.B, self.F, self.levels, self.t_min, self.ray_type = B, F, levels, float(t_min), ray_type
@@ -73,6 +76,8 @@ class RayScene:
         s = stream_handle()
         X.crsh_gather_triangles(_p(verts), int(verts.shape[0]), _p(self.faces), self.m,
                                 [_p(a) for a in self.v9], s)
+        X.crsh_mesh_spheres([_p(a) for a in self.v9], self.m, _p(self.mesh_first), _p(self.mesh_count),
+                            self.n_mesh, _p(self.msph), s)
         for i, k in enumerate(("ox", "oy", "oz")):
             self.rays[k][:n].copy_(o[:, i])
         for i, k in enumerate(("dx", "dy", "dz")):

@@ -175,6 +175,8 @@ def lib():
                                      C.c_float * 3, vp, vp, vp, vp]
         L.crsh_gather_triangles.restype = st
         L.crsh_gather_triangles.argtypes = [vp, C.c_uint32, vp, C.c_uint32, vp * 9, vp]
+        L.crsh_mesh_spheres.restype = st
+        L.crsh_mesh_spheres.argtypes = [vp * 9, C.c_uint32, vp, vp, C.c_uint32, vp, vp]
         L.crsh_closest_hit_backward.restype = st
         L.crsh_closest_hit_backward.argtypes = [C.POINTER(Rays), C.c_uint32, C.POINTER(Hits), vp, vp, vp, vp,
                                                 C.c_uint32, vp, C.c_uint32, vp, vp, vp, vp]
@@ -301,6 +303,10 @@ def crsh_hash_rays(rays, n, typ, light, lo, inv_ext, keys, ids, meta, stream):
 
 def crsh_gather_triangles(verts, n_verts, faces, m, v9, stream):
     return _check(lib().crsh_gather_triangles(verts, n_verts, faces, m, (vp * 9)(*v9), stream))
+
+
+def crsh_mesh_spheres(v9, m, mesh_first, mesh_count, n_mesh, msph, stream):
+    return _check(lib().crsh_mesh_spheres((vp * 9)(*v9), m, mesh_first, mesh_count, n_mesh, msph, stream))
 
 
 def crsh_closest_hit_backward(rays, n, hits, g_t, g_u, g_v, verts, n_verts, faces, m, g_verts, g_o, g_d, stream):

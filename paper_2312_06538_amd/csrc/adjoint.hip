@@ -37,6 +37,83 @@ __global__ void k_gather_tris(const float *__restrict__ verts, uint32_t n_verts,
     }
 }
 
+struct tri9 {
+    const float *v[9];
+};
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, WAVE));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, WAVE));
+    return v;
+}
+
+// Enclosing sphere of every mesh from its triangles' vertices (Sec. 3.3.1
+// asks for a bounding sphere per mesh; any enclosing one keeps the culling
+// conservative).  One workgroup per mesh: the centre is the midpoint of the
+// vertices' bounding box, the radius the largest float32 vertex distance
+// from it widened by 2^-20 of itself.  Each float32 difference, square and
+// sum is off by at most a few units in the last place relative to the
+// exact value (all terms are non-negative), so the widened radius is at
+// least the exact largest distance.  An empty mesh gets (0, 0, 0, 0).
+__global__ __launch_bounds__(256) void k_mesh_spheres(tri9 T, uint32_t m, const uint32_t *__restrict__ mesh_first,
+                                                      const uint32_t *__restrict__ mesh_count, uint32_t n_mesh,
+                                                      float *__restrict__ msph)
+{
+    __shared__ float s_lo[3][256 / WAVE], s_hi[3][256 / WAVE], s_d[256 / WAVE];
+    const uint32_t w = threadIdx.x / WAVE;
+    for (uint32_t i = blockIdx.x; i < n_mesh; i += gridDim.x) {
+        const uint32_t b = min(mesh_first[i], m);
+        const uint32_t e = (uint32_t)min((uint64_t)b + mesh_count[i], (uint64_t)m);
+        f3 lo = mk(INFINITY, INFINITY, INFINITY), hi = mk(-INFINITY, -INFINITY, -INFINITY);
+        for (uint32_t t = b + threadIdx.x; t < e; t += blockDim.x) {
+            for (int k = 0; k < 3; ++k) {
+                const f3 p = mk(T.v[3 * k][t], T.v[3 * k + 1][t], T.v[3 * k + 2][t]);
+                lo = mk(fminf(lo.x, p.x), fminf(lo.y, p.y), fminf(lo.z, p.z));
+                hi = mk(fmaxf(hi.x, p.x), fmaxf(hi.y, p.y), fmaxf(hi.z, p.z));
+            }
+        }
+        lo = mk(wave_min(lo.x), wave_min(lo.y), wave_min(lo.z));
+        hi = mk(wave_max(hi.x), wave_max(hi.y), wave_max(hi.z));
+        if (lane_id() == 0) {
+            s_lo[0][w] = lo.x, s_lo[1][w] = lo.y, s_lo[2][w] = lo.z;
+            s_hi[0][w] = hi.x, s_hi[1][w] = hi.y, s_hi[2][w] = hi.z;
+        }
+        __syncthreads();
+        for (uint32_t k = 0; k < blockDim.x / WAVE; ++k) {
+            lo = mk(fminf(lo.x, s_lo[0][k]), fminf(lo.y, s_lo[1][k]), fminf(lo.z, s_lo[2][k]));
+            hi = mk(fmaxf(hi.x, s_hi[0][k]), fmaxf(hi.y, s_hi[1][k]), fmaxf(hi.z, s_hi[2][k]));
+        }
+        const f3 c = e > b ? lo * 0.5f + hi * 0.5f : mk(0.0f, 0.0f, 0.0f);
+        float d2 = 0.0f;
+        for (uint32_t t = b + threadIdx.x; t < e; t += blockDim.x) {
+            for (int k = 0; k < 3; ++k) {
+                const f3 q = mk(T.v[3 * k][t], T.v[3 * k + 1][t], T.v[3 * k + 2][t]) - c;
+                d2 = fmaxf(d2, dot(q, q));
+            }
+        }
+        d2 = wave_max(d2);
+        if (lane_id() == 0) s_d[w] = d2;
+        __syncthreads();
+        for (uint32_t k = 0; k < blockDim.x / WAVE; ++k) d2 = fmaxf(d2, s_d[k]);
+        if (threadIdx.x == 0) {
+            const float r = sqrtf(d2);
+            msph[4 * i] = c.x;
+            msph[4 * i + 1] = c.y;
+            msph[4 * i + 2] = c.z;
+            msph[4 * i + 3] = r + r * 0x1p-20f;
+        }
+        __syncthreads();    // the LDS slots are reused by the next mesh
+    }
+}
+
 struct adj_in {
     const float *ox, *oy, *oz, *dx, *dy, *dz;
     const int32_t *tri;
@@ -126,6 +203,27 @@ extern "C" crsh_status crsh_gather_triangles(const float *verts, uint32_t n_vert
                                              v[7], v[8]);
     }
     return hip_check(hipGetLastError(), "crsh_gather_triangles launch");
+}
+
+extern "C" crsh_status crsh_mesh_spheres(const float *const v[9], uint32_t m, const uint32_t *mesh_first,
+                                         const uint32_t *mesh_count, uint32_t n_mesh, float *msph,
+                                         hipStream_t stream)
+{
+    if (!v || (n_mesh && (!mesh_first || !mesh_count || !msph))) {
+        set_error("crsh_mesh_spheres: NULL argument");
+        return CRSH_ERR_INVALID;
+    }
+    tri9 T{};
+    for (int k = 0; k < 9; ++k) {
+        if (!v[k] && m) {
+            set_error("crsh_mesh_spheres: missing vertex array");
+            return CRSH_ERR_INVALID;
+        }
+        T.v[k] = v[k];
+    }
+    if (n_mesh) k_mesh_spheres<<<std::min<uint32_t>(n_mesh, 4096), 256, 0, stream>>>(T, m, mesh_first, mesh_count,
+                                                                                       n_mesh, msph);
+    return hip_check(hipGetLastError(), "crsh_mesh_spheres launch");
 }
 
 extern "C" crsh_status crsh_closest_hit_backward(const crsh_rays *rays, uint32_t n, const crsh_hits *hits,

@@ -63,6 +63,27 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m)
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Raw buffer resource over `bytes` bytes at p (bytes clamped to 2^32 - 1):
+// loads through it take a 32-bit byte offset, and a load past the end
+// returns zeros instead of touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint64_t bytes)
+{
+    const int n = (int)(bytes < 0xFFFFFFFFull ? bytes : 0xFFFFFFFFull);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, n, 0x00020000);
+}
+
+__device__ __forceinline__ float4 buf_load4(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ float buf_load1(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 // inclusive prefix sum over the 64 lanes of a wave
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v)
@@ -218,6 +239,10 @@ size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t
 // the plain form; in the batched form B per level-1 node, at most the rays
 // plus B - 1 per frame.
 size_t hit_ws_bytes(uint32_t m, uint32_t slots);
+// bounds of the final tests' 32-bit byte offsets (32 B per ray slot, 48 B
+// per triangle)
+#define CRSH_HIT_MAX_SLOTS (1u << 27)
+#define CRSH_HIT_MAX_TRIS (1u << 26)
 constexpr uint32_t hit_slots(uint32_t rays, bool batch)
 {
     return batch ? rays + CRSH_MAX_FRAMES * (CRSH_MAX_BUNDLE - 1) : rays;

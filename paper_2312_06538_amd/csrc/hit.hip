@@ -8,9 +8,8 @@
 //              (G = bundle rounded up to a power of two) takes one pair, one
 //              lane per ray of its leaf, so a leaf's rays are read
 //              contiguously from the sorted ray arrays.  A hit lowers the
-//              ray's 64-bit (t bits, triangle) key with an atomic minimum:
-//              positive floats order like their bit patterns, so the minimum
-//              is the closest hit with ties to the lower triangle id.
+//              ray's 64-bit (order-mapped t, triangle) key with an atomic
+//              minimum: the closest hit, ties to the lower triangle id.
 // k_hit_final  one thread per sorted ray: decode the key, recompute u, v with
 //              the same test, write the result at the ray id.
 // Ray slots: k_hit reads the rays of leaf l at slots l * B + j, j < B, of a
@@ -45,15 +44,6 @@ __global__ void k_hit_prep(const float *__restrict__ v0x, const float *__restric
 struct sorted_rays {
     const float *ox, *oy, *oz, *dx, *dy, *dz, *tmax;
 };
-
-#ifndef CRSH_HIT_UNROLL
-#define CRSH_HIT_UNROLL 1
-#endif
-constexpr int HIT_UNROLL = CRSH_HIT_UNROLL;    // pairs per lane group in flight at once
-#ifndef CRSH_HIT_CHUNK
-#define CRSH_HIT_CHUNK 64
-#endif
-constexpr uint32_t HIT_CHUNK = CRSH_HIT_CHUNK;  // consecutive pairs a wave tests before the grid stride
 
 // t_min word of a padded slot (a NaN); a NaN t_min of a real ray is stored as
 // the default quiet NaN, which accepts no hit either
@@ -107,6 +97,21 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
 // Slots in use: the plain form's sorted rays, or B per level-1 node.  PACKED:
 // the level-1 pairs are packed words in ptri (node above the low
 // CRSH_PACKED_TRI_BITS, triangle minus tri_base below; pnode unused).
+//
+// A wave takes runs of 64 consecutive pairs before the grid stride
+// (neighbouring level-1 pairs share their triangle -- siblings of one
+// parent pair -- or their leaves, so a run finds its rays in the vector L1
+// cache).  Each lane reads one pair of the run, its triangle, and writes a
+// 64-byte record to the wave's LDS slice: the triangle (v0, e1, e2), the
+// triangle id, the byte offset of the leaf's first ray slot and the number
+// of rays of the leaf.  The run is then tested 64 / G pairs at a time, each
+// lane group reading its pair's record from LDS (the 16 lanes of a group
+// read the same address), so the vector memory path carries only the rays.
+// Rays are read with buffer loads on 32-bit byte offsets (the host bounds
+// them; a read past the end returns zeros).  The test is split where most
+// of its cost lies: every lane computes the division-free first half, and
+// the wave runs the rest (the division included) only when one of its
+// lanes can still pass.
 template <bool BATCH, bool PACKED>
 __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const float4 *__restrict__ tri,
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
@@ -114,74 +119,84 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
                                              crsh_meta *meta, uint32_t slot_cap, uint32_t m, uint32_t tri_base)
 {
     __shared__ uint64_t s_red[256 / WAVE];
+    __shared__ float4 s_rec[256 / WAVE][3][WAVE];    // [wave][record word][pair of the run]
     const uint32_t ns = BATCH ? batch_slots(meta, B, slot_cap) : min(meta->n_rays, slot_cap);
     uint64_t np = meta->n_levels ? meta->pairs[0] : 0;
     np = np < cap1 ? np : cap1;
     const uint32_t l = lane_id();
     const uint32_t G = 1u << log2G;
-    const uint32_t slot = l >> log2G;        // pair slot of this lane in the wave
+    const uint32_t slot = l >> log2G;        // pair of this lane within a step
     const uint32_t j = l & (G - 1);          // ray of the leaf
     const uint32_t per_wave = WAVE >> log2G;
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const uint32_t wib = threadIdx.x / WAVE;
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
+    const __amdgpu_buffer_rsrc_t rays_r = make_rsrc(R, (uint64_t)ns * 32u);
+    const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
+    const uint32_t jo = j * 32u;
+    float4(*rec)[WAVE] = s_rec[wib];
     uint64_t tests = 0;
-    // A wave tests HIT_CHUNK consecutive pairs before it moves on by the grid
-    // stride.  Neighbouring level-1 pairs share their triangle (siblings of
-    // one parent pair) or their leaves (the same parent node against the
-    // next triangle), so a wave that walks a run of them finds its rays and
-    // triangles in the vector L1 cache; with a stride of one wave step
-    // instead, the reuse depends on the waves of a workgroup staying in step,
-    // which they stop doing over a long launch.  Each lane group takes
-    // HIT_UNROLL pairs per iteration and issues all their loads before any
-    // test.
-    const bool lane_ok = j < B;
-    for (uint64_t c0 = wave * HIT_CHUNK; c0 < np; c0 += nwaves * HIT_CHUNK) {
-        const uint64_t c1 = min(np, c0 + HIT_CHUNK);
-        for (uint64_t q0 = c0; q0 < c1; q0 += HIT_UNROLL * per_wave) {
-            uint32_t t[HIT_UNROLL], s[HIT_UNROLL];
-            bool ok[HIT_UNROLL];
-#pragma unroll
-            for (int k = 0; k < HIT_UNROLL; ++k) {
-                const uint64_t q = q0 + slot + k * per_wave;
-                ok[k] = lane_ok && q < c1;
-                uint32_t leaf;
-                if constexpr (PACKED) {
-                    const uint32_t w = ok[k] ? ptri[q] : 0u;
-                    t[k] = tri_base + (w & ((1u << CRSH_PACKED_TRI_BITS) - 1u));
-                    leaf = w >> CRSH_PACKED_TRI_BITS;
-                } else {
-                    t[k] = ok[k] ? ptri[q] : 0u;
-                    leaf = ok[k] ? pnode[q] : 0u;
-                }
-                s[k] = leaf * B + j;
-                ok[k] = ok[k] && s[k] < ns && t[k] < m;
+    for (uint64_t c0 = wave * WAVE; c0 < np; c0 += nwaves * WAVE) {
+        const uint32_t cn = __builtin_amdgcn_readfirstlane((uint32_t)min(np - c0, (uint64_t)WAVE));
+        uint32_t my_t = 0u, my_rb = 0u, my_cnt = 0u;
+        if (l < cn) {
+            uint32_t leaf;
+            if constexpr (PACKED) {
+                const uint32_t w = ptri[c0 + l];
+                my_t = tri_base + (w & ((1u << CRSH_PACKED_TRI_BITS) - 1u));
+                leaf = w >> CRSH_PACKED_TRI_BITS;
+            } else {
+                my_t = ptri[c0 + l];
+                leaf = pnode[c0 + l];
             }
-            tri_t tr[HIT_UNROLL];
-            float4 ro[HIT_UNROLL], rd[HIT_UNROLL];
-#pragma unroll
-            for (int k = 0; k < HIT_UNROLL; ++k) {
-                tr[k] = load_tri(tri, ok[k] ? t[k] : 0u);
-                ro[k] = R[2 * (ok[k] ? s[k] : 0u)];
-                rd[k] = R[2 * (ok[k] ? s[k] : 0u) + 1];
+            // rays of the leaf present in the slot array (none for a pair out
+            // of range)
+            const uint64_t first = (uint64_t)leaf * B;
+            if (my_t < m && first < ns) {
+                my_cnt = (uint32_t)min((uint64_t)B, ns - first);
+                my_rb = (uint32_t)first * 32u;
             }
-#pragma unroll
-            for (int k = 0; k < HIT_UNROLL; ++k) {
-                if (!ok[k]) continue;
-                // a padded slot's NaN t_min accepts nothing; it only must not
-                // count as a test (branching on it would hold the triangle
-                // loads behind the ray load)
-                tests += (BATCH && __float_as_uint(rd[k].w) == PAD_SLOT) ? 0u : 1u;
+        }
+        const uint32_t tb = my_cnt ? my_t * 48u : 0u;
+        const float4 ta = buf_load4(tris_r, tb);
+        const float4 tbv = buf_load4(tris_r, tb + 16u);
+        const float tc = buf_load1(tris_r, tb + 32u);
+        __builtin_amdgcn_wave_barrier();          // the previous run's reads come first
+        rec[0][l] = ta;
+        rec[1][l] = tbv;
+        rec[2][l] = make_float4(tc, __uint_as_float(my_t), __uint_as_float(my_rb), __uint_as_float(my_cnt));
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t k = 0; k < cn; k += per_wave) {
+            const uint32_t src = k + slot;
+            const float4 a = rec[0][src];
+            const float4 b = rec[1][src];
+            const float4 c = rec[2][src];
+            const uint32_t cnt = __float_as_uint(c.w);
+            const uint32_t ro = __float_as_uint(c.z) + jo;
+            bool ok = j < cnt;
+            const float4 ro4 = buf_load4(rays_r, ro);
+            const float4 rd4 = buf_load4(rays_r, ro + 16u);
+            tri_t tr;
+            tr.v0 = mk(a.x, a.y, a.z);
+            tr.e1 = mk(a.w, b.x, b.y);
+            tr.e2 = mk(b.z, b.w, c.x);
+            // a padded slot's NaN t_min accepts nothing; it only must not
+            // count as a test
+            if (BATCH) ok = ok && __float_as_uint(rd4.w) != PAD_SLOT;
+            tests += (uint64_t)__popcll(ballot(ok));
+            const f3 D = mk(rd4.x, rd4.y, rd4.z);
+            mt_head h;
+            const bool maybe = mt_first_half(mk(ro4.x, ro4.y, ro4.z), D, tr, h) && ok;
+            // a wave-uniform branch: the wave runs the second half only if
+            // one of its lanes needs it
+            if (ballot(maybe) != 0) {
                 float th;
-                if (moller_trumbore_t(mk(ro[k].x, ro[k].y, ro[k].z), mk(rd[k].x, rd[k].y, rd[k].z), rd[k].w, ro[k].w,
-                                      tr[k], th)) {
-                    unsigned long long key = ((unsigned long long)__float_as_uint(th) << 32) | t[k];
-                    atomicMin(&keys[s[k]], key);
-                }
+                if (mt_second_half(D, rd4.w, ro4.w, tr, h, th) && maybe)
+                    atomicMin(&keys[ro >> 5], hit_key(th, __float_as_uint(c.y)));
             }
         }
     }
-    tests = wave_sum(tests);
-    if (l == 0) s_red[threadIdx.x / WAVE] = tests;
+    if (l == 0) s_red[wib] = tests;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t tot = 0;
@@ -229,7 +244,7 @@ __global__ void k_hit_final(sorted_rays R, const float4 *__restrict__ tri, const
                 best = (int32_t)t;
             } else {                     // cannot happen: same inputs, same operations
                 best = (int32_t)t;
-                th = __uint_as_float((uint32_t)(key >> 32));
+                th = hit_key_t(key);
             }
         }
         out.tri[id] = best;
@@ -347,6 +362,14 @@ crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32
         }
     if (hits->capacity < sorted->capacity) {
         set_error("%s: hit capacity below the ray capacity", who);
+        return CRSH_ERR_INVALID;
+    }
+    // the final tests address ray slots (32 B) and triangles (48 B) by
+    // 32-bit byte offsets
+    if ((uint64_t)sorted->capacity + (uint64_t)CRSH_MAX_FRAMES * (CRSH_MAX_BUNDLE - 1) > CRSH_HIT_MAX_SLOTS ||
+        scene->m > CRSH_HIT_MAX_TRIS) {
+        set_error("%s: at most %u ray slots and %u triangles", who, (unsigned)CRSH_HIT_MAX_SLOTS,
+                  (unsigned)CRSH_HIT_MAX_TRIS);
         return CRSH_ERR_INVALID;
     }
     return CRSH_OK;

@@ -6,6 +6,24 @@
 
 namespace crsh {
 
+// Closest-hit key: the bits of t mapped to an unsigned order that follows
+// the float order for either sign (negative values complemented, others with
+// the sign bit set; -0 taken as +0, so equal distances tie) above the
+// triangle id.  The 64-bit minimum is the smallest t, ties to the lower
+// triangle; all ones (the bits of a NaN) means no hit.
+__device__ __forceinline__ unsigned long long hit_key(float t, uint32_t tri)
+{
+    uint32_t b = __float_as_uint(t == 0.0f ? 0.0f : t);
+    b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ((unsigned long long)b << 32) | tri;
+}
+
+__device__ __forceinline__ float hit_key_t(unsigned long long key)
+{
+    const uint32_t b = (uint32_t)(key >> 32);
+    return __uint_as_float((b & 0x80000000u) ? (b & 0x7FFFFFFFu) : ~b);
+}
+
 struct tri_t {
     f3 v0, e1, e2;
 };
@@ -58,6 +76,46 @@ __device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float t
     return true;
 }
 
+
+// The first half of the test, for the final-test kernel: p = D x e2,
+// det = e1 . p, T = O - v0 and a = T . p (u = a / det before rounding), and
+// whether the ray can still pass -- false exactly when moller_trumbore's
+// determinant check or its division-free decision on u rejects it.
+struct mt_head {
+    f3 p, T;
+    float det, a;
+};
+
+__device__ __forceinline__ bool mt_first_half(f3 O, f3 D, const tri_t &tr, mt_head &h)
+{
+    h.p = cross(D, tr.e2);
+    h.det = dot(tr.e1, h.p);
+    h.T = O - tr.v0;
+    h.a = dot(h.T, h.p);
+    // moller_trumbore's early checks, combined without branches.  With
+    // s = a carrying det's sign (|s| = |a|; s < 0 iff a and det have
+    // opposite signs, a = -0 counting as 0), its two rejections are
+    // s <= -2^-60 and s > |det| (1 + 2^-19) while |det| <= 2^60; a NaN s
+    // fails both comparisons and is rejected here, as the division would
+    // reject it (u NaN).
+    const float adet = fabsf(h.det);
+    const float sg = __uint_as_float(__float_as_uint(h.a) ^ (__float_as_uint(h.det) & 0x80000000u));
+    return adet >= DET_EPS && (adet > 0x1p60f || (sg > -0x1p-60f && sg <= adet * (1.0f + 0x1p-19f)));
+}
+
+// The rest of the test for a ray that mt_first_half let through: the same
+// operations, in the same order, as moller_trumbore after its early checks.
+__device__ __forceinline__ bool mt_second_half(f3 D, float t_min, float tmax, const tri_t &tr, const mt_head &h,
+                                               float &tt)
+{
+    const float inv = 1.0f / h.det;
+    const float u = h.a * inv;
+    const f3 q = cross(h.T, tr.e1);
+    const float v = dot(D, q) * inv;
+    const float t = dot(tr.e2, q) * inv;
+    tt = t;
+    return (u >= 0.0f && u <= 1.0f) && (v >= 0.0f && u + v <= 1.0f) && (t > t_min && t < tmax);
+}
 
 // The same test for the final-test kernel, without early exits: every
 // quantity of the test is computed and the acceptance conditions are combined

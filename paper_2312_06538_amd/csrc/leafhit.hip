@@ -360,7 +360,7 @@ __global__ __launch_bounds__(LH_THREADS) void k_leaf_hit(lh_args a, lh_ws L, crs
                         const float4 o = s_o[ri], d = s_d[ri];
                         float th, uh, vh;
                         if (moller_trumbore(mk(o.x, o.y, o.z), mk(d.x, d.y, d.z), t_min, o.w, tr, th, uh, vh))
-                            atomicMin(&s_best[ri], ((unsigned long long)__float_as_uint(th) << 32) | tt);
+                            atomicMin(&s_best[ri], hit_key(th, tt));
                     }
                 }
             }

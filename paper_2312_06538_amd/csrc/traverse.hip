@@ -31,6 +31,9 @@
 #ifndef CRSH_COUNT_LANES
 #define CRSH_COUNT_LANES 1   // plain count pass forming level 1: one (parent, child) test per lane
 #endif
+#ifndef CRSH_COUNT_STAGED
+#define CRSH_COUNT_STAGED 0  // plain count passes: child nodes of a top node's sub-tree staged in LDS (measured slower)
+#endif
 #ifndef CRSH_COUNT_LANES_MIN_BUNDLE
 #define CRSH_COUNT_LANES_MIN_BUNDLE 16   // ... for bundles of at least this many rays
 #endif
@@ -505,6 +508,218 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
     }
 }
 
+// Count pass of the plain form with the child nodes staged in LDS.  Every
+// pair below the top descends from one top node, and the pairs of a level
+// come grouped by top node (the top level is written node by node and each
+// level below in the order of its parents), so a tile of consecutive parent
+// pairs almost always lies within one top node's sub-tree.  The children of
+// that sub-tree at the child level -- F^(levels above the child level) nodes,
+// consecutive in the level -- are copied to LDS once, and the tests (Eq. 9)
+// read them from there: the node data no longer goes through the vector
+// memory path, which bound the count (36 bytes gathered per test).
+//
+// Each block takes one contiguous run of tiles (a grid stride would send it
+// to another sub-tree at every tile).  A tile's parent pairs are read one
+// per thread into an LDS record (triangle sphere, parent node; two buffers
+// in turn), then tested one (parent, child) per lane: the NF lanes of a
+// parent read its record (one address) and NF consecutive staged children,
+// so a wave's LDS reads fall on few rows and its ballot is directly the pass
+// bits of its 64 / NF parents in the mask layout.  The tile is tested once
+// per top node from that of its first pair to that of its last, staging
+// each in turn (usually one); a pair whose top node lies outside that range
+// (the grouping above rules it out) is tested from global memory, so the
+// result never depends on the grouping.  Sub-trees whose children do not
+// fit the LDS buffer are tested from global memory throughout.  Pass masks,
+// tile counts and counters are those of k_level_count.
+constexpr uint32_t STAGE_NODES = 1024;    // child nodes one LDS buffer holds
+
+template <int NF, bool PACKED>
+__global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_staged(int32_t parent_level, uint32_t F,
+                                                                      const float4 *__restrict__ na,
+                                                                      const float4 *__restrict__ nb,
+                                                                      const float *__restrict__ ns,
+                                                                      const float4 *__restrict__ tsph, uint32_t m,
+                                                                      pair_levels P, trav_scratch S, crsh_meta *meta)
+{
+    static_assert(LEVEL_PPT == 1 && WAVE % NF == 0, "whole parents per wave");
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per slice; NF slices per tile
+    __shared__ float4 sA[STAGE_NODES], sB[STAGE_NODES];
+    __shared__ float sS[STAGE_NODES];
+    __shared__ float4 s_sph[2][LEVEL_TILE];        // the tile's records, two buffers in turn
+    __shared__ uint32_t s_par[2][LEVEL_TILE];
+    __shared__ uint32_t s_lo[2], s_hi[2];          // top nodes of the tile's first and last pair
+    __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
+    __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
+    __shared__ uint32_t s_next;
+    const uint32_t nl = meta->n_levels;
+    if ((uint32_t)parent_level > nl || parent_level < 2) return;
+    const uint64_t ntiles = level_items(meta, parent_level, 0, P);
+    clear_scan(S, ntiles);                  // the scan that follows reads these
+    const pairs_dev in = P.p[parent_level - 1];
+    if (in.tri == nullptr || P.p[parent_level - 2].tri == nullptr) return;
+    uint64_t nin = meta->pairs[parent_level - 1];
+    nin = nin < in.cap ? nin : in.cap;
+    const uint32_t nk = meta->level_cnt[parent_level - 2];
+    const uint32_t offk = meta->level_off[parent_level - 2];
+    // parent-level nodes per top node (Wp, capped at 2^32 - 1: then every
+    // parent has top node 0) and child-level nodes (Wc); with Wp a power of
+    // two the top node of a parent is a shift of it
+    uint64_t Wp64 = 1;
+    for (uint32_t k = (uint32_t)parent_level; k < nl && Wp64 < 0xFFFFFFFFull; ++k) Wp64 *= F;
+    const uint32_t Wp = (uint32_t)min(Wp64, (uint64_t)0xFFFFFFFFu);
+    const uint64_t Wc = Wp64 * F;
+    const bool lds = Wc <= STAGE_NODES;
+    const bool pow2 = (Wp & (Wp - 1u)) == 0u;
+    const uint32_t wsh = pow2 ? (uint32_t)__builtin_ctz(Wp) : 0u;
+    auto top_of = [&](uint32_t par) { return pow2 ? par >> wsh : par / Wp; };
+    const uint32_t j = threadIdx.x % NF;    // child of this lane
+    const uint32_t w = threadIdx.x / WAVE;
+    uint64_t tests = 0;
+    uint32_t staged = NONE;                  // top node whose children are in LDS
+    // this block's run of tiles [t0, t1)
+    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t0 = min((uint64_t)blockIdx.x * per, ntiles);
+    const uint64_t t1 = min(t0 + per, ntiles);
+    // two-stage prefetch: the next tile's triangle spheres and the pairs of
+    // the tile after it are in flight while a tile is tested (the sphere
+    // load depends on the pair load, so one stage would leave two dependent
+    // round trips to memory exposed per tile)
+    auto load_pair = [&](uint64_t tile, uint32_t &tri, uint32_t &par) {
+        const uint64_t q = tile * LEVEL_TILE + threadIdx.x;
+        tri = 0u;
+        par = NONE;
+        if (q < nin) pair_get<PACKED>(in, q, tri, par);
+    };
+    uint32_t par_n = NONE, tri_nn = 0u, par_nn = NONE;
+    float4 sp_n = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (t0 < t1) {
+        uint32_t tri0;
+        load_pair(t0, tri0, par_n);
+        sp_n = tsph[tri0 < m ? tri0 : 0u];
+        if (t0 + 1 < t1) load_pair(t0 + 1, tri_nn, par_nn);
+    }
+    uint32_t it = 0;
+    for (uint64_t tile = t0; tile < t1; ++tile, ++it) {
+        const uint32_t b = it & 1u;
+        {
+            const uint32_t par = par_n;
+            const float4 sp = sp_n;
+            par_n = par_nn;
+            sp_n = tsph[tri_nn < m ? tri_nn : 0u];
+            if (tile + 2 < t1) load_pair(tile + 2, tri_nn, par_nn);
+            const uint64_t q = tile * LEVEL_TILE + threadIdx.x;
+            s_par[b][threadIdx.x] = par;
+            s_sph[b][threadIdx.x] = sp;
+            const uint64_t qlast = min(nin, (tile + 1) * LEVEL_TILE) - 1;
+            const uint32_t top = par != NONE ? top_of(par) : NONE;
+            if (q == tile * LEVEL_TILE) s_lo[b] = top;
+            if (q == qlast) s_hi[b] = top;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && it) {        // the previous tile's survivors
+            uint32_t t = 0;
+            for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) t += s_red32[b ^ 1u][ww];
+            S.cnt[tile - 1] = t;
+        }
+        const uint32_t lo = s_lo[b], hi = s_hi[b];
+        // this lane's (parent, child) of every slice
+        uint32_t ch[NF];
+        uint32_t topr[NF];
+        uint32_t okm = 0;                    // bit r: the lane has a child to test in slice r
+#pragma unroll
+        for (int r = 0; r < NF; ++r) {
+            const uint32_t par = s_par[b][r * PR + threadIdx.x / NF];
+            ch[r] = par * F + j;
+            topr[r] = par != NONE ? top_of(par) : NONE;
+            if (par != NONE && j < F && ch[r] < nk) okm |= 1u << r;
+        }
+        uint64_t bal[NF];
+#pragma unroll
+        for (int r = 0; r < NF; ++r) bal[r] = 0;
+        auto test = [&](int r, float4 A, float4 Bv, float Sg) {
+            const float4 sp = s_sph[b][r * PR + threadIdx.x / NF];
+            ++tests;
+            return packed_meets(A, Bv, Sg, mk(sp.x, sp.y, sp.z), sp.w);
+        };
+        if (lds) {
+            uint32_t cur = lo;
+            while (cur <= hi) {              // uniform (lo and hi are block-wide)
+                if (cur != staged) {
+                    // every lane is past its reads of the old contents (the
+                    // barrier above, or the one ending the previous top node)
+                    const uint64_t c0 = (uint64_t)cur * Wc;
+                    for (uint32_t i = threadIdx.x; i < (uint32_t)Wc; i += LEVEL_THREADS) {
+                        const uint64_t c = c0 + i;
+                        const uint32_t g = offk + (uint32_t)(c < nk ? c : 0u);
+                        sA[i] = na[g];
+                        sB[i] = nb[g];
+                        sS[i] = ns[g];
+                    }
+                    __syncthreads();
+                    staged = cur;
+                }
+                const uint32_t base = cur * (uint32_t)Wc;     // first staged child
+#pragma unroll
+                for (int r = 0; r < NF; ++r) {
+                    bool pass = false;
+                    if (((okm >> r) & 1u) && topr[r] == cur) {
+                        const uint32_t i = ch[r] - base;
+                        pass = test(r, sA[i], sB[i], sS[i]);
+                    }
+                    bal[r] |= ballot(pass);
+                }
+                if (cur == hi) break;
+                // the next top node of the tile: the smallest above cur (one
+                // exists: hi is the top node of a pair and cur < hi)
+                if (threadIdx.x == 0) s_next = NONE;
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < NF; ++r)
+                    if (((okm >> r) & 1u) && topr[r] > cur && topr[r] <= hi) atomicMin(&s_next, topr[r]);
+                __syncthreads();
+                cur = s_next;
+                __syncthreads();             // every lane has read s_next
+            }
+        }
+        // children not tested above: every one without the LDS buffer; with
+        // it, those of parents outside [lo, hi]
+#pragma unroll
+        for (int r = 0; r < NF; ++r) {
+            bool pass = false;
+            if (((okm >> r) & 1u) && (!lds || topr[r] < lo || topr[r] > hi)) {
+                const uint32_t g = offk + ch[r];
+                pass = test(r, na[g], nb[g], ns[g]);
+            }
+            bal[r] |= ballot(pass);
+        }
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < NF; ++r) {
+            if (lane_id() == 0) {
+                const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + w * (WAVE / NF)) * NF;   // a multiple of 64
+                *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal[r], (uint32_t)(bal[r] >> 32));
+            }
+            c += (uint32_t)__popcll(bal[r]);
+        }
+        if (lane_id() == 0) s_red32[b][w] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && it) {            // the block's last tile
+        uint32_t t = 0;
+        for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) t += s_red32[(it - 1u) & 1u][ww];
+        S.cnt[t1 - 1] = t;
+    }
+    tests = wave_sum(tests);
+    if (lane_id() == 0) s_red[w] = tests;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t tt = 0;
+        for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) tt += s_red[ww];
+        if (tt) atomicAdd((unsigned long long *)&meta->tests[parent_level - 2], (unsigned long long)tt);
+    }
+}
+
 // Survivors of a tile are first placed in LDS at their tile-local offsets
 // and then copied out with consecutive lanes writing consecutive pairs, so
 // the stores are coalesced whatever the pass masks.
@@ -729,7 +944,8 @@ static uint32_t resident_blocks(K kernel, uint32_t threads)
 
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
-                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed, bool lanes)
+                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed, bool lanes,
+                        bool staged)
 {
     const batch_dev b = bd ? *bd : batch_dev{};
     const uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), 4096);
@@ -760,7 +976,26 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     case 8: CRSH_COUNT_LANES_ONE(8, PK) break;                                                               \
     default: CRSH_COUNT_LANES_ONE(16, PK) break;                                                             \
     }
-    if (CRSH_COUNT_LANES && lanes && !bd && LEVEL_PPT == 1 && L == 2) {
+#define CRSH_COUNT_STAGED_ONE(NF, PK)                                                                        \
+    {                                                                                                        \
+        const uint32_t rb = resident_blocks(k_level_count_staged<NF, PK>, LEVEL_THREADS);                    \
+        const uint32_t gl = rb ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), rb) : g;    \
+        k_level_count_staged<NF, PK><<<gl, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); \
+    }
+#define CRSH_COUNT_STAGED_NF(PK)                                                                             \
+    switch (nf) {                                                                                            \
+    case 2: CRSH_COUNT_STAGED_ONE(2, PK) break;                                                              \
+    case 4: CRSH_COUNT_STAGED_ONE(4, PK) break;                                                              \
+    case 8: CRSH_COUNT_STAGED_ONE(8, PK) break;                                                              \
+    default: CRSH_COUNT_STAGED_ONE(16, PK) break;                                                            \
+    }
+    if (CRSH_COUNT_STAGED && staged && !bd && LEVEL_PPT == 1) {
+        if (packed) {
+            CRSH_COUNT_STAGED_NF(true)
+        } else {
+            CRSH_COUNT_STAGED_NF(false)
+        }
+    } else if (CRSH_COUNT_LANES && lanes && !bd && LEVEL_PPT == 1 && L == 2) {
         if (packed) {
             CRSH_COUNT_LANES_NF(true)
         } else {
@@ -773,6 +1008,8 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     } else {
         CRSH_COUNT_NF(false, false)
     }
+#undef CRSH_COUNT_STAGED_NF
+#undef CRSH_COUNT_STAGED_ONE
 #undef CRSH_COUNT_LANES_NF
 #undef CRSH_COUNT_LANES_ONE
 #undef CRSH_COUNT_NF
@@ -925,8 +1162,12 @@ static crsh_status traverse_run(const crsh_nodes *nodes, const crsh_scene *scene
     case 8: CRSH_EMIT(8, BT, PK); break;                                                                   \
     default: CRSH_EMIT(16, BT, PK); break;                                                                 \
     }
+        // children per top node at the child level, bounded with the levels
+        // that have pair storage (the tree has no more)
+        uint64_t wc = 1;
+        for (int k = L - 1; k < levels && wc <= STAGE_NODES; ++k) wc *= (uint64_t)merge;
         level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream, packed,
-                           bundle >= CRSH_COUNT_LANES_MIN_BUNDLE);
+                           bundle >= CRSH_COUNT_LANES_MIN_BUNDLE, wc <= STAGE_NODES);
         k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
             prof_scope ps("k_level_emit", stream);

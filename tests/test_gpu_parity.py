@@ -252,6 +252,26 @@ def test_closest_hit_matches_oracle(name):
     assert int(m.final_tests) == o["trav"]["final_tests"]
 
 
+@pytest.mark.parametrize("t_min", [-1.0, -1e-3, 0.0])
+def test_closest_hit_with_an_interval_start_at_or_below_zero(t_min):
+    """Intervals that admit t <= 0: every bounce ray meets its own surface
+    at t of about -1e-3 (origins sit 1e-3 off the surface), so with t_min
+    = -1 the closest hit has a negative t, and several negative hits
+    compete; the keys must order negative distances as floats do (and
+    -0 like +0).  Same level-1 pairs as the oracle's."""
+    base, kw = small("refl_96")
+    print(f"[hit] t_min {t_min}", flush=True)
+    wl = workload(base, **kw)
+    o = oracle_run(base, **kw)
+    ref = O.closest_hit(o["hash"]["rays"], o["sorted_ids"], wl.B, o["trav"]["pairs"][1], wl.scene, t_min)
+    g, m = _gu().gpu_closest_hit(o["hash"]["rays"], o["sorted_ids"], wl.B, o["trav"]["pairs"][1], wl.scene, t_min)
+    assert np.array_equal(g[0], ref[0])
+    for a, b in zip(g[1:], ref[1:]):
+        assert np.allclose(a, b, rtol=1e-5, atol=0)
+    if t_min < -1e-2:
+        assert int(((ref[0] >= 0) & (ref[1] < 0)).sum()) > 1000
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_pipeline_end_to_end(name):
     base, kw = small(name)

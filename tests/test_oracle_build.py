@@ -244,3 +244,52 @@ def test_random_folds_contain_rays(rng):
             continue
         phi = np.arctan2(np.float64(s), np.float64(c))
         assert np.all(_ang(d32.astype(np.float64), x.astype(np.float64)) <= phi + 1e-12)
+
+
+def _tri_scene(tris):
+    from workloads.scenes import Scene
+    tris = np.ascontiguousarray(tris, np.float32)
+    m = len(tris)
+    return Scene(tris=tris, mesh_first=np.zeros(1, np.uint32), mesh_count=np.array([m], np.uint32),
+                 mesh_sphere=np.zeros((1, 4), np.float32), mesh_mat=np.zeros(1, np.int32),
+                 mat_flags=np.zeros(1, np.uint32), mat_ior=np.ones(1, np.float32))
+
+
+def test_triangle_spheres_closed_forms():
+    """Triangle bounding spheres (the spheres of Eq. 9's coarse tests):
+    centroid and largest centroid-vertex distance.  A right triangle with
+    legs 3 on the axes has centroid (1, 1, 0) and farthest vertices at
+    sqrt(5); an equilateral triangle of circumradius 2 centred at c has its
+    centroid at c and every vertex at 2; a degenerate triangle (one point)
+    has radius (nearly) zero.  The padding widens by at most 2^-20 of
+    (radius + largest centre coordinate)."""
+    s3 = np.sqrt(3.0)
+    c = np.array([5.0, -7.0, 11.0])
+    tris = np.array([
+        [[0, 0, 0], [3, 0, 0], [0, 3, 0]],
+        [c + [2, 0, 0], c + [-1, s3, 0], c + [-1, -s3, 0]],
+        [[1.5, 2.5, -4], [1.5, 2.5, -4], [1.5, 2.5, -4]],
+    ], np.float64)
+    cx, cy, cz, r = (x.astype(np.float64) for x in O.tri_spheres(_tri_scene(tris)))
+    want_c = [[1, 1, 0], c, [1.5, 2.5, -4]]
+    want_r = [np.sqrt(5.0), 2.0, 0.0]
+    for i in range(3):
+        got_c = np.array([cx[i], cy[i], cz[i]])
+        assert np.allclose(got_c, want_c[i], rtol=0, atol=4e-6 * (1 + np.abs(want_c[i]).max())), i
+        slack = 2.0 ** -20 * (want_r[i] + np.abs(want_c[i]).max()) + 1e-5 * want_r[i] + 1e-6
+        assert want_r[i] - 1e-6 <= r[i] <= want_r[i] + slack, (i, r[i])
+
+
+@pytest.mark.parametrize("name", ["shadow_128", "refl_96", "mixed_128x72"])
+def test_triangle_spheres_contain_every_vertex(name):
+    """Every vertex of every triangle of the workload lies inside its
+    triangle's sphere in float64, and no sphere is looser than its float64
+    centroid-vertex distance by more than the padding."""
+    base, kw = small(name)
+    sc = workload(base, **kw).scene
+    cx, cy, cz, r = (x.astype(np.float64) for x in O.tri_spheres(sc))
+    ctr = np.stack([cx, cy, cz], 1)
+    d = np.linalg.norm(sc.tris.astype(np.float64) - ctr[:, None, :], axis=2).max(axis=1)
+    assert np.all(d <= r)
+    m = np.abs(ctr).max(axis=1)
+    assert np.all(r <= d * (1 + 2.0 ** -18) + 2.0 ** -18 * m + 1e-30)
