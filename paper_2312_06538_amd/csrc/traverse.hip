@@ -2,12 +2,12 @@
 //
 // Every level is produced in three launches with no wait between blocks:
 //   count  each work item (top level: one (top node, mesh) pair per wave;
-//          lower levels: a tile of 256 parent pairs, one per thread, every
-//          child unrolled, pipelined over the block's tiles -- or, for the
-//          pass forming level 1 of the plain form, one (parent, child) test
-//          per lane) runs its Eq. 9 tests and records how many pass (lower
-//          levels also keep the pass bits, one per child slot, packed in
-//          32-bit words);
+//          lower levels: a tile of 256 parent pairs -- in the plain form one
+//          (parent, child) test per lane, in the batched form one parent
+//          pair per thread with every child unrolled, pipelined over the
+//          block's tiles) runs its Eq. 9 tests and records how many pass
+//          (lower levels also keep the pass bits, one per child slot,
+//          packed in 32-bit words);
 //   scan   exclusive scan of the counts -> output offset of every item;
 //   emit   each item writes its survivors at its offset, in (parent pair,
 //          child) order -- at the top level (node, mesh, triangle) order;
@@ -29,13 +29,10 @@
 #include "traverse.hpp"
 
 #ifndef CRSH_COUNT_LANES
-#define CRSH_COUNT_LANES 1   // plain count pass forming level 1: one (parent, child) test per lane
-#endif
-#ifndef CRSH_COUNT_STAGED
-#define CRSH_COUNT_STAGED 0  // plain count passes: child nodes of a top node's sub-tree staged in LDS (measured slower)
+#define CRSH_COUNT_LANES 1   // plain count passes: one (parent, child) test per lane
 #endif
 #ifndef CRSH_COUNT_LANES_MIN_BUNDLE
-#define CRSH_COUNT_LANES_MIN_BUNDLE 16   // ... for bundles of at least this many rays
+#define CRSH_COUNT_LANES_MIN_BUNDLE 1    // ... for bundles of at least this many rays
 #endif
 
 namespace crsh {
@@ -416,18 +413,20 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     }
 }
 
-// Count pass of the plain form with one (parent pair, child) test per lane:
-// the NF lanes of a parent load its NF consecutive child nodes, so a wave's
-// node loads are contiguous (with a parent per thread, each load instruction
-// strides NF nodes across the lanes and the NF loads touch the same lines NF
-// times).  A slice covers LEVEL_THREADS / NF parents; NF slices make the
-// count tile of LEVEL_TILE parents.  A wave's ballot is the pass bits of its
-// 64 / NF parents in the mask layout of the count pass (NF bits per parent,
-// parent-major), stored as two words.  Used for the pass that forms level 1,
-// whose children are the leaves (the largest node level, past one L2), with
-// bundles of 16 rays or more: at the upper levels, whose nodes stay cached,
-// and with 4-ray bundles the pipelined parent-per-thread count measured
-// faster.
+// Count pass of the plain form with one (parent pair, child) test per lane.
+// A tile of LEVEL_TILE parent pairs is tested in NF slices of LEVEL_TILE /
+// NF parents; in a slice the NF lanes of a parent test its NF consecutive
+// children, so a wave's node loads cover 64 / NF runs of NF consecutive
+// nodes, and its ballot is directly the pass bits of its 64 / NF parents in
+// the mask layout of the count pass (NF bits per parent, parent-major).
+// What the NF lanes of a parent share -- the parent node and the triangle
+// sphere -- is read once: each lane reads the pair and sphere of one of
+// the wave's 64 parents of the tile into a wave-private LDS record, and the
+// lanes of a slice read their parent's record from there.  The vector memory
+// path, which bounds this pass, then carries per test only the child's
+// 36 bytes (buffer loads on 32-bit offsets) and 3/(64 NF) of a pair read.
+// The next tile's pairs and spheres are requested before a tile is tested
+// (pairs two tiles ahead, since the sphere read depends on them).
 template <int NF, bool PACKED>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t parent_level, uint32_t F,
                                                                      const float4 *__restrict__ na,
@@ -437,121 +436,13 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
                                                                      pair_levels P, trav_scratch S, crsh_meta *meta)
 {
     static_assert(LEVEL_PPT == 1 && WAVE % NF == 0, "whole parents per wave");
-    constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per slice
-    constexpr uint32_t SLICES = NF;               // PR * SLICES = LEVEL_TILE
-    __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
-    __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
-    const uint32_t nl = meta->n_levels;
-    if ((uint32_t)parent_level > nl) return;
-    const uint64_t ntiles = level_items(meta, parent_level, 0, P);
-    clear_scan(S, ntiles);                  // the scan that follows reads these
-    const pairs_dev in = P.p[parent_level - 1];
-    if (in.tri == nullptr || P.p[parent_level - 2].tri == nullptr) return;
-    uint64_t nin = meta->pairs[parent_level - 1];
-    nin = nin < in.cap ? nin : in.cap;
-    const uint32_t nk = meta->level_cnt[parent_level - 2];
-    const uint32_t offk = meta->level_off[parent_level - 2];
-    const uint32_t j = threadIdx.x % NF;
-    const uint32_t w = threadIdx.x / WAVE;
-    uint64_t tests = 0;
-    uint32_t parity = 0;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
-        float4 sp[SLICES], A[SLICES], Bv[SLICES];
-        float Sg[SLICES];
-        uint32_t okm = 0;                  // bit r: this lane tests a child in slice r
-#pragma unroll
-        for (uint32_t r = 0; r < SLICES; ++r) {
-            const uint64_t q = tile * LEVEL_TILE + r * PR + threadIdx.x / NF;
-            uint32_t tri = 0u, par = 0xFFFFFFFFu;
-            if (q < nin) pair_get<PACKED>(in, q, tri, par);
-            const uint32_t ch = par * F + j;
-            const bool ok = par != 0xFFFFFFFFu && j < F && ch < nk;
-            if (ok) okm |= 1u << r;
-            const uint32_t g = offk + (ok ? ch : 0u);
-            sp[r] = tsph[tri < m ? tri : 0u];
-            A[r] = na[g];
-            Bv[r] = nb[g];
-            Sg[r] = ns[g];
-        }
-        uint32_t c = 0;
-#pragma unroll
-        for (uint32_t r = 0; r < SLICES; ++r) {
-            bool pass = false;
-            if ((okm >> r) & 1u) {
-                ++tests;
-                pass = packed_meets(A[r], Bv[r], Sg[r], mk(sp[r].x, sp[r].y, sp[r].z), sp[r].w);
-            }
-            const uint64_t bal = ballot(pass);
-            if (lane_id() == 0) {
-                const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + w * (WAVE / NF)) * NF;   // a multiple of 64
-                *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal, (uint32_t)(bal >> 32));
-            }
-            c += (uint32_t)__popcll(bal);
-        }
-        // survivors of the tile: wave sums in alternating LDS slots (one
-        // barrier per tile)
-        if (lane_id() == 0) s_red32[parity][w] = c;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) t += s_red32[parity][ww];
-            S.cnt[tile] = t;
-        }
-    }
-    tests = wave_sum(tests);
-    if (lane_id() == 0) s_red[threadIdx.x / WAVE] = tests;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t tt = 0;
-        for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) tt += s_red[ww];
-        if (tt) atomicAdd((unsigned long long *)&meta->tests[parent_level - 2], (unsigned long long)tt);
-    }
-}
-
-// Count pass of the plain form with the child nodes staged in LDS.  Every
-// pair below the top descends from one top node, and the pairs of a level
-// come grouped by top node (the top level is written node by node and each
-// level below in the order of its parents), so a tile of consecutive parent
-// pairs almost always lies within one top node's sub-tree.  The children of
-// that sub-tree at the child level -- F^(levels above the child level) nodes,
-// consecutive in the level -- are copied to LDS once, and the tests (Eq. 9)
-// read them from there: the node data no longer goes through the vector
-// memory path, which bound the count (36 bytes gathered per test).
-//
-// Each block takes one contiguous run of tiles (a grid stride would send it
-// to another sub-tree at every tile).  A tile's parent pairs are read one
-// per thread into an LDS record (triangle sphere, parent node; two buffers
-// in turn), then tested one (parent, child) per lane: the NF lanes of a
-// parent read its record (one address) and NF consecutive staged children,
-// so a wave's LDS reads fall on few rows and its ballot is directly the pass
-// bits of its 64 / NF parents in the mask layout.  The tile is tested once
-// per top node from that of its first pair to that of its last, staging
-// each in turn (usually one); a pair whose top node lies outside that range
-// (the grouping above rules it out) is tested from global memory, so the
-// result never depends on the grouping.  Sub-trees whose children do not
-// fit the LDS buffer are tested from global memory throughout.  Pass masks,
-// tile counts and counters are those of k_level_count.
-constexpr uint32_t STAGE_NODES = 1024;    // child nodes one LDS buffer holds
-
-template <int NF, bool PACKED>
-__global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_staged(int32_t parent_level, uint32_t F,
-                                                                      const float4 *__restrict__ na,
-                                                                      const float4 *__restrict__ nb,
-                                                                      const float *__restrict__ ns,
-                                                                      const float4 *__restrict__ tsph, uint32_t m,
-                                                                      pair_levels P, trav_scratch S, crsh_meta *meta)
-{
-    static_assert(LEVEL_PPT == 1 && WAVE % NF == 0, "whole parents per wave");
+    constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per slice; NF slices make a tile
+    constexpr uint32_t PW = WAVE / NF;            // parents of a wave per slice
     constexpr uint32_t NONE = 0xFFFFFFFFu;
-    constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per slice; NF slices per tile
-    __shared__ float4 sA[STAGE_NODES], sB[STAGE_NODES];
-    __shared__ float sS[STAGE_NODES];
-    __shared__ float4 s_sph[2][LEVEL_TILE];        // the tile's records, two buffers in turn
-    __shared__ uint32_t s_par[2][LEVEL_TILE];
-    __shared__ uint32_t s_lo[2], s_hi[2];          // top nodes of the tile's first and last pair
     __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
     __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
-    __shared__ uint32_t s_next;
+    __shared__ float4 s_sph[LEVEL_THREADS / WAVE][WAVE];      // [wave][record]
+    __shared__ uint32_t s_par[LEVEL_THREADS / WAVE][WAVE];
     const uint32_t nl = meta->n_levels;
     if ((uint32_t)parent_level > nl || parent_level < 2) return;
     const uint64_t ntiles = level_items(meta, parent_level, 0, P);
@@ -562,156 +453,82 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_staged(int32_t pa
     nin = nin < in.cap ? nin : in.cap;
     const uint32_t nk = meta->level_cnt[parent_level - 2];
     const uint32_t offk = meta->level_off[parent_level - 2];
-    // parent-level nodes per top node (Wp, capped at 2^32 - 1: then every
-    // parent has top node 0) and child-level nodes (Wc); with Wp a power of
-    // two the top node of a parent is a shift of it
-    uint64_t Wp64 = 1;
-    for (uint32_t k = (uint32_t)parent_level; k < nl && Wp64 < 0xFFFFFFFFull; ++k) Wp64 *= F;
-    const uint32_t Wp = (uint32_t)min(Wp64, (uint64_t)0xFFFFFFFFu);
-    const uint64_t Wc = Wp64 * F;
-    const bool lds = Wc <= STAGE_NODES;
-    const bool pow2 = (Wp & (Wp - 1u)) == 0u;
-    const uint32_t wsh = pow2 ? (uint32_t)__builtin_ctz(Wp) : 0u;
-    auto top_of = [&](uint32_t par) { return pow2 ? par >> wsh : par / Wp; };
-    const uint32_t j = threadIdx.x % NF;    // child of this lane
+    const uint32_t l = lane_id();
     const uint32_t w = threadIdx.x / WAVE;
-    uint64_t tests = 0;
-    uint32_t staged = NONE;                  // top node whose children are in LDS
-    // this block's run of tiles [t0, t1)
-    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-    const uint64_t t0 = min((uint64_t)blockIdx.x * per, ntiles);
-    const uint64_t t1 = min(t0 + per, ntiles);
-    // two-stage prefetch: the next tile's triangle spheres and the pairs of
-    // the tile after it are in flight while a tile is tested (the sphere
-    // load depends on the pair load, so one stage would leave two dependent
-    // round trips to memory exposed per tile)
+    const uint32_t j = l % NF;              // child of this lane in every slice
+    const uint32_t pi = l / NF;             // parent of this lane within the wave's slice
+    // the parent whose pair and sphere this lane reads: slice l / PW,
+    // parent l % PW of the wave's share of it
+    const uint32_t own = (l / PW) * PR + w * PW + l % PW;
+    // nodes from offk + ch for ch < nk, by 32-bit byte offsets
+    const uint64_t nodes = (uint64_t)offk + nk;
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(na, nodes * 16u);
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(nb, nodes * 16u);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(ns, nodes * 4u);
     auto load_pair = [&](uint64_t tile, uint32_t &tri, uint32_t &par) {
-        const uint64_t q = tile * LEVEL_TILE + threadIdx.x;
+        const uint64_t q = tile * LEVEL_TILE + own;
         tri = 0u;
         par = NONE;
         if (q < nin) pair_get<PACKED>(in, q, tri, par);
     };
+    uint64_t tests = 0;
+    uint32_t parity = 0;
+    // two-stage prefetch: the sphere of the next tile and the pair of the
+    // tile after it are in flight while a tile is tested
     uint32_t par_n = NONE, tri_nn = 0u, par_nn = NONE;
     float4 sp_n = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (t0 < t1) {
+    if (blockIdx.x < ntiles) {
         uint32_t tri0;
-        load_pair(t0, tri0, par_n);
+        load_pair(blockIdx.x, tri0, par_n);
         sp_n = tsph[tri0 < m ? tri0 : 0u];
-        if (t0 + 1 < t1) load_pair(t0 + 1, tri_nn, par_nn);
+        if (blockIdx.x + gridDim.x < ntiles) load_pair(blockIdx.x + gridDim.x, tri_nn, par_nn);
     }
-    uint32_t it = 0;
-    for (uint64_t tile = t0; tile < t1; ++tile, ++it) {
-        const uint32_t b = it & 1u;
-        {
-            const uint32_t par = par_n;
-            const float4 sp = sp_n;
-            par_n = par_nn;
-            sp_n = tsph[tri_nn < m ? tri_nn : 0u];
-            if (tile + 2 < t1) load_pair(tile + 2, tri_nn, par_nn);
-            const uint64_t q = tile * LEVEL_TILE + threadIdx.x;
-            s_par[b][threadIdx.x] = par;
-            s_sph[b][threadIdx.x] = sp;
-            const uint64_t qlast = min(nin, (tile + 1) * LEVEL_TILE) - 1;
-            const uint32_t top = par != NONE ? top_of(par) : NONE;
-            if (q == tile * LEVEL_TILE) s_lo[b] = top;
-            if (q == qlast) s_hi[b] = top;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0 && it) {        // the previous tile's survivors
-            uint32_t t = 0;
-            for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) t += s_red32[b ^ 1u][ww];
-            S.cnt[tile - 1] = t;
-        }
-        const uint32_t lo = s_lo[b], hi = s_hi[b];
-        // this lane's (parent, child) of every slice
-        uint32_t ch[NF];
-        uint32_t topr[NF];
-        uint32_t okm = 0;                    // bit r: the lane has a child to test in slice r
-#pragma unroll
-        for (int r = 0; r < NF; ++r) {
-            const uint32_t par = s_par[b][r * PR + threadIdx.x / NF];
-            ch[r] = par * F + j;
-            topr[r] = par != NONE ? top_of(par) : NONE;
-            if (par != NONE && j < F && ch[r] < nk) okm |= 1u << r;
-        }
-        uint64_t bal[NF];
-#pragma unroll
-        for (int r = 0; r < NF; ++r) bal[r] = 0;
-        auto test = [&](int r, float4 A, float4 Bv, float Sg) {
-            const float4 sp = s_sph[b][r * PR + threadIdx.x / NF];
-            ++tests;
-            return packed_meets(A, Bv, Sg, mk(sp.x, sp.y, sp.z), sp.w);
-        };
-        if (lds) {
-            uint32_t cur = lo;
-            while (cur <= hi) {              // uniform (lo and hi are block-wide)
-                if (cur != staged) {
-                    // every lane is past its reads of the old contents (the
-                    // barrier above, or the one ending the previous top node)
-                    const uint64_t c0 = (uint64_t)cur * Wc;
-                    for (uint32_t i = threadIdx.x; i < (uint32_t)Wc; i += LEVEL_THREADS) {
-                        const uint64_t c = c0 + i;
-                        const uint32_t g = offk + (uint32_t)(c < nk ? c : 0u);
-                        sA[i] = na[g];
-                        sB[i] = nb[g];
-                        sS[i] = ns[g];
-                    }
-                    __syncthreads();
-                    staged = cur;
-                }
-                const uint32_t base = cur * (uint32_t)Wc;     // first staged child
-#pragma unroll
-                for (int r = 0; r < NF; ++r) {
-                    bool pass = false;
-                    if (((okm >> r) & 1u) && topr[r] == cur) {
-                        const uint32_t i = ch[r] - base;
-                        pass = test(r, sA[i], sB[i], sS[i]);
-                    }
-                    bal[r] |= ballot(pass);
-                }
-                if (cur == hi) break;
-                // the next top node of the tile: the smallest above cur (one
-                // exists: hi is the top node of a pair and cur < hi)
-                if (threadIdx.x == 0) s_next = NONE;
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < NF; ++r)
-                    if (((okm >> r) & 1u) && topr[r] > cur && topr[r] <= hi) atomicMin(&s_next, topr[r]);
-                __syncthreads();
-                cur = s_next;
-                __syncthreads();             // every lane has read s_next
-            }
-        }
-        // children not tested above: every one without the LDS buffer; with
-        // it, those of parents outside [lo, hi]
-#pragma unroll
-        for (int r = 0; r < NF; ++r) {
-            bool pass = false;
-            if (((okm >> r) & 1u) && (!lds || topr[r] < lo || topr[r] > hi)) {
-                const uint32_t g = offk + ch[r];
-                pass = test(r, na[g], nb[g], ns[g]);
-            }
-            bal[r] |= ballot(pass);
-        }
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
+        // this tile's records (the wave's previous reads of them are done:
+        // program order within the wave)
+        __builtin_amdgcn_wave_barrier();
+        s_sph[w][l] = sp_n;
+        s_par[w][l] = par_n;
+        __builtin_amdgcn_wave_barrier();
+        par_n = par_nn;
+        sp_n = tsph[tri_nn < m ? tri_nn : 0u];
+        if (tile + 2 * (uint64_t)gridDim.x < ntiles) load_pair(tile + 2 * (uint64_t)gridDim.x, tri_nn, par_nn);
         uint32_t c = 0;
 #pragma unroll
-        for (int r = 0; r < NF; ++r) {
-            if (lane_id() == 0) {
-                const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + w * (WAVE / NF)) * NF;   // a multiple of 64
-                *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal[r], (uint32_t)(bal[r] >> 32));
+        for (uint32_t r = 0; r < NF; ++r) {
+            const uint32_t rec = r * PW + pi;
+            const uint32_t par = s_par[w][rec];
+            const uint32_t ch = par * F + j;
+            const bool ok = par != NONE && j < F && ch < nk;
+            const uint32_t g = offk + (ok ? ch : 0u);
+            const float4 A = buf_load4(ra, g * 16u);
+            const float4 Bv = buf_load4(rb, g * 16u);
+            const float Sg = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
+            const float4 sp = s_sph[w][rec];
+            bool pass = false;
+            if (ok) {
+                ++tests;
+                pass = packed_meets(A, Bv, Sg, mk(sp.x, sp.y, sp.z), sp.w);
             }
-            c += (uint32_t)__popcll(bal[r]);
+            const uint64_t bal = ballot(pass);
+            if (l == 0) {
+                const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + w * PW) * NF;   // a multiple of 64
+                *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal, (uint32_t)(bal >> 32));
+            }
+            c += (uint32_t)__popcll(bal);
         }
-        if (lane_id() == 0) s_red32[b][w] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && it) {            // the block's last tile
-        uint32_t t = 0;
-        for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) t += s_red32[(it - 1u) & 1u][ww];
-        S.cnt[t1 - 1] = t;
+        // survivors of the tile: wave sums in alternating LDS slots (one
+        // barrier per tile)
+        if (l == 0) s_red32[parity][w] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) t += s_red32[parity][ww];
+            S.cnt[tile] = t;
+        }
     }
     tests = wave_sum(tests);
-    if (lane_id() == 0) s_red[w] = tests;
+    if (l == 0) s_red[w] = tests;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t tt = 0;
@@ -944,8 +761,7 @@ static uint32_t resident_blocks(K kernel, uint32_t threads)
 
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
-                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed, bool lanes,
-                        bool staged)
+                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed, bool lanes)
 {
     const batch_dev b = bd ? *bd : batch_dev{};
     const uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), 4096);
@@ -976,26 +792,7 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     case 8: CRSH_COUNT_LANES_ONE(8, PK) break;                                                               \
     default: CRSH_COUNT_LANES_ONE(16, PK) break;                                                             \
     }
-#define CRSH_COUNT_STAGED_ONE(NF, PK)                                                                        \
-    {                                                                                                        \
-        const uint32_t rb = resident_blocks(k_level_count_staged<NF, PK>, LEVEL_THREADS);                    \
-        const uint32_t gl = rb ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), rb) : g;    \
-        k_level_count_staged<NF, PK><<<gl, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); \
-    }
-#define CRSH_COUNT_STAGED_NF(PK)                                                                             \
-    switch (nf) {                                                                                            \
-    case 2: CRSH_COUNT_STAGED_ONE(2, PK) break;                                                              \
-    case 4: CRSH_COUNT_STAGED_ONE(4, PK) break;                                                              \
-    case 8: CRSH_COUNT_STAGED_ONE(8, PK) break;                                                              \
-    default: CRSH_COUNT_STAGED_ONE(16, PK) break;                                                            \
-    }
-    if (CRSH_COUNT_STAGED && staged && !bd && LEVEL_PPT == 1) {
-        if (packed) {
-            CRSH_COUNT_STAGED_NF(true)
-        } else {
-            CRSH_COUNT_STAGED_NF(false)
-        }
-    } else if (CRSH_COUNT_LANES && lanes && !bd && LEVEL_PPT == 1 && L == 2) {
+    if (CRSH_COUNT_LANES && lanes && !bd && LEVEL_PPT == 1) {
         if (packed) {
             CRSH_COUNT_LANES_NF(true)
         } else {
@@ -1008,8 +805,6 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     } else {
         CRSH_COUNT_NF(false, false)
     }
-#undef CRSH_COUNT_STAGED_NF
-#undef CRSH_COUNT_STAGED_ONE
 #undef CRSH_COUNT_LANES_NF
 #undef CRSH_COUNT_LANES_ONE
 #undef CRSH_COUNT_NF
@@ -1162,12 +957,8 @@ static crsh_status traverse_run(const crsh_nodes *nodes, const crsh_scene *scene
     case 8: CRSH_EMIT(8, BT, PK); break;                                                                   \
     default: CRSH_EMIT(16, BT, PK); break;                                                                 \
     }
-        // children per top node at the child level, bounded with the levels
-        // that have pair storage (the tree has no more)
-        uint64_t wc = 1;
-        for (int k = L - 1; k < levels && wc <= STAGE_NODES; ++k) wc *= (uint64_t)merge;
         level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream, packed,
-                           bundle >= CRSH_COUNT_LANES_MIN_BUNDLE, wc <= STAGE_NODES);
+                           bundle >= CRSH_COUNT_LANES_MIN_BUNDLE);
         k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
             prof_scope ps("k_level_emit", stream);
