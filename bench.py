@@ -26,22 +26,34 @@ sys.path.insert(0, ROOT)
 # operation per lane per cycle, 64 lanes per CU (4 SIMD x 16), 256 CUs,
 # 2.4 GHz -> 39.3 T operations/s.
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# float32 operations of one complete Moller-Trumbore test as written (two
-# cross products 9 + 9, four dot products 5 x 4, one reciprocal, three
-# scalings by it, origin offset 3, seven comparisons and one add).
-MT_OPS = 53
+# Algorithmic float32 operations of the Moller-Trumbore test as written
+# (Sec. 3.3.8), with its early exits: every test computes p = D x e2 (9),
+# det = e1 . p (5), checks |det| (1), 1 / det (1), T = O - v0 (3), u (a dot
+# product 5 and the scaling 1) and checks its two bounds (2): 27 operations;
+# a test whose u passes adds q = T x e1 (9), v (6) and its checks (v >= 0,
+# u + v, <= 1: 3): 18 more; a test whose u and v pass adds t (6) and its two
+# bounds (2): 8 more.  The kernels count the tests that pass u and those that
+# pass u and v (crsh_meta.final_u_pass / final_uv_pass).  e1 and e2 are
+# per-triangle precomputation, not per-test work; a test failing the
+# determinant check (a ray parallel to the plane, a vanishing share) is
+# counted as if it reached the u check.
+MT_OPS_ALL, MT_OPS_U, MT_OPS_UV = 27, 18, 8
 # float32 operations of one node-sphere test (Eq. 9) as written: P - C (3),
-# (P-C).a (5), (P-C) x a (9), its squared length (5), |t| tan + (d + r) sec
-# (5), squaring (1), comparison (1), the full-cone check (1).
-NODE_OPS = 30
+# t = (P-C).a (5), (P-C) x a (9), its squared length (5),
+# |t| tan + (d + r) sec (4: two products, two sums), squaring (1),
+# comparison (1), the full-cone check (1).
+NODE_OPS = 29
 HBM_PEAK_GBS = 8000.0
+# MI355X's published float32 vector peak, which counts a fused multiply-add
+# as two operations and packed float32 as two lanes
+PUBLISHED_FP32_TFLOPS = 157.3
 
 
 # HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, WRITE_SIZE; calibrated against a copy of known size).
 # The summary records a hash of the kernel's source files; a figure taken
 # before the sources changed is not reported.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_hit_hbm_traffic_refl_1024.md")
+TRAFFIC_PROFILES = "profiles/*_hbm_traffic_*.md"
 TRAFFIC_SOURCES = {"k_hit": ["paper_2312_06538_amd/csrc/hit.hip", "paper_2312_06538_amd/csrc/intersect.hpp",
                              "paper_2312_06538_amd/csrc/batch.hpp", "paper_2312_06538_amd/csrc/common.hpp",
                              "include/crsh.h"]}
@@ -57,21 +69,22 @@ def sources_sha256(kernel):
 
 
 def measured_traffic(kernel, workload):
-    """(bytes per launch, note) from the traffic summary, or (None, why)."""
-    try:
-        lines = open(TRAFFIC_PROFILE).read().splitlines()
-    except OSError:
-        return None, "no traffic summary"
-    for ln in lines:
-        if not ln.startswith("bench-traffic:"):
-            continue
-        kv = dict(f.split("=", 1) for f in ln.split()[1:])
-        if kv.get("kernel") != kernel or kv.get("workload") != workload:
-            continue
-        if kv.get("sources") != sources_sha256(kernel):
-            return None, "counters predate the kernel's current sources"
-        return int(kv["bytes"]), f"rocprofv3 FETCH_SIZE + WRITE_SIZE, {os.path.basename(TRAFFIC_PROFILE)}"
-    return None, "no counters for this kernel and workload"
+    """(bytes per launch, note) from a traffic summary, or (None, why)."""
+    import glob
+    stale = False
+    for path in sorted(glob.glob(os.path.join(ROOT, TRAFFIC_PROFILES))):
+        for ln in open(path).read().splitlines():
+            if not ln.startswith("bench-traffic:"):
+                continue
+            kv = dict(f.split("=", 1) for f in ln.split()[1:])
+            if kv.get("kernel") != kernel or kv.get("workload") != workload:
+                continue
+            if kv.get("sources") != sources_sha256(kernel):
+                stale = True
+                continue
+            return int(kv["bytes"]), f"rocprofv3 FETCH_SIZE + WRITE_SIZE, {os.path.basename(path)}"
+    return None, ("counters predate the kernel's current sources" if stale
+                  else "no counters for this kernel and workload")
 
 
 def hip():
@@ -205,8 +218,12 @@ def main():
                     help="pair storage: two uint32 arrays, or one packed word per pair over triangle batches of "
                          "at most 2^14 triangles (crsh_traverse_packed)")
     ap.add_argument("--variant", default="crsh", choices=["crsh", "unsorted"],
-                    help="unsorted: the comparison hierarchy without ray sorting, whole-mesh culling or a "
-                         "level cap, on the same inputs")
+                    help="unsorted: the comparison hierarchy without ray sorting or whole-mesh culling, on the "
+                         "same inputs and with the same hierarchy shape")
+    ap.add_argument("--size", default=None, help="WxH: the workload's scene and camera at another resolution")
+    ap.add_argument("--bundle", type=int, default=None, help="rays per leaf (B) instead of the workload's")
+    ap.add_argument("--merge", type=int, default=None, help="children per node (F) instead of the workload's")
+    ap.add_argument("--levels", type=int, default=None, help="hierarchy levels (n) instead of the workload's")
     ap.add_argument("--frames", type=int, default=64, help="batch_64: number of frames")
     ap.add_argument("--sort-sweep", action="store_true",
                     help="instead of a frame: crsh_sort on 2^20..2^27 random keys, GB/s per radix pass")
@@ -235,7 +252,13 @@ def main():
     from workloads import make_workload
 
     t0 = time.perf_counter()
-    wl = make_workload(args.workload, seed=args.seed)
+    kw = {}
+    if args.size:
+        kw["W"], kw["H"] = (int(x) for x in args.size.lower().split("x"))
+    for k, v in (("B", args.bundle), ("F", args.merge), ("n", args.levels)):
+        if v is not None:
+            kw[k] = v
+    wl = make_workload(args.workload, seed=args.seed, **kw)
     if args.variant == "unsorted":
         from workloads import unsorted_variant
         wl = unsorted_variant(wl)
@@ -293,13 +316,16 @@ def main():
     final = int(m.final_tests)
     brute = n * wl.scene.m
     kern = {}
-    work = {"k_hit": final * MT_OPS, "k_level": int(m.tests[0]) * NODE_OPS}
+    u_pass, uv_pass = int(m.final_u_pass), int(m.final_uv_pass)
+    work = {"k_hit": final * MT_OPS_ALL + u_pass * MT_OPS_U + uv_pass * MT_OPS_UV,
+            "k_level": int(m.tests[0]) * NODE_OPS}
     for name in work:
         if durs.get(name):
             avg = sum(durs[name]) / len(durs[name])
             tops = work[name] / (avg * 1e-3) / 1e12
             kern[name] = {"bound": "alu", "achieved": round(tops, 3), "peak": round(ALU_PEAK_TOPS, 1),
                           "unit": "TOP/s", "frac": round(tops / ALU_PEAK_TOPS, 4), "traffic": None,
+                          "frac_of_published_fp32": round(tops / PUBLISHED_FP32_TFLOPS, 4),
                           "kernel": name, "kernel_ms": round(avg, 4), "ops_per_launch": work[name],
                           "launches_timed": len(durs[name])}
     dom = max(kern, key=lambda k: kern[k]["kernel_ms"]) if kern else None
@@ -337,7 +363,8 @@ def main():
                                f"{wl.scene.n_mesh} meshes, {wl.scene.m} triangles, B={wl.B} F={wl.F} n={wl.n}",
                    "rays": n, "triangles": wl.scene.m, "seed": args.seed, "variant": args.variant,
                    "pairs": args.pairs},
-        "tests": {"node_tests": node_tests, "final_ray_tri_tests": final, "total": node_tests + final,
+        "tests": {"node_tests": node_tests, "final_ray_tri_tests": final, "final_u_pass": u_pass,
+                  "final_uv_pass": uv_pass, "total": node_tests + final,
                   "brute_force": brute, "frac_of_brute": round((node_tests + final) / brute, 5),
                   "mesh_tests": int(m.mesh_tests), "levels": nl},
         "roofline": roof,

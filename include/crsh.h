@@ -95,6 +95,8 @@ typedef struct crsh_meta {
     uint64_t final_tests;                   /* ray-triangle tests of Sec. 3.3.8 */
     uint64_t rays_required;                 /* rays that crsh_hash wanted to write */
     uint64_t nodes_required;                /* nodes that crsh_build wanted to write */
+    uint64_t final_u_pass;                  /* final tests whose u passed (Moller-Trumbore, Sec. 3.3.8) */
+    uint64_t final_uv_pass;                 /* final tests whose u and v passed */
 } crsh_meta;
 
 /* Primary-hit buffer (Sec. 3.2), W*H pixels in row-major order: hit position,

@@ -824,9 +824,12 @@ void orc_trav_free(orc_trav *T)
  * Stage 5: final intersection tests and closest hit (Sec. 3.3.8)
  * ====================================================================== */
 
-/* Moller-Trumbore ray-triangle test, two-sided, accepting t in (t_min, tmax). */
-static int mt_test(v3 O, v3 D, float t_min, float tmax, v3 v0, v3 v1, v3 v2,
-                   float *pt, float *pu, float *pv)
+/* Moller-Trumbore ray-triangle test, two-sided, accepting t in (t_min, tmax).
+ * Returns how far the test got: 0 the determinant is too small, 1 u failed,
+ * 2 v (or u + v) failed, 3 t is outside the interval, 4 accepted (then t, u,
+ * v are written). */
+static int mt_stage(v3 O, v3 D, float t_min, float tmax, v3 v0, v3 v1, v3 v2,
+                    float *pt, float *pu, float *pv)
 {
     v3 e1 = vsub(v1, v0);
     v3 e2 = vsub(v2, v0);
@@ -836,14 +839,20 @@ static int mt_test(v3 O, v3 D, float t_min, float tmax, v3 v0, v3 v1, v3 v2,
     float inv = 1.0f / det;
     v3 T = vsub(O, v0);
     float u = vdot(T, p) * inv;
-    if (!(u >= 0.0f && u <= 1.0f)) return 0;
+    if (!(u >= 0.0f && u <= 1.0f)) return 1;
     v3 q = vcross(T, e1);
     float v = vdot(D, q) * inv;
-    if (!(v >= 0.0f && u + v <= 1.0f)) return 0;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return 2;
     float t = vdot(e2, q) * inv;
-    if (!(t > t_min && t < tmax)) return 0;
+    if (!(t > t_min && t < tmax)) return 3;
     *pt = t; *pu = u; *pv = v;
-    return 1;
+    return 4;
+}
+
+static int mt_test(v3 O, v3 D, float t_min, float tmax, v3 v0, v3 v1, v3 v2,
+                   float *pt, float *pu, float *pv)
+{
+    return mt_stage(O, D, t_min, tmax, v0, v1, v2, pt, pu, pv) == 4;
 }
 
 int orc_mt(const float o[3], const float d[3], float t_min, float tmax, const float tri[9], float out[3])
@@ -869,8 +878,10 @@ static void keep_closest(int32_t *best_tri, float *bt, float *bu, float *bv, uin
 void orc_closest_hit(const orc_rays *rays, const uint32_t *sorted_ids, uint32_t n_rays, int B,
                      const uint32_t *pair_tri, const uint32_t *pair_node, uint64_t n_pairs,
                      const float *const v[9], float t_min,
-                     int32_t *hit_tri, float *ht, float *hu, float *hv)
+                     int32_t *hit_tri, float *ht, float *hu, float *hv, uint64_t *stage_counts)
 {
+    /* stage_counts (may be NULL) accumulates [tests whose u passed, tests
+     * whose u and v passed] */
     for (uint64_t q = 0; q < n_pairs; ++q) {
         uint32_t t = pair_tri[q], j = pair_node[q];
         v3 a = mk(v[0][t], v[1][t], v[2][t]);
@@ -881,10 +892,14 @@ void orc_closest_hit(const orc_rays *rays, const uint32_t *sorted_ids, uint32_t 
         for (uint32_t s = s0; s < s1; ++s) {
             uint32_t id = sorted_ids[s];
             float tt, uu, vv;
-            if (mt_test(mk(rays->ox[id], rays->oy[id], rays->oz[id]),
-                        mk(rays->dx[id], rays->dy[id], rays->dz[id]),
-                        t_min, rays->tmax[id], a, b, c, &tt, &uu, &vv))
-                keep_closest(hit_tri, ht, hu, hv, id, t, tt, uu, vv);
+            const int st = mt_stage(mk(rays->ox[id], rays->oy[id], rays->oz[id]),
+                                    mk(rays->dx[id], rays->dy[id], rays->dz[id]),
+                                    t_min, rays->tmax[id], a, b, c, &tt, &uu, &vv);
+            if (stage_counts) {
+                stage_counts[0] += st >= 2;
+                stage_counts[1] += st >= 3;
+            }
+            if (st == 4) keep_closest(hit_tri, ht, hu, hv, id, t, tt, uu, vv);
         }
     }
 }

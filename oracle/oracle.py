@@ -85,7 +85,7 @@ def lib():
         L.orc_trav_counters.argtypes = [C.c_void_p, u64p, u64p]
         L.orc_trav_free.argtypes = [C.c_void_p]
         L.orc_closest_hit.argtypes = [C.POINTER(Rays), u32p, C.c_uint32, C.c_int, u32p, u32p, C.c_uint64,
-                                      f32p * 9, C.c_float, i32p, f32p, f32p, f32p]
+                                      f32p * 9, C.c_float, i32p, f32p, f32p, f32p, u64p]
         L.orc_brute_closest_hit.argtypes = [C.POINTER(Rays), u32p, C.c_uint32, f32p * 9, C.c_uint32,
                                             C.c_float, i32p, f32p, f32p, f32p]
         L.orc_brute_all_hits.restype = C.c_uint64
@@ -266,8 +266,10 @@ def _tri_arr(scene):
     return v, (f32p * 9)(*[_p(a, f32p) for a in v])
 
 
-def closest_hit(rays, sorted_ids, B, pairs1, scene, t_min, init=None):
-    """Stage 5 over the level-1 pairs.  Returns (tri int32, t, u, v) by ray id."""
+def closest_hit(rays, sorted_ids, B, pairs1, scene, t_min, init=None, stages=None):
+    """Stage 5 over the level-1 pairs.  Returns (tri int32, t, u, v) by ray id.
+    With `stages` (a dict), adds to stages["u"] / stages["uv"] the tests whose
+    u passed / whose u and v passed."""
     rays = {k: _f32(rays[k]) for k in RAY_FIELDS} | {"pix": _u32(rays["pix"])}
     sorted_ids = _u32(sorted_ids)
     n = len(sorted_ids)
@@ -279,8 +281,13 @@ def closest_hit(rays, sorted_ids, B, pairs1, scene, t_min, init=None):
     ptri, pnode = _u32(pairs1[0]), _u32(pairs1[1])
     keep, arr = _tri_arr(scene)
     rs = _rays_struct(rays)
+    cnt = np.zeros(2, np.uint64)
     lib().orc_closest_hit(C.byref(rs), _p(sorted_ids, u32p), n, B, _p(ptri, u32p), _p(pnode, u32p),
-                          len(ptri), arr, t_min, _p(tri, i32p), _p(t, f32p), _p(u, f32p), _p(v, f32p))
+                          len(ptri), arr, t_min, _p(tri, i32p), _p(t, f32p), _p(u, f32p), _p(v, f32p),
+                          _p(cnt, u64p))
+    if stages is not None:
+        stages["u"] = stages.get("u", 0) + int(cnt[0])
+        stages["uv"] = stages.get("uv", 0) + int(cnt[1])
     return tri, t, u, v
 
 
@@ -456,14 +463,15 @@ def run_pipeline(wl, top_subset=None, tri_batches=None):
     batches = tri_batches or [(0, wl.scene.m)]
     hits = None
     travs = []
+    stages = {"u": 0, "uv": 0}
     for (b, e) in batches:
         tr = traverse(tree, wl.scene, b, e, top_subset=top_subset, tsph=tsph)
         travs.append(tr)
         if tree["n_levels"]:
-            hits = closest_hit(h["rays"], ids, wl.B, tr["pairs"][1], wl.scene, wl.t_min, init=hits)
+            hits = closest_hit(h["rays"], ids, wl.B, tr["pairs"][1], wl.scene, wl.t_min, init=hits, stages=stages)
     if hits is None:
         n = h["n"]
         hits = (np.full(n, -1, np.int32), np.zeros(n, np.float32), np.zeros(n, np.float32),
                 np.zeros(n, np.float32))
     return {"hash": h, "sorted_keys": ks, "sorted_ids": ids, "tree": tree, "tsph": tsph,
-            "trav": travs[0] if len(travs) == 1 else travs, "hits": hits}
+            "trav": travs[0] if len(travs) == 1 else travs, "hits": hits, "stages": stages}

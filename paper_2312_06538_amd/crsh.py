@@ -43,7 +43,8 @@ class Meta(C.Structure):
                 ("pairs", C.c_uint64 * MAX_LEVELS), ("hits", C.c_uint64 * MAX_LEVELS),
                 ("tests", C.c_uint64 * MAX_LEVELS),
                 ("mesh_tests", C.c_uint64), ("mesh_hits", C.c_uint64), ("final_tests", C.c_uint64),
-                ("rays_required", C.c_uint64), ("nodes_required", C.c_uint64)]
+                ("rays_required", C.c_uint64), ("nodes_required", C.c_uint64),
+                ("final_u_pass", C.c_uint64), ("final_uv_pass", C.c_uint64)]
 
 
 class Gbuf(C.Structure):

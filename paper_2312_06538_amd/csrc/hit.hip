@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
                                              uint64_t cap1, uint32_t B, uint32_t log2G, unsigned long long *keys,
                                              crsh_meta *meta, uint32_t slot_cap, uint32_t m, uint32_t tri_base)
 {
-    __shared__ uint64_t s_red[256 / WAVE];
+    __shared__ uint64_t s_red[3][256 / WAVE];
     __shared__ float4 s_rec[256 / WAVE][3][WAVE];    // [wave][record word][pair of the run]
     const uint32_t ns = BATCH ? batch_slots(meta, B, slot_cap) : min(meta->n_rays, slot_cap);
     uint64_t np = meta->n_levels ? meta->pairs[0] : 0;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
     const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
     const uint32_t jo = j * 32u;
     float4(*rec)[WAVE] = s_rec[wib];
-    uint64_t tests = 0;
+    uint64_t tests = 0, upass = 0, uvpass = 0;   // wave-wide counts
     for (uint64_t c0 = wave * WAVE; c0 < np; c0 += nwaves * WAVE) {
         const uint32_t cn = __builtin_amdgcn_readfirstlane((uint32_t)min(np - c0, (uint64_t)WAVE));
         uint32_t my_t = 0u, my_rb = 0u, my_cnt = 0u;
@@ -191,17 +191,26 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
             // one of its lanes needs it
             if (ballot(maybe) != 0) {
                 float th;
-                if (mt_second_half(D, rd4.w, ro4.w, tr, h, th) && maybe)
-                    atomicMin(&keys[ro >> 5], hit_key(th, __float_as_uint(c.y)));
+                const uint32_t st = maybe ? mt_second_half(D, rd4.w, ro4.w, tr, h, th) : 0u;
+                upass += (uint64_t)__popcll(ballot((st & MT_U) != 0u));
+                uvpass += (uint64_t)__popcll(ballot((st & MT_UV) != 0u));
+                if (st & MT_HIT) atomicMin(&keys[ro >> 5], hit_key(th, __float_as_uint(c.y)));
             }
         }
     }
-    if (l == 0) s_red[wib] = tests;
+    if (l == 0) {
+        s_red[0][wib] = tests;
+        s_red[1][wib] = upass;
+        s_red[2][wib] = uvpass;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 3) {
         uint64_t tot = 0;
-        for (uint32_t i = 0; i < blockDim.x / WAVE; ++i) tot += s_red[i];
-        if (tot) atomicAdd((unsigned long long *)&meta->final_tests, (unsigned long long)tot);
+        for (uint32_t i = 0; i < blockDim.x / WAVE; ++i) tot += s_red[threadIdx.x][i];
+        unsigned long long *dst = threadIdx.x == 0 ? (unsigned long long *)&meta->final_tests
+                                : threadIdx.x == 1 ? (unsigned long long *)&meta->final_u_pass
+                                                   : (unsigned long long *)&meta->final_uv_pass;
+        if (tot) atomicAdd(dst, (unsigned long long)tot);
     }
 }
 

@@ -40,7 +40,12 @@ __device__ __forceinline__ tri_t load_tri(const float4 *__restrict__ tri, uint32
     return r;
 }
 
-// Two-sided Moller-Trumbore, accepted for t_min < t < tmax.
+// Checks of the test a ray passed: MT_U (u in [0, 1]), MT_UV (and v >= 0,
+// u + v <= 1), MT_HIT (and t_min < t < tmax), each implying the ones before.
+constexpr uint32_t MT_U = 1u, MT_UV = 2u, MT_HIT = 4u;
+
+// Two-sided Moller-Trumbore, accepted for t_min < t < tmax; the checks passed
+// go to *checks when given.
 //
 // u = a * (1/det) is first decided without the division where its sign or
 // size settles the test exactly as the rounded quotient would: with
@@ -49,8 +54,9 @@ __device__ __forceinline__ tri_t load_tri(const float4 *__restrict__ tri, uint32
 // |det| (1 + 2^-19) with equal signs gives a quotient above 1 + 2^-20, which
 // two roundings cannot bring down to 1.  Other cases divide as written.
 __device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float tmax, const tri_t &tr, float &tt,
-                                                float &uu, float &vv)
+                                                float &uu, float &vv, uint32_t *checks = nullptr)
 {
+    if (checks) *checks = 0u;
     f3 p = cross(D, tr.e2);
     float det = dot(tr.e1, p);
     const float adet = fabsf(det);
@@ -65,11 +71,14 @@ __device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float t
     float inv = 1.0f / det;
     float u = a * inv;
     if (!(u >= 0.0f && u <= 1.0f)) return false;
+    if (checks) *checks = MT_U;
     f3 q = cross(T, tr.e1);
     float v = dot(D, q) * inv;
     if (!(v >= 0.0f && u + v <= 1.0f)) return false;
+    if (checks) *checks = MT_U | MT_UV;
     float t = dot(tr.e2, q) * inv;
     if (!(t > t_min && t < tmax)) return false;
+    if (checks) *checks = MT_U | MT_UV | MT_HIT;
     tt = t;
     uu = u;
     vv = v;
@@ -105,8 +114,9 @@ __device__ __forceinline__ bool mt_first_half(f3 O, f3 D, const tri_t &tr, mt_he
 
 // The rest of the test for a ray that mt_first_half let through: the same
 // operations, in the same order, as moller_trumbore after its early checks.
-__device__ __forceinline__ bool mt_second_half(f3 D, float t_min, float tmax, const tri_t &tr, const mt_head &h,
-                                               float &tt)
+// Returns the checks passed (MT_U, MT_UV, MT_HIT).
+__device__ __forceinline__ uint32_t mt_second_half(f3 D, float t_min, float tmax, const tri_t &tr, const mt_head &h,
+                                                   float &tt)
 {
     const float inv = 1.0f / h.det;
     const float u = h.a * inv;
@@ -114,7 +124,10 @@ __device__ __forceinline__ bool mt_second_half(f3 D, float t_min, float tmax, co
     const float v = dot(D, q) * inv;
     const float t = dot(tr.e2, q) * inv;
     tt = t;
-    return (u >= 0.0f && u <= 1.0f) && (v >= 0.0f && u + v <= 1.0f) && (t > t_min && t < tmax);
+    const bool pu = u >= 0.0f && u <= 1.0f;
+    const bool puv = pu && (v >= 0.0f && u + v <= 1.0f);
+    const bool hit = puv && (t > t_min && t < tmax);
+    return (pu ? MT_U : 0u) | (puv ? MT_UV : 0u) | (hit ? MT_HIT : 0u);
 }
 
 // The same test for the final-test kernel, without early exits: every

@@ -255,7 +255,7 @@ __global__ __launch_bounds__(LH_THREADS) void k_leaf_hit(lh_args a, lh_ws L, crs
     __shared__ float4 s_d[LH_MAX_RAYS];
     __shared__ unsigned long long s_best[LH_MAX_RAYS];
     __shared__ uint32_t s_first[NF], s_count[NF];
-    __shared__ uint64_t s_red[3][LH_WAVES];
+    __shared__ uint64_t s_red[5][LH_WAVES];
     uint32_t n2;
     uint64_t nin;
     level2_sizes(meta, a.cap2, a.node_cap, n2, nin);
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(LH_THREADS) void k_leaf_hit(lh_args a, lh_ws L, crs
     const uint32_t j = l & ((1u << a.log2G) - 1u);
     const uint32_t tk = l / NF;          // Eq. 9 slot of this lane: triangle tk of a round ...
     const uint32_t tc = l % NF;          // ... against child tc
-    uint64_t tests = 0, hits = 0, finals = 0;
+    uint64_t tests = 0, hits = 0, finals = 0, upass = 0, uvpass = 0;
     for (uint32_t item = blockIdx.x; item < items; item += gridDim.x) {
         const uint32_t P = last_at_most(n2, item, [&](uint32_t q) { return L.ib[q]; });
         const uint64_t pstart = L.off[P];
@@ -359,8 +359,12 @@ __global__ __launch_bounds__(LH_THREADS) void k_leaf_hit(lh_args a, lh_ws L, crs
                         const uint32_t ri = cc * a.B + j;
                         const float4 o = s_o[ri], d = s_d[ri];
                         float th, uh, vh;
-                        if (moller_trumbore(mk(o.x, o.y, o.z), mk(d.x, d.y, d.z), t_min, o.w, tr, th, uh, vh))
+                        uint32_t checks;
+                        if (moller_trumbore(mk(o.x, o.y, o.z), mk(d.x, d.y, d.z), t_min, o.w, tr, th, uh, vh,
+                                            &checks))
                             atomicMin(&s_best[ri], hit_key(th, tt));
+                        upass += (checks & MT_U) ? 1u : 0u;
+                        uvpass += (checks & MT_UV) ? 1u : 0u;
                     }
                 }
             }
@@ -378,22 +382,26 @@ __global__ __launch_bounds__(LH_THREADS) void k_leaf_hit(lh_args a, lh_ws L, crs
     tests = wave_sum(tests);
     hits = wave_sum(hits);
     finals = wave_sum(finals);
+    upass = wave_sum(upass);
+    uvpass = wave_sum(uvpass);
     if (l == 0) {
         s_red[0][w] = tests;
         s_red[1][w] = hits;
         s_red[2][w] = finals;
+        s_red[3][w] = upass;
+        s_red[4][w] = uvpass;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint64_t t0 = 0, t1 = 0, t2 = 0;
-        for (uint32_t i = 0; i < LH_WAVES; ++i) {
-            t0 += s_red[0][i];
-            t1 += s_red[1][i];
-            t2 += s_red[2][i];
-        }
-        if (t0) atomicAdd((unsigned long long *)&meta->tests[0], (unsigned long long)t0);
-        if (t1) atomicAdd((unsigned long long *)&meta->hits[0], (unsigned long long)t1);
-        if (t2) atomicAdd((unsigned long long *)&meta->final_tests, (unsigned long long)t2);
+        uint64_t t[5] = {0, 0, 0, 0, 0};
+        for (uint32_t i = 0; i < LH_WAVES; ++i)
+            for (int k = 0; k < 5; ++k) t[k] += s_red[k][i];
+        unsigned long long *dst[5] = {(unsigned long long *)&meta->tests[0], (unsigned long long *)&meta->hits[0],
+                                      (unsigned long long *)&meta->final_tests,
+                                      (unsigned long long *)&meta->final_u_pass,
+                                      (unsigned long long *)&meta->final_uv_pass};
+        for (int k = 0; k < 5; ++k)
+            if (t[k]) atomicAdd(dst[k], (unsigned long long)t[k]);
     }
 }
 

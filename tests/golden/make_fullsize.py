@@ -12,7 +12,8 @@ sub-trees' levels in top-node order.
 Written per workload, to ``fullsize_<name>.json``:
 
 * every traversal counter of the frame: node tests and surviving pairs per
-  level, mesh tests and hits, final ray-triangle tests;
+  level, mesh tests and hits, final ray-triangle tests, and how many of
+  those passed the u check and the u and v checks;
 * per top node: its level-1 pair count and the SHA-256 of its level-1 pairs
   (the triangle ids, then the node ids, as little-endian uint32);
 * ``pairs1_sha256``: SHA-256 of the concatenated per-top-node digests;
@@ -47,7 +48,8 @@ def _subtree(i):
     t0 = time.perf_counter()
     tr = O.traverse(tree, wl.scene, top_subset=np.array([i], np.uint32), tsph=tsph)
     t1 = time.perf_counter()
-    hits = O.closest_hit(h["rays"], ids, wl.B, tr["pairs"][1], wl.scene, wl.t_min)
+    stages = {}
+    hits = O.closest_hit(h["rays"], ids, wl.B, tr["pairs"][1], wl.scene, wl.t_min, stages=stages)
     t2 = time.perf_counter()
     nl = tree["n_levels"]
     span = wl.B * wl.F ** (nl - 1)
@@ -56,7 +58,8 @@ def _subtree(i):
     p1t, p1n = tr["pairs"][1]
     dig = hashlib.sha256(np.ascontiguousarray(p1t, "<u4").tobytes() + np.ascontiguousarray(p1n, "<u4").tobytes())
     return {"i": i, "tests": tr["tests"], "hits": tr["hits"], "mesh_tests": tr["mesh_tests"],
-            "mesh_hits": tr["mesh_hits"], "final_tests": tr["final_tests"], "n1": int(len(p1t)),
+            "mesh_hits": tr["mesh_hits"], "final_tests": tr["final_tests"], "u_pass": stages["u"],
+            "uv_pass": stages["uv"], "n1": int(len(p1t)),
             "sha": dig.hexdigest(), "rid": rid, "hit": [a[rid] for a in hits],
             "sec_traverse": t1 - t0, "sec_hit": t2 - t1}
 
@@ -82,7 +85,7 @@ def make(name, jobs, out_dir):
     t, u, v = (np.zeros(n, np.float32) for _ in range(3))
     tests = {lv: 0 for lv in range(1, nl + 1)}
     hits = {lv: 0 for lv in range(1, nl + 1)}
-    tot = {"mesh_tests": 0, "mesh_hits": 0, "final_tests": 0}
+    tot = {"mesh_tests": 0, "mesh_hits": 0, "final_tests": 0, "u_pass": 0, "uv_pass": 0}
     per_top = []
     secs = []
     ctx = mp.get_context("fork")

@@ -39,7 +39,7 @@ LAYOUT_C = r"""
 #define O(t, f) printf(#t "." #f " %zu\n", offsetof(t, f));
 int main(void) {
   S(crsh_meta) O(crsh_meta, status) O(crsh_meta, pairs) O(crsh_meta, hits) O(crsh_meta, tests)
-  O(crsh_meta, final_tests) O(crsh_meta, nodes_required)
+  O(crsh_meta, final_tests) O(crsh_meta, nodes_required) O(crsh_meta, final_u_pass) O(crsh_meta, final_uv_pass)
   S(crsh_gbuf) O(crsh_gbuf, mat) O(crsh_gbuf, w)
   S(crsh_raygen) O(crsh_raygen, mat_flags) O(crsh_raygen, ray_types) O(crsh_raygen, inv_ext)
   S(crsh_rays) O(crsh_rays, pix) O(crsh_rays, capacity)

@@ -100,12 +100,14 @@ def check_frame(got, wl, orc, all_levels):
 
 
 def _counters(orcs):
-    tot = {"mesh_tests": 0, "mesh_hits": 0, "final_tests": 0, "tests": {}, "hits": {}}
+    tot = {"mesh_tests": 0, "mesh_hits": 0, "final_tests": 0, "tests": {}, "hits": {}, "u": 0, "uv": 0}
     for o in orcs:
         tr = o["trav"]
         tot["mesh_tests"] += tr["mesh_tests"]
         tot["mesh_hits"] += tr["mesh_hits"]
         tot["final_tests"] += tr["final_tests"]
+        tot["u"] += o.get("stages", {}).get("u", 0)
+        tot["uv"] += o.get("stages", {}).get("uv", 0)
         for lv, v in tr["tests"].items():
             tot["tests"][lv] = tot["tests"].get(lv, 0) + v
         for lv, (t, _) in tr["pairs"].items():
@@ -132,6 +134,7 @@ def test_batch_matches_oracle_per_frame(hit_block):
     assert int(m.mesh_tests) == tot["mesh_tests"]
     assert int(m.mesh_hits) == tot["mesh_hits"]
     assert int(m.final_tests) == tot["final_tests"]
+    assert (int(m.final_u_pass), int(m.final_uv_pass)) == (tot["u"], tot["uv"])
     for lv, v in tot["tests"].items():
         assert int(m.tests[lv - 1]) == v, lv
     for lv, v in tot["hits"].items():

@@ -52,6 +52,7 @@ def check_against_golden(g, gold, F):
     assert [g["hits"][lv] for lv in range(1, nl + 1)] == gold["hits"]
     for k in ("mesh_tests", "mesh_hits", "final_tests"):
         assert g[k] == gold[k], k
+    assert (int(g["meta"].final_u_pass), int(g["meta"].final_uv_pass)) == (gold["u_pass"], gold["uv_pass"])
     t1, n1 = g["pairs"][1]
     assert len(t1) == gold["hits"][0]
     span = F ** (nl - 1)

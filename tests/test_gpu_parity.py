@@ -187,7 +187,8 @@ def test_traverse_bit_exact(name):
     assert g["mesh_hits"] == tr["mesh_hits"]
 
 
-@pytest.mark.parametrize("B,F,n", [(16, 2, 4), (16, 3, 3), (16, 8, 3), (32, 16, 2), (24, 4, 4), (8, 4, 4)])
+@pytest.mark.parametrize("B,F,n", [(16, 2, 4), (16, 3, 3), (16, 8, 3), (32, 16, 2), (24, 4, 4), (8, 4, 4),
+                                   (8, 8, 2)])
 def test_traverse_shapes(B, F, n):
     """Traversal pairs, node tests and survivors of every level for merge
     factors 2..16 and bundles on both sides of 16 rays (the level-1 count
@@ -250,6 +251,8 @@ def test_closest_hit_matches_oracle(name):
     for a, b in zip(g[1:], o["hits"][1:]):
         assert np.allclose(a, b, rtol=1e-5, atol=0)
     assert int(m.final_tests) == o["trav"]["final_tests"]
+    # how far the tests got: u passed, u and v passed
+    assert (int(m.final_u_pass), int(m.final_uv_pass)) == (o["stages"]["u"], o["stages"]["uv"])
 
 
 @pytest.mark.parametrize("t_min", [-1.0, -1e-3, 0.0])
@@ -286,17 +289,22 @@ def test_pipeline_end_to_end(name):
     for lv, (t, n) in o["trav"]["pairs"].items():
         assert _same(g["pairs"][lv][0], t) and _same(g["pairs"][lv][1], n)
     assert g["final_tests"] == o["trav"]["final_tests"]
+    assert (int(g["meta"].final_u_pass), int(g["meta"].final_uv_pass)) == (o["stages"]["u"], o["stages"]["uv"])
     assert np.array_equal(g["hit"][0], o["hits"][0])
     for a, b in zip(g["hit"][1:], o["hits"][1:]):
         assert np.allclose(a, b, rtol=1e-5, atol=0)
 
 
-def test_unsorted_comparison_mode_bit_exact():
+@pytest.mark.parametrize("name,shape,levels", [("mixed_128x72", {}, 16), ("mixed_128x72", {}, None),
+                                               ("refl_96", dict(B=8, F=8, n=2), None)])
+def test_unsorted_comparison_mode_bit_exact(name, shape, levels):
     """The comparison configuration (keys of type and light only, one
-    always-passing mesh, hierarchy to a single top node): every product."""
+    always-passing mesh): every product -- built to a single top node, at
+    the workload's own shape, and at the paper's evaluation setting
+    (hierarchy depth 2, node subdivision 8, Sec. 4.1)."""
     from workloads import unsorted_variant
-    base, kw = small("mixed_128x72")
-    wl = unsorted_variant(workload(base, **kw))
+    base, kw = small(name)
+    wl = unsorted_variant(workload(base, **kw, **shape), levels=levels)
     o = O.run_pipeline(wl)
     print(f"[unsorted] {o['hash']['n']} rays, {o['tree']['n_levels']} levels", flush=True)
     g = _gu().run_pipeline(wl, pair_capacity=1 << 20)
@@ -361,6 +369,8 @@ def _check_fused(g, o):
     order (level-1 tests and pairs formed, ray-triangle tests)."""
     tr = o["trav"]
     assert g["final_tests"] == tr["final_tests"]
+    if "stages" in o:
+        assert (int(g["meta"].final_u_pass), int(g["meta"].final_uv_pass)) == (o["stages"]["u"], o["stages"]["uv"])
     nl = o["tree"]["n_levels"]
     for lv in range(1, nl + 1):
         assert g["tests"][lv] == tr["tests"][lv], lv

@@ -217,3 +217,39 @@ def test_adjoint64_matches_finite_differences(rng):
     dv0, dv1, dv2, do, dd, _ = O.adjoint64([0.25, 0.5, 1.0], [0, 0, -1.0], [0, 0, 0, 1, 0, 0, 0, 1, 0], [1, 0, 0])
     assert np.allclose(do, [0, 0, 1]) and np.allclose(dd, [0, 0, 1])
     assert np.allclose([dv0[2], dv1[2], dv2[2]], [-0.25, -0.25, -0.5])
+
+
+def test_stage_counts_follow_the_test_order():
+    """How far each final test got (Sec. 3.3.8): one triangle (0,0,0),
+    (1,0,0), (0,1,0) in the z = 0 plane, rays straight down from z = 1 in one
+    leaf: a ray parallel to the plane (determinant check fails), one with
+    u < 0, one with u in range but u + v > 1, one inside but beyond tmax,
+    and two hits.  u passes: 4; u and v pass: 3; closest hits: 2."""
+    tri = np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32)
+    sc = Scene(tris=tri, mesh_first=np.array([0], np.uint32), mesh_count=np.array([1], np.uint32),
+               mesh_sphere=np.array([[0.5, 0.5, 0.0, 2.0]], np.float32),
+               mesh_mat=np.zeros(1, np.int32), mat_flags=np.zeros(1, np.uint32),
+               mat_ior=np.ones(1, np.float32))
+    #           parallel  u<0   u+v>1  tmax   hit    hit
+    ox = np.array([0.2, -0.3, 0.6, 0.2, 0.2, 0.1], np.float32)
+    oy = np.array([0.2, 0.2, 0.6, 0.2, 0.3, 0.1], np.float32)
+    dz = np.array([0.0, -1, -1, -1, -1, -1], np.float32)
+    dx = np.array([1.0, 0, 0, 0, 0, 0], np.float32)
+    rays = {"ox": ox, "oy": oy, "oz": np.ones(6, np.float32), "dx": dx, "dy": np.zeros(6, np.float32),
+            "dz": dz, "tmax": np.array([9, 9, 9, 0.5, 9, 9], np.float32), "pix": np.zeros(6, np.uint32)}
+    ids = np.arange(6, dtype=np.uint32)
+    st = {}
+    hits = O.closest_hit(rays, ids, 8, (np.zeros(1, np.uint32), np.zeros(1, np.uint32)), sc, 1e-4, stages=st)
+    assert (st["u"], st["uv"]) == (4, 3)
+    assert list(hits[0]) == [-1, -1, -1, -1, 0, 0]
+    # on a workload: final tests >= u passes >= u-and-v passes >= hit rays,
+    # and the counts add up over calls
+    base, kw = small("refl_96")
+    o = oracle_run(base, **kw)
+    assert o["trav"]["final_tests"] >= o["stages"]["u"] >= o["stages"]["uv"] >= int((o["hits"][0] >= 0).sum())
+    st2 = {}
+    O.closest_hit(o["hash"]["rays"], o["sorted_ids"], workload(base, **kw).B, o["trav"]["pairs"][1],
+                  workload(base, **kw).scene, workload(base, **kw).t_min, stages=st2)
+    O.closest_hit(o["hash"]["rays"], o["sorted_ids"], workload(base, **kw).B, o["trav"]["pairs"][1],
+                  workload(base, **kw).scene, workload(base, **kw).t_min, stages=st2)
+    assert st2 == {"u": 2 * o["stages"]["u"], "uv": 2 * o["stages"]["uv"]}

@@ -301,17 +301,19 @@ def _finish(name, seed, sc, W, H, eye, look, vfov, lights, B, F, n, types):
                     lo=lo, inv_ext=inv)
 
 
-def unsorted_variant(wl, levels=16):
+def unsorted_variant(wl, levels=None):
     """The comparison configuration of the same inputs: the ray-space
     hierarchy without ray sorting and without whole-mesh culling (Sec. 2) --
     keys of ray type and light only, every triangle in one mesh whose sphere
-    always passes, and the hierarchy built to its single top node (up to
-    `levels` levels)."""
+    always passes -- with the same hierarchy shape (B, F and the level count,
+    as the paper compares both hierarchies at one depth, Sec. 4.1), or
+    `levels` levels when given."""
     sc = wl.scene
     one = Scene(tris=sc.tris, mesh_first=np.zeros(1, np.uint32), mesh_count=np.array([sc.m], np.uint32),
                 mesh_sphere=np.array([[0.0, 0.0, 0.0, 1e30]], np.float32), mesh_mat=np.zeros(1, np.int32),
                 mat_flags=sc.mat_flags, mat_ior=sc.mat_ior, verts=sc.verts, faces=sc.faces)
-    return replace(wl, name=wl.name + "_unsorted", scene=one, ray_types=wl.ray_types | KEY_TYPE_ONLY, n=levels)
+    return replace(wl, name=wl.name + "_unsorted", scene=one, ray_types=wl.ray_types | KEY_TYPE_ONLY,
+                   n=wl.n if levels is None else levels)
 
 
 MAKERS = {"shadow_128": make_shadow_128, "refl_1024": make_refl_1024, "mixed_1080p": make_mixed_1080p, "adjoint_512": make_adjoint_512}
