@@ -129,6 +129,12 @@ def _cpu_subtrees(top_nodes):
     return time.perf_counter() - t0
 
 
+def host_cores(max_cores=16):
+    """Host threads for process pools: the affinity mask, at most the share
+    of the host that one GPU gets."""
+    return max(1, min(len(os.sched_getaffinity(0)), max_cores))
+
+
 def cpu_baseline(wl, n_sample_top=64, n_sample_one=4, max_cores=16):
     """The oracle as it stands (sequential C, never tuned) on the host's
     cores.  Hash, sort and build run over the whole frame in one process.
@@ -161,7 +167,7 @@ def cpu_baseline(wl, n_sample_top=64, n_sample_one=4, max_cores=16):
     span = wl.B * wl.F ** (nl - 1)
     rays_under = lambda sub: int(sum(min(span, h["n"] - int(i) * span) for i in sub))
     hsb = t["hash"] + t["sort"] + t["build"]
-    cores = max(1, min(len(os.sched_getaffinity(0)), max_cores))
+    cores = host_cores(max_cores)
     sub = [int(i) for i in np.unique(np.linspace(0, ntop - 1, min(n_sample_top, ntop)).astype(np.int64))]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
@@ -232,6 +238,10 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="batch_64: JSON cache of tuned points")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched form's figures (64 frames as one captured batch against the same frames "
+                         "through the plain calls) that follow the measurement of the frame (taken only with the "
+                         "workload's own shape and the crsh variant)")
     ap.add_argument("--cpu-sample-top", type=int, default=128,
                     help="top-level sub-trees the oracle traverses in the process pool")
     ap.add_argument("--cpu-sample-one", type=int, default=4,
@@ -272,6 +282,16 @@ def main():
         cpu = cpu_baseline(wl, args.cpu_sample_top, args.cpu_sample_one)
         print(f"[bench] oracle baseline in {time.perf_counter() - t0:.1f}s: {cpu['value']:.0f} rays/s on "
               f"{cpu['cores']} cores", file=sys.stderr, flush=True)
+
+    # the batched form's frames, built in a process pool, also before the GPU
+    wls = None
+    reshaped = args.size or args.variant != "crsh" or any(v is not None for v in (args.bundle, args.merge, args.levels))
+    if not args.no_batch and not reshaped:
+        from workloads.scenes import make_batch
+        t0 = time.perf_counter()
+        wls = make_batch(args.seed, args.frames, jobs=host_cores())
+        print(f"[bench] batch of {len(wls)} frames built in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+              flush=True)
 
     import torch
     from paper_2312_06538_amd import crsh as X
@@ -380,8 +400,19 @@ def main():
         out["copy_probe_bytes"] = 4 * n4
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    rc = 0
+    if wls is not None:
+        # the batched form, after the headline frame's buffers are released
+        del bf, fr
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        bt = measure_batch(args, wls)
+        out["batch_64"] = {"value": bt["value"], "unit": bt["unit"], "ms_per_batch": bt["ms_per_step"],
+                           "per_frame_plain": bt["per_frame_plain"], "config": bt["config"], "tests": bt["tests"]}
+        if not bt["per_frame_plain"]["same_closest_hits"]:
+            rc = 1
     print(json.dumps(out), flush=True)
-    return 0
+    return rc
 
 
 def bench_sort_sweep(args):
@@ -443,10 +474,12 @@ def bench_sort_sweep(args):
     return 0
 
 
-def bench_batch(args):
+def measure_batch(args, wls=None):
     """Batched form: `frames` independent frames (log-uniform sizes) as one
     captured batch, against the same frames one after the other through the
-    plain calls with the same hierarchy shape."""
+    plain calls with the same hierarchy shape.  Returns the JSON record; its
+    `per_frame_plain.same_closest_hits` says whether the two forms found the
+    same closest hits (bits of t, u, v included)."""
     import dataclasses
 
     import torch
@@ -457,9 +490,10 @@ def bench_batch(args):
     from paper_2312_06538_amd.batch import DeviceBatch
 
     log = lambda msg: print(msg, file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    wls = make_batch(args.seed, args.frames)
-    log(f"[bench] batch of {len(wls)} frames built in {time.perf_counter() - t0:.1f}s")
+    if wls is None:
+        t0 = time.perf_counter()
+        wls = make_batch(args.seed, args.frames, jobs=host_cores())
+        log(f"[bench] batch of {len(wls)} frames built in {time.perf_counter() - t0:.1f}s")
     stream = torch.cuda.Stream()
     p = dict(T.START)
     db = DeviceBatch(wls, p["B"], 4, p["levels"], p["hit_block"], pair_capacity=1 << 24)
@@ -520,9 +554,9 @@ def bench_batch(args):
     same = True
     for f, ((fr, bf), r) in enumerate(zip(plain, batch_res)):
         pm, _ = P.read_meta(bf)
-        g = P.results(fr, bf, pm)
-        for a, b in zip(g["hit"], r["hit"]):
-            if not np.array_equal(np.asarray(a).view(np.uint32), np.asarray(b).view(np.uint32)):
+        res = P.results(fr, bf, pm)
+        for x, y in zip(res["hit"], r["hit"]):
+            if not np.array_equal(np.asarray(x).view(np.uint32), np.asarray(y).view(np.uint32)):
                 same = False
                 log(f"[bench] frame {f}: batched and plain closest hits differ")
                 break
@@ -545,8 +579,13 @@ def bench_batch(args):
         "tests": {"final_ray_tri_tests": int(m2.final_tests),
                   "node_tests": sum(int(m2.tests[k]) for k in range(int(m2.n_levels)))},
     }
+    return out
+
+
+def bench_batch(args):
+    out = measure_batch(args)
     print(json.dumps(out), flush=True)
-    return 0 if same else 1
+    return 0 if out["per_frame_plain"]["same_closest_hits"] else 1
 
 
 if __name__ == "__main__":

@@ -2,10 +2,8 @@
 //
 // Every level is produced in three launches with no wait between blocks:
 //   count  each work item (top level: one (top node, mesh) pair per wave;
-//          lower levels: a tile of 256 parent pairs -- in the plain form one
-//          (parent, child) test per lane, in the batched form one parent
-//          pair per thread with every child unrolled, pipelined over the
-//          block's tiles) runs its Eq. 9 tests and records how many pass
+//          lower levels: a tile of 256 parent pairs, one (parent, child)
+//          test per lane) runs its Eq. 9 tests and records how many pass
 //          (lower levels also keep the pass bits, one per child slot,
 //          packed in 32-bit words);
 //   scan   exclusive scan of the counts -> output offset of every item;
@@ -413,7 +411,7 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
     }
 }
 
-// Count pass of the plain form with one (parent pair, child) test per lane.
+// Count pass with one (parent pair, child) test per lane.
 // A tile of LEVEL_TILE parent pairs is tested in NF slices of LEVEL_TILE /
 // NF parents; in a slice the NF lanes of a parent test its NF consecutive
 // children, so a wave's node loads cover 64 / NF runs of NF consecutive
@@ -426,14 +424,19 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_le
 // path, which bounds this pass, then carries per test only the child's
 // 36 bytes (buffer loads on 32-bit offsets) and 3/(64 NF) of a pair read.
 // The next tile's pairs and spheres are requested before a tile is tested
-// (pairs two tiles ahead, since the sphere read depends on them).
-template <int NF, bool PACKED>
+// (pairs two tiles ahead, since the sphere read depends on them).  In the
+// batched form a parent's children are the range the build recorded with it
+// (first, count); the lane that reads a parent's pair reads that record too,
+// in the same stage as the sphere, and puts it in the parent's LDS record,
+// so no lane of the slice repeats the dependent read.
+template <int NF, bool BATCH, bool PACKED>
 __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t parent_level, uint32_t F,
                                                                      const float4 *__restrict__ na,
                                                                      const float4 *__restrict__ nb,
                                                                      const float *__restrict__ ns,
                                                                      const float4 *__restrict__ tsph, uint32_t m,
-                                                                     pair_levels P, trav_scratch S, crsh_meta *meta)
+                                                                     pair_levels P, trav_scratch S, crsh_meta *meta,
+                                                                     batch_dev bd)
 {
     static_assert(LEVEL_PPT == 1 && WAVE % NF == 0, "whole parents per wave");
     constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per slice; NF slices make a tile
@@ -442,7 +445,8 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
     __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
     __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
     __shared__ float4 s_sph[LEVEL_THREADS / WAVE][WAVE];      // [wave][record]
-    __shared__ uint32_t s_par[LEVEL_THREADS / WAVE][WAVE];
+    __shared__ uint32_t s_first[LEVEL_THREADS / WAVE][WAVE];  // first child (level-local)
+    __shared__ uint32_t s_cnt[LEVEL_THREADS / WAVE][WAVE];    // children (0: no parent)
     const uint32_t nl = meta->n_levels;
     if ((uint32_t)parent_level > nl || parent_level < 2) return;
     const uint64_t ntiles = level_items(meta, parent_level, 0, P);
@@ -453,6 +457,8 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
     nin = nin < in.cap ? nin : in.cap;
     const uint32_t nk = meta->level_cnt[parent_level - 2];
     const uint32_t offk = meta->level_off[parent_level - 2];
+    const uint32_t offp = meta->level_off[parent_level - 1];
+    const uint32_t np = meta->level_cnt[parent_level - 1];
     const uint32_t l = lane_id();
     const uint32_t w = threadIdx.x / WAVE;
     const uint32_t j = l % NF;              // child of this lane in every slice
@@ -473,14 +479,28 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
     };
     uint64_t tests = 0;
     uint32_t parity = 0;
-    // two-stage prefetch: the sphere of the next tile and the pair of the
-    // tile after it are in flight while a tile is tested
-    uint32_t par_n = NONE, tri_nn = 0u, par_nn = NONE;
+    // a parent's children: plain, par * F + [0, F); batch, the build's
+    // record (level-local first child, count)
+    auto children = [&](uint32_t par, uint32_t &first, uint32_t &cnt) {
+        if constexpr (BATCH) {
+            const bool ok = par < np;
+            first = ok ? bd.node_first[offp + par] : 0u;
+            cnt = ok ? bd.node_info[offp + par] & INFO_COUNT_MASK : 0u;
+        } else {
+            first = par * F;
+            cnt = par != NONE ? F : 0u;
+        }
+    };
+    // two-stage prefetch: the sphere (and batch: the child range) of the
+    // next tile and the pair of the tile after it are in flight while a
+    // tile is tested
+    uint32_t first_n = 0u, cnt_n = 0u, tri_nn = 0u, par_nn = NONE;
     float4 sp_n = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (blockIdx.x < ntiles) {
-        uint32_t tri0;
-        load_pair(blockIdx.x, tri0, par_n);
+        uint32_t tri0, par0;
+        load_pair(blockIdx.x, tri0, par0);
         sp_n = tsph[tri0 < m ? tri0 : 0u];
+        children(par0, first_n, cnt_n);
         if (blockIdx.x + gridDim.x < ntiles) load_pair(blockIdx.x + gridDim.x, tri_nn, par_nn);
     }
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
@@ -488,18 +508,18 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
         // program order within the wave)
         __builtin_amdgcn_wave_barrier();
         s_sph[w][l] = sp_n;
-        s_par[w][l] = par_n;
+        s_first[w][l] = first_n;
+        s_cnt[w][l] = cnt_n;
         __builtin_amdgcn_wave_barrier();
-        par_n = par_nn;
         sp_n = tsph[tri_nn < m ? tri_nn : 0u];
+        children(par_nn, first_n, cnt_n);
         if (tile + 2 * (uint64_t)gridDim.x < ntiles) load_pair(tile + 2 * (uint64_t)gridDim.x, tri_nn, par_nn);
         uint32_t c = 0;
 #pragma unroll
         for (uint32_t r = 0; r < NF; ++r) {
             const uint32_t rec = r * PW + pi;
-            const uint32_t par = s_par[w][rec];
-            const uint32_t ch = par * F + j;
-            const bool ok = par != NONE && j < F && ch < nk;
+            const uint32_t ch = s_first[w][rec] + j;
+            const bool ok = j < s_cnt[w][rec] && ch < nk;
             const uint32_t g = offk + (ok ? ch : 0u);
             const float4 A = buf_load4(ra, g * 16u);
             const float4 Bv = buf_load4(rb, g * 16u);
@@ -779,24 +799,26 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
     default: CRSH_COUNT(16, BT, PK); break;                                                                  \
     }
     prof_scope ps("k_level", stream);
-#define CRSH_COUNT_LANES_ONE(NF, PK)                                                                         \
+#define CRSH_COUNT_LANES_ONE(NF, BT, PK)                                                                     \
     {                                                                                                        \
-        const uint32_t rb = resident_blocks(k_level_count_lanes<NF, PK>, LEVEL_THREADS);                     \
+        const uint32_t rb = resident_blocks(k_level_count_lanes<NF, BT, PK>, LEVEL_THREADS);                 \
         const uint32_t gl = rb ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), rb) : g;    \
-        k_level_count_lanes<NF, PK><<<gl, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta); \
+        k_level_count_lanes<NF, BT, PK><<<gl, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta, b); \
     }
-#define CRSH_COUNT_LANES_NF(PK)                                                                              \
+#define CRSH_COUNT_LANES_NF(BT, PK)                                                                          \
     switch (nf) {                                                                                            \
-    case 2: CRSH_COUNT_LANES_ONE(2, PK) break;                                                               \
-    case 4: CRSH_COUNT_LANES_ONE(4, PK) break;                                                               \
-    case 8: CRSH_COUNT_LANES_ONE(8, PK) break;                                                               \
-    default: CRSH_COUNT_LANES_ONE(16, PK) break;                                                             \
+    case 2: CRSH_COUNT_LANES_ONE(2, BT, PK) break;                                                           \
+    case 4: CRSH_COUNT_LANES_ONE(4, BT, PK) break;                                                           \
+    case 8: CRSH_COUNT_LANES_ONE(8, BT, PK) break;                                                           \
+    default: CRSH_COUNT_LANES_ONE(16, BT, PK) break;                                                         \
     }
-    if (CRSH_COUNT_LANES && lanes && !bd && LEVEL_PPT == 1) {
-        if (packed) {
-            CRSH_COUNT_LANES_NF(true)
+    if (CRSH_COUNT_LANES && lanes && LEVEL_PPT == 1) {
+        if (bd) {
+            CRSH_COUNT_LANES_NF(true, false)
+        } else if (packed) {
+            CRSH_COUNT_LANES_NF(false, true)
         } else {
-            CRSH_COUNT_LANES_NF(false)
+            CRSH_COUNT_LANES_NF(false, false)
         }
     } else if (bd) {
         CRSH_COUNT_NF(true, false)

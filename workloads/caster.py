@@ -16,6 +16,18 @@ import numpy as np
 NEAR = 1e-4
 
 
+def _cross(a, b):
+    """Row-wise cross product of two [N,3] float64 arrays (the same products
+    and differences as np.cross, without its copies)."""
+    a0, a1, a2 = a[:, 0], a[:, 1], a[:, 2]
+    b0, b1, b2 = b[:, 0], b[:, 1], b[:, 2]
+    c = np.empty(a.shape, dtype=np.float64)
+    c[:, 0] = a1 * b2 - a2 * b1
+    c[:, 1] = a2 * b0 - a0 * b2
+    c[:, 2] = a0 * b1 - a1 * b0
+    return c
+
+
 def camera_basis(eye, look, up=(0.0, 1.0, 0.0)):
     eye = np.asarray(eye, dtype=np.float64)
     f = np.asarray(look, dtype=np.float64) - eye
@@ -105,7 +117,7 @@ def cast_primary(tris32, tri_mat, W, H, eye, look, vfov_deg, chunk=4_000_000):
     best_tri = np.full(W * H, -1, dtype=np.int64)
     e1 = tris[:, 1] - tris[:, 0]
     e2 = tris[:, 2] - tris[:, 0]
-    nrm = np.cross(e1, e2)
+    nrm = _cross(e1, e2)
     start = 0
     csum = np.cumsum(area)
     while start < len(ids):
@@ -132,7 +144,7 @@ def cast_primary(tris32, tri_mat, W, H, eye, look, vfov_deg, chunk=4_000_000):
         for k in range(3):
             va = tris[tt, k]
             vb = tris[tt, (k + 1) % 3]
-            side = np.einsum("ij,ij->i", np.cross(vb - va, h - va), n)
+            side = np.einsum("ij,ij->i", _cross(vb - va, h - va), n)
             ok &= side >= 0
         pix, t, tt = pix[ok], t[ok], tt[ok]
         order = np.lexsort((tt, t, pix))

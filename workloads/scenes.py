@@ -281,15 +281,44 @@ def make_frame(seed, target_rays, target_tris, B=16, F=4, n=5):
     return _finish("frame", seed, sc, Wd, Wd, eye, look, 45.0, lights, B, F, n, SHADOW | REFLECT)
 
 
-def make_batch(seed=0, frames=64):
+def _batch_frame(job):
+    fseed, tr, tt, path = job
+    import os
+    if path and os.path.exists(path):
+        return _load(path)
+    wl = make_frame(fseed, tr, tt)
+    if path:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        _save(wl, path)
+    return wl
+
+
+def make_batch(seed=0, frames=64, cache_dir=None, jobs=1):
     """Frame list of the batched workload: rays per frame log-uniform in
-    [4096, 1M], triangles per frame log-uniform in [1000, 200000]."""
+    [4096, 1M], triangles per frame log-uniform in [1000, 200000].  With
+    `cache_dir` (or CRSH_WORKLOAD_CACHE) every frame is kept there as an
+    .npz and reloaded by later calls; `jobs` > 1 builds the frames in a
+    forked process pool (call it before the process uses the GPU)."""
+    import os
+    cache_dir = cache_dir or os.environ.get("CRSH_WORKLOAD_CACHE")
     rng = np.random.default_rng(seed)
-    out = []
+    work = []
     for i in range(frames):
         tr = float(np.exp(rng.uniform(np.log(4096), np.log(1 << 20))))
         tt = float(np.exp(rng.uniform(np.log(1000), np.log(200000))))
-        out.append(make_frame(seed * 1000 + i + 1, tr, tt))
+        fseed = seed * 1000 + i + 1
+        path = os.path.join(cache_dir, f"frame_seed{fseed}_{tr:.6g}_{tt:.6g}.npz") if cache_dir else None
+        work.append((fseed, tr, tt, path))
+    if jobs <= 1 or frames <= 1:
+        return [_batch_frame(w) for w in work]
+    import multiprocessing as mp
+    # largest frames first, so that the pool's tail is short
+    order = sorted(range(frames), key=lambda k: -work[k][1] * work[k][2])
+    with mp.get_context("fork").Pool(min(jobs, frames)) as pool:
+        built = pool.map(_batch_frame, [work[k] for k in order], chunksize=1)
+    out = [None] * frames
+    for k, wl in zip(order, built):
+        out[k] = wl
     return out
 
 
