@@ -118,5 +118,19 @@ __device__ __forceinline__ bool packed_meets(float4 A, float4 Bv, float sec, f3 
     return lhs2 <= rhs * rhs;
 }
 
+// packed_meets with every operation performed and the outcome selected at
+// the end: the same values and the same decision, with no branch for the
+// compiler to sink a caller's loads of A, Bv and sec into.
+__device__ __forceinline__ bool packed_meets_flat(float4 A, float4 Bv, float sec, f3 P, float d)
+{
+    const f3 v = P - mk(A.x, A.y, A.z);
+    const f3 a = mk(Bv.x, Bv.y, Bv.z);
+    const float t = dot(v, a);
+    const f3 w = cross(v, a);
+    const float lhs2 = dot(w, w);
+    const float rhs = fabsf(t) * Bv.w + (d + A.w) * sec;
+    return !(sec > 0.0f) | (lhs2 <= rhs * rhs);
+}
+
 
 }  // namespace crsh

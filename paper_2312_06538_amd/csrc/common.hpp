@@ -213,13 +213,10 @@ constexpr uint32_t SORT_PASSES = 4;       // 8-bit digits of a 32-bit key
 constexpr uint32_t HASH_BLOCK = 256;      // pixels per hash block
 constexpr uint64_t HASH_STATIC_MAX_PIXELS = CRSH_HASH_STATIC_MAX_PIXELS;  // crsh_hash_static
 constexpr uint32_t LEVEL_THREADS = 256;   // threads of a traversal tile
-#ifndef CRSH_LEVEL_PPT
-#define CRSH_LEVEL_PPT 1
-#endif
 #ifndef CRSH_EMIT_PPT
 #define CRSH_EMIT_PPT 2
 #endif
-constexpr uint32_t LEVEL_PPT = CRSH_LEVEL_PPT;   // parent pairs per thread of the count pass
+constexpr uint32_t LEVEL_PPT = 1;   // parent pairs per thread of the count pass
 constexpr uint32_t LEVEL_TILE = LEVEL_THREADS * LEVEL_PPT;   // parent pairs per count tile
 constexpr uint32_t EMIT_PPT = CRSH_EMIT_PPT;     // parent pairs per thread of the emit pass
 constexpr uint32_t EMIT_TILE = LEVEL_THREADS * EMIT_PPT;     // parent pairs per emit tile
@@ -235,12 +232,13 @@ size_t sort_ws_bytes(uint32_t cap);
 size_t hash_ws_bytes(uint64_t pixels);
 size_t trav_ws_bytes(uint32_t m, uint32_t node_cap, uint64_t top_items, uint64_t max_pairs);
 // Final-test workspace: packed triangles (48 B each), then per ray slot the
-// packed ray (32 B) and a closest-hit key (8 B).  Slots: one per sorted ray in
+// packed ray (32 B: origin and direction in two arrays of 16 B per slot) and
+// a closest-hit key (8 B).  Slots: one per sorted ray in
 // the plain form; in the batched form B per level-1 node, at most the rays
 // plus B - 1 per frame.
 size_t hit_ws_bytes(uint32_t m, uint32_t slots);
-// bounds of the final tests' 32-bit byte offsets (32 B per ray slot, 48 B
-// per triangle)
+// bounds of the final tests' 32-bit byte offsets (16 B per ray slot in each
+// of two arrays, 48 B per triangle)
 #define CRSH_HIT_MAX_SLOTS (1u << 27)
 #define CRSH_HIT_MAX_TRIS (1u << 26)
 constexpr uint32_t hit_slots(uint32_t rays, bool batch)
@@ -248,19 +246,21 @@ constexpr uint32_t hit_slots(uint32_t rays, bool batch)
     return batch ? rays + CRSH_MAX_FRAMES * (CRSH_MAX_BUNDLE - 1) : rays;
 }
 struct hit_slots_ws {
-    float4 *rays4;               // 2 x float4 per slot
+    float4 *org;                 // per slot: origin, tmax
+    float4 *dir;                 // per slot: direction, t_min
     unsigned long long *keys;    // per slot (batched form)
     uint32_t slots;
 };
 inline hit_slots_ws carve_hit_slots(void *at, uint32_t slots)
 {
     hit_slots_ws h;
-    h.rays4 = (float4 *)at;
-    h.keys = (unsigned long long *)((char *)at + align256((size_t)slots * 32));
+    h.org = (float4 *)at;
+    h.dir = (float4 *)((char *)at + align256((size_t)slots * 16));
+    h.keys = (unsigned long long *)((char *)h.dir + align256((size_t)slots * 16));
     h.slots = slots;
     return h;
 }
-inline size_t hit_slots_bytes(uint32_t slots) { return align256((size_t)slots * 32) + align256((size_t)slots * 8); }
+inline size_t hit_slots_bytes(uint32_t slots) { return 2 * align256((size_t)slots * 16) + align256((size_t)slots * 8); }
 
 // Stage launchers shared by the plain entry points (bd == nullptr) and the
 // batched form (bd: the batch's device view, frame-aware kernels).

@@ -57,15 +57,18 @@ __device__ __forceinline__ uint32_t batch_slots(const crsh_meta *meta, uint32_t 
     return (uint32_t)(ns < slot_cap ? ns : slot_cap);
 }
 
-// Plain form: sorted rays repacked as 2 x float4 (origin, tmax), (direction,
-// t_min): two 16-byte loads per test instead of seven scattered ones.
-__global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, float t_min, float4 *rays)
+// Plain form: sorted rays repacked as (origin, tmax) and (direction, t_min),
+// one float4 array each: two 16-byte loads per test instead of seven
+// scattered ones, and the 16 rays of a leaf are 256 contiguous bytes in
+// either array.
+__global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, float t_min, float4 *org,
+                           float4 *dir)
 {
     const uint32_t n = min(meta->n_rays, cap);
     const float tm = slot_tmin(t_min);
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
-        rays[2 * s] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
-        rays[2 * s + 1] = make_float4(R.dx[s], R.dy[s], R.dz[s], tm);
+        org[s] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
+        dir[s] = make_float4(R.dx[s], R.dy[s], R.dz[s], tm);
     }
 }
 
@@ -73,7 +76,8 @@ __global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, f
 // (first ray and count as the build recorded them) with its frame's t_min,
 // or the padding marker; every slot's closest-hit key starts at all ones.
 __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t ray_cap, uint32_t B,
-                                 uint32_t slot_cap, batch_dev bd, float4 *rays, unsigned long long *keys)
+                                 uint32_t slot_cap, batch_dev bd, float4 *org, float4 *dir,
+                                 unsigned long long *keys)
 {
     const uint32_t n = min(meta->n_rays, ray_cap);
     const uint32_t ns = batch_slots(meta, B, slot_cap);
@@ -84,11 +88,11 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
         const uint32_t f = info >> INFO_FRAME_SHIFT;
         const uint32_t s = bd.node_first[leaf] + j;
         if (j < (info & INFO_COUNT_MASK) && s < n && f < bd.n_frames) {
-            rays[2 * p] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
-            rays[2 * p + 1] = make_float4(R.dx[s], R.dy[s], R.dz[s], slot_tmin(bd.frames[f].t_min));
+            org[p] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
+            dir[p] = make_float4(R.dx[s], R.dy[s], R.dz[s], slot_tmin(bd.frames[f].t_min));
         } else {
-            rays[2 * p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            rays[2 * p + 1] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(PAD_SLOT));
+            org[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            dir[p] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(PAD_SLOT));
         }
         keys[p] = ~0ull;
     }
@@ -108,12 +112,15 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
 // lane group reading its pair's record from LDS (the 16 lanes of a group
 // read the same address), so the vector memory path carries only the rays.
 // Rays are read with buffer loads on 32-bit byte offsets (the host bounds
-// them; a read past the end returns zeros).  The test is split where most
+// them; a read past the end returns zeros), origins and directions from
+// their own arrays, so each of the two loads of a step covers 256
+// contiguous bytes per pair.  The test is split where most
 // of its cost lies: every lane computes the division-free first half, and
 // the wave runs the rest (the division included) only when one of its
 // lanes can still pass.
 template <bool BATCH, bool PACKED>
-__global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const float4 *__restrict__ tri,
+__global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, const float4 *__restrict__ RD,
+                                             const float4 *__restrict__ tri,
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
                                              uint64_t cap1, uint32_t B, uint32_t log2G, unsigned long long *keys,
                                              crsh_meta *meta, uint32_t slot_cap, uint32_t m, uint32_t tri_base)
@@ -131,9 +138,10 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
     const uint32_t wib = threadIdx.x / WAVE;
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
-    const __amdgpu_buffer_rsrc_t rays_r = make_rsrc(R, (uint64_t)ns * 32u);
+    const __amdgpu_buffer_rsrc_t org_r = make_rsrc(RO, (uint64_t)ns * 16u);
+    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * 16u);
     const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
-    const uint32_t jo = j * 32u;
+    const uint32_t jo = j * 16u;
     float4(*rec)[WAVE] = s_rec[wib];
     uint64_t tests = 0, upass = 0, uvpass = 0;   // wave-wide counts
     for (uint64_t c0 = wave * WAVE; c0 < np; c0 += nwaves * WAVE) {
@@ -154,7 +162,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
             const uint64_t first = (uint64_t)leaf * B;
             if (my_t < m && first < ns) {
                 my_cnt = (uint32_t)min((uint64_t)B, ns - first);
-                my_rb = (uint32_t)first * 32u;
+                my_rb = (uint32_t)first * 16u;
             }
         }
         const uint32_t tb = my_cnt ? my_t * 48u : 0u;
@@ -174,8 +182,8 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
             const uint32_t cnt = __float_as_uint(c.w);
             const uint32_t ro = __float_as_uint(c.z) + jo;
             bool ok = j < cnt;
-            const float4 ro4 = buf_load4(rays_r, ro);
-            const float4 rd4 = buf_load4(rays_r, ro + 16u);
+            const float4 ro4 = buf_load4(org_r, ro);
+            const float4 rd4 = buf_load4(dir_r, ro);
             tri_t tr;
             tr.v0 = mk(a.x, a.y, a.z);
             tr.e1 = mk(a.w, b.x, b.y);
@@ -194,7 +202,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ R, const
                 const uint32_t st = maybe ? mt_second_half(D, rd4.w, ro4.w, tr, h, th) : 0u;
                 upass += (uint64_t)__popcll(ballot((st & MT_U) != 0u));
                 uvpass += (uint64_t)__popcll(ballot((st & MT_UV) != 0u));
-                if (st & MT_HIT) atomicMin(&keys[ro >> 5], hit_key(th, __float_as_uint(c.y)));
+                if (st & MT_HIT) atomicMin(&keys[ro >> 4], hit_key(th, __float_as_uint(c.y)));
             }
         }
     }
@@ -303,23 +311,23 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
     sorted_rays S{sorted->ox, sorted->oy, sorted->oz, sorted->dx, sorted->dy, sorted->dz, sorted->tmax};
     if (bd)     // also the start value of every slot key, read by k_hit_final
         k_hit_rays_batch<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, (uint32_t)bundle, hs.slots, *bd,
-                                                hs.rays4, hs.keys);
+                                                hs.org, hs.dir, hs.keys);
     if (!level1->capacity) return;
-    if (!bd) k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, t_min, hs.rays4);
+    if (!bd) k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, t_min, hs.org, hs.dir);
     uint32_t log2G = 0;
     while ((1u << log2G) < (uint32_t)bundle) ++log2G;
     const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
     prof_scope ps("k_hit", stream);
     if (bd)
-        k_hit<true, false><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, level1->node,
+        k_hit<true, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                            level1->capacity, (uint32_t)bundle, log2G, hs.keys, meta,
                                                            hs.slots, scene->m, 0u);
     else if (packed)
-        k_hit<false, true><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, nullptr, level1->capacity,
+        k_hit<false, true><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, nullptr, level1->capacity,
                                                            (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
                                                            scene->m, tri_base);
     else
-        k_hit<false, false><<<grid, hit_block, 0, stream>>>(hs.rays4, tri, level1->tri, level1->node,
+        k_hit<false, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                             level1->capacity, (uint32_t)bundle, log2G, hits->tkey,
                                                             meta, hs.slots, scene->m, 0u);
 }
@@ -373,8 +381,8 @@ crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32
         set_error("%s: hit capacity below the ray capacity", who);
         return CRSH_ERR_INVALID;
     }
-    // the final tests address ray slots (32 B) and triangles (48 B) by
-    // 32-bit byte offsets
+    // the final tests address ray slots (16 B in each of two arrays) and
+    // triangles (48 B) by 32-bit byte offsets
     if ((uint64_t)sorted->capacity + (uint64_t)CRSH_MAX_FRAMES * (CRSH_MAX_BUNDLE - 1) > CRSH_HIT_MAX_SLOTS ||
         scene->m > CRSH_HIT_MAX_TRIS) {
         set_error("%s: at most %u ray slots and %u triangles", who, (unsigned)CRSH_HIT_MAX_SLOTS,

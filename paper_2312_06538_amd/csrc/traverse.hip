@@ -26,12 +26,6 @@
 #include "bounds.hpp"
 #include "traverse.hpp"
 
-#ifndef CRSH_COUNT_LANES
-#define CRSH_COUNT_LANES 1   // plain count passes: one (parent, child) test per lane
-#endif
-#ifndef CRSH_COUNT_LANES_MIN_BUNDLE
-#define CRSH_COUNT_LANES_MIN_BUNDLE 1    // ... for bundles of at least this many rays
-#endif
 
 namespace crsh {
 
@@ -251,166 +245,6 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
 }
 
 // ----------------------------------------------------------- lower levels
-// Children of a parent: plain, par * F + [0, F) below nk; batch, the range
-// (pfirst[par], count) recorded by the build.
-template <int PPT, bool PACKED>
-__device__ __forceinline__ void load_tile_pairs(uint64_t q0, uint64_t nin, const pairs_dev &in, uint32_t *tri,
-                                                uint32_t *par)
-{
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        tri[k] = 0u;
-        par[k] = 0xFFFFFFFFu;
-        if (q0 + k < nin) pair_get<PACKED>(in, q0 + k, tri[k], par[k]);
-    }
-}
-
-// Eq. 9 tests of a thread's PPT parent pairs (tri, par; par = ~0 for none)
-// against their children, in two steps for a pipeline over tiles: the loads
-// of a tile's triangle spheres and child nodes are issued one iteration
-// before the tests that use them (one bit per (pair, child) that passes).
-template <int NF, int PPT>
-struct child_set {
-    float4 sp[PPT];
-    float4 A[PPT][NF], Bv[PPT][NF];
-    float Sg[PPT][NF];
-    uint32_t okm;                          // bit k * NF + j: child j of pair k exists
-};
-
-template <int NF, int PPT, bool BATCH>
-__device__ __forceinline__ void load_children(child_set<NF, PPT> &c, uint32_t F, uint32_t nk, uint32_t offk,
-                                              const float4 *__restrict__ na, const float4 *__restrict__ nb,
-                                              const float *__restrict__ ns, const float4 *__restrict__ tsph,
-                                              uint32_t m, const uint32_t *__restrict__ pfirst,
-                                              const uint32_t *__restrict__ pinfo, uint32_t np, const uint32_t *tri,
-                                              const uint32_t *par)
-{
-    c.okm = 0;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        c.sp[k] = tsph[tri[k] < m ? tri[k] : 0u];
-        uint32_t cfirst, ccount;
-        if constexpr (BATCH) {
-            const bool ok = par[k] < np;
-            cfirst = ok ? pfirst[par[k]] : 0u;
-            ccount = ok ? pinfo[par[k]] & INFO_COUNT_MASK : 0u;
-        } else {
-            cfirst = par[k] * F;
-            ccount = par[k] != 0xFFFFFFFFu ? F : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            const uint32_t ch = cfirst + (uint32_t)j;
-            const bool ok = (uint32_t)j < ccount && ch < nk;
-            if (ok) c.okm |= 1u << (k * NF + j);
-            const uint32_t g = offk + (ok ? ch : 0u);
-            c.A[k][j] = na[g];
-            c.Bv[k][j] = nb[g];
-            c.Sg[k][j] = ns[g];
-        }
-    }
-}
-
-template <int NF, int PPT>
-__device__ __forceinline__ uint32_t test_children(const child_set<NF, PPT> &c, uint64_t &tests)
-{
-    uint32_t mask = 0;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const f3 Pc = mk(c.sp[k].x, c.sp[k].y, c.sp[k].z);
-#pragma unroll
-        for (int j = 0; j < NF; ++j) {
-            if (!((c.okm >> (k * NF + j)) & 1u)) continue;
-            ++tests;
-            if (packed_meets(c.A[k][j], c.Bv[k][j], c.Sg[k][j], Pc, c.sp[k].w)) mask |= 1u << (k * NF + j);
-        }
-    }
-    return mask;
-}
-
-template <int NF, int PPT, bool BATCH, bool PACKED = false>
-__global__ __launch_bounds__(LEVEL_THREADS) void k_level_count(int32_t parent_level, uint32_t F,
-                                                               const float4 *__restrict__ na,
-                                                               const float4 *__restrict__ nb,
-                                                               const float *__restrict__ ns,
-                                                               const float4 *__restrict__ tsph, uint32_t m,
-                                                               pair_levels P, trav_scratch S, crsh_meta *meta,
-                                                               batch_dev bd)
-{
-    static_assert(NF * PPT <= 32, "one bit per child test");
-    static_assert(LEVEL_THREADS * PPT == LEVEL_TILE, "tile size");
-    __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
-    __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
-    const uint32_t nl = meta->n_levels;
-    if ((uint32_t)parent_level > nl) return;
-    const uint64_t ntiles = level_items(meta, parent_level, 0, P);
-    clear_scan(S, ntiles);                  // the scan that follows reads these
-    const pairs_dev in = P.p[parent_level - 1];
-    if (in.tri == nullptr || P.p[parent_level - 2].tri == nullptr) return;
-    uint64_t nin = meta->pairs[parent_level - 1];
-    nin = nin < in.cap ? nin : in.cap;
-    const uint32_t nk = meta->level_cnt[parent_level - 2];
-    const uint32_t offk = meta->level_off[parent_level - 2];
-    const uint32_t offp = meta->level_off[parent_level - 1];
-    const uint32_t np = meta->level_cnt[parent_level - 1];
-    const uint32_t *pfirst = BATCH ? bd.node_first + offp : nullptr;
-    const uint32_t *pinfo = BATCH ? bd.node_info + offp : nullptr;
-    uint64_t tests = 0;
-    // two-stage pipeline: tile i is tested with the child nodes loaded
-    // during tile i - 1, while tile i + 1's children and tile i + 2's parent
-    // pairs are requested
-    uint32_t tri_n[PPT], par_n[PPT];
-    child_set<NF, PPT> cs;
-    const uint64_t stride = gridDim.x;
-    if (blockIdx.x < ntiles) {
-        uint32_t tri0[PPT], par0[PPT];
-        load_tile_pairs<PPT, PACKED>((uint64_t)blockIdx.x * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri0, par0);
-        load_children<NF, PPT, BATCH>(cs, F, nk, offk, na, nb, ns, tsph, m, pfirst, pinfo, np, tri0, par0);
-        if (blockIdx.x + stride < ntiles)
-            load_tile_pairs<PPT, PACKED>((blockIdx.x + stride) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in, tri_n,
-                                 par_n);
-    }
-    uint32_t parity = 0;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
-        const child_set<NF, PPT> cur = cs;
-        if (tile + stride < ntiles) {
-            load_children<NF, PPT, BATCH>(cs, F, nk, offk, na, nb, ns, tsph, m, pfirst, pinfo, np, tri_n, par_n);
-            if (tile + 2 * stride < ntiles)
-                load_tile_pairs<PPT, PACKED>((tile + 2 * stride) * LEVEL_TILE + (uint64_t)threadIdx.x * PPT, nin, in,
-                                     tri_n, par_n);
-        }
-        const uint32_t mask = test_children<NF, PPT>(cur, tests);
-        // pass masks packed at NF bits per parent pair: the G threads of a
-        // 32-bit word combine their bits (groups are aligned in the wave)
-        {
-            constexpr uint32_t G = 32 / (PPT * NF);
-            uint32_t word = mask << ((threadIdx.x % G) * PPT * NF);
-#pragma unroll
-            for (uint32_t o = 1; o < G; o <<= 1) word |= __shfl_xor(word, o, WAVE);
-            if (threadIdx.x % G == 0) S.mask[(tile * LEVEL_THREADS + threadIdx.x) / G] = word;
-        }
-        // survivors of the tile: wave sums in alternating LDS slots, so one
-        // barrier per tile suffices (a slot is reused two tiles later, after
-        // the next tile's barrier)
-        const uint32_t c = wave_sum((uint32_t)__popc(mask));
-        if (lane_id() == 0) s_red32[parity][threadIdx.x / WAVE] = c;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < LEVEL_THREADS / WAVE; ++w) t += s_red32[parity][w];
-            S.cnt[tile] = t;
-        }
-    }
-    tests = wave_sum(tests);
-    if (lane_id() == 0) s_red[threadIdx.x / WAVE] = tests;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t tt = 0;
-        for (int w = 0; w < LEVEL_THREADS / WAVE; ++w) tt += s_red[w];
-        if (tt) atomicAdd((unsigned long long *)&meta->tests[parent_level - 2], (unsigned long long)tt);
-    }
-}
-
 // Count pass with one (parent pair, child) test per lane.
 // A tile of LEVEL_TILE parent pairs is tested in NF slices of LEVEL_TILE /
 // NF parents; in a slice the NF lanes of a parent test its NF consecutive
@@ -515,27 +349,37 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
         children(par_nn, first_n, cnt_n);
         if (tile + 2 * (uint64_t)gridDim.x < ntiles) load_pair(tile + 2 * (uint64_t)gridDim.x, tri_nn, par_nn);
         uint32_t c = 0;
+        // slices in groups of K: every node load of a group is issued before
+        // its first test, and the test has no branch to sink them into
+        constexpr uint32_t K = NF < 4 ? NF : 4;
 #pragma unroll
-        for (uint32_t r = 0; r < NF; ++r) {
-            const uint32_t rec = r * PW + pi;
-            const uint32_t ch = s_first[w][rec] + j;
-            const bool ok = j < s_cnt[w][rec] && ch < nk;
-            const uint32_t g = offk + (ok ? ch : 0u);
-            const float4 A = buf_load4(ra, g * 16u);
-            const float4 Bv = buf_load4(rb, g * 16u);
-            const float Sg = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
-            const float4 sp = s_sph[w][rec];
-            bool pass = false;
-            if (ok) {
-                ++tests;
-                pass = packed_meets(A, Bv, Sg, mk(sp.x, sp.y, sp.z), sp.w);
+        for (uint32_t r0 = 0; r0 < NF; r0 += K) {
+            float4 A[K], Bv[K];
+            float Sg[K];
+            bool ok[K];
+#pragma unroll
+            for (uint32_t k = 0; k < K; ++k) {
+                const uint32_t rec = (r0 + k) * PW + pi;
+                const uint32_t ch = s_first[w][rec] + j;
+                ok[k] = j < s_cnt[w][rec] && ch < nk;
+                const uint32_t g = offk + (ok[k] ? ch : 0u);
+                A[k] = buf_load4(ra, g * 16u);
+                Bv[k] = buf_load4(rb, g * 16u);
+                Sg[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
             }
-            const uint64_t bal = ballot(pass);
-            if (l == 0) {
-                const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + w * PW) * NF;   // a multiple of 64
-                *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal, (uint32_t)(bal >> 32));
+#pragma unroll
+            for (uint32_t k = 0; k < K; ++k) {
+                const uint32_t r = r0 + k;
+                const float4 sp = s_sph[w][r * PW + pi];
+                const bool meets = packed_meets_flat(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w);
+                tests += ok[k] ? 1u : 0u;
+                const uint64_t bal = ballot(ok[k] & meets);
+                if (l == 0) {
+                    const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + w * PW) * NF;   // a multiple of 64
+                    *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal, (uint32_t)(bal >> 32));
+                }
+                c += (uint32_t)__popcll(bal);
             }
-            c += (uint32_t)__popcll(bal);
         }
         // survivors of the tile: wave sums in alternating LDS slots (one
         // barrier per tile)
@@ -781,56 +625,39 @@ static uint32_t resident_blocks(K kernel, uint32_t threads)
 
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
-                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed, bool lanes)
+                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed)
 {
     const batch_dev b = bd ? *bd : batch_dev{};
-    const uint32_t g = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), 4096);
     const uint32_t Fu = (uint32_t)merge;
     const int L = parent_level;
     int nf = 2;
     while (nf < merge) nf *= 2;
-#define CRSH_COUNT(NF, BT, PK)                                                                               \
-    k_level_count<NF, LEVEL_PPT, BT, PK><<<g, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta, b)
-#define CRSH_COUNT_NF(BT, PK)                                                                                \
-    switch (nf) {                                                                                            \
-    case 2: CRSH_COUNT(2, BT, PK); break;                                                                    \
-    case 4: CRSH_COUNT(4, BT, PK); break;                                                                    \
-    case 8: CRSH_COUNT(8, BT, PK); break;                                                                    \
-    default: CRSH_COUNT(16, BT, PK); break;                                                                  \
-    }
     prof_scope ps("k_level", stream);
-#define CRSH_COUNT_LANES_ONE(NF, BT, PK)                                                                     \
+    // a persistent grid of whole rounds of resident blocks (at most one
+    // block per tile)
+#define CRSH_COUNT_ONE(NF, BT, PK)                                                                           \
     {                                                                                                        \
         const uint32_t rb = resident_blocks(k_level_count_lanes<NF, BT, PK>, LEVEL_THREADS);                 \
-        const uint32_t gl = rb ? (uint32_t)std::min<uint64_t>(std::max<uint64_t>(tiles_cap, 1), rb) : g;    \
+        const uint64_t want = std::max<uint64_t>(tiles_cap, 1);                                              \
+        const uint32_t gl = (uint32_t)std::min<uint64_t>(want, rb ? rb : 4096);                              \
         k_level_count_lanes<NF, BT, PK><<<gl, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta, b); \
     }
-#define CRSH_COUNT_LANES_NF(BT, PK)                                                                          \
+#define CRSH_COUNT_NF(BT, PK)                                                                                \
     switch (nf) {                                                                                            \
-    case 2: CRSH_COUNT_LANES_ONE(2, BT, PK) break;                                                           \
-    case 4: CRSH_COUNT_LANES_ONE(4, BT, PK) break;                                                           \
-    case 8: CRSH_COUNT_LANES_ONE(8, BT, PK) break;                                                           \
-    default: CRSH_COUNT_LANES_ONE(16, BT, PK) break;                                                         \
+    case 2: CRSH_COUNT_ONE(2, BT, PK) break;                                                                 \
+    case 4: CRSH_COUNT_ONE(4, BT, PK) break;                                                                 \
+    case 8: CRSH_COUNT_ONE(8, BT, PK) break;                                                                 \
+    default: CRSH_COUNT_ONE(16, BT, PK) break;                                                               \
     }
-    if (CRSH_COUNT_LANES && lanes && LEVEL_PPT == 1) {
-        if (bd) {
-            CRSH_COUNT_LANES_NF(true, false)
-        } else if (packed) {
-            CRSH_COUNT_LANES_NF(false, true)
-        } else {
-            CRSH_COUNT_LANES_NF(false, false)
-        }
-    } else if (bd) {
+    if (bd) {
         CRSH_COUNT_NF(true, false)
     } else if (packed) {
         CRSH_COUNT_NF(false, true)
     } else {
         CRSH_COUNT_NF(false, false)
     }
-#undef CRSH_COUNT_LANES_NF
-#undef CRSH_COUNT_LANES_ONE
 #undef CRSH_COUNT_NF
-#undef CRSH_COUNT
+#undef CRSH_COUNT_ONE
 }
 
 void tri_spheres_launch(const crsh_scene *scene, uint32_t b, uint32_t e, float4 *out, hipStream_t stream)
@@ -979,8 +806,7 @@ static crsh_status traverse_run(const crsh_nodes *nodes, const crsh_scene *scene
     case 8: CRSH_EMIT(8, BT, PK); break;                                                                   \
     default: CRSH_EMIT(16, BT, PK); break;                                                                 \
     }
-        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream, packed,
-                           bundle >= CRSH_COUNT_LANES_MIN_BUNDLE);
+        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream, packed);
         k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
             prof_scope ps("k_level_emit", stream);
