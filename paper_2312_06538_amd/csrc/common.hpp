@@ -218,6 +218,10 @@ constexpr uint32_t LEVEL_THREADS = 256;   // threads of a traversal tile
 #endif
 constexpr uint32_t LEVEL_PPT = 1;   // parent pairs per thread of the count pass
 constexpr uint32_t LEVEL_TILE = LEVEL_THREADS * LEVEL_PPT;   // parent pairs per count tile
+constexpr uint32_t COUNT_THREADS = 512;    // threads of a count block: COUNT_TPS tiles per step
+constexpr uint32_t COUNT_TPS = COUNT_THREADS / LEVEL_THREADS;
+constexpr uint32_t COUNT_WINDOW = 1024;    // child nodes a count block keeps in LDS (36 B each)
+#define COUNT_WAVES_PER_SIMD 6             // 3 count blocks per compute unit (LDS: 48 KiB each)
 constexpr uint32_t EMIT_PPT = CRSH_EMIT_PPT;     // parent pairs per thread of the emit pass
 constexpr uint32_t EMIT_TILE = LEVEL_THREADS * EMIT_PPT;     // parent pairs per emit tile
 static_assert(EMIT_PPT % LEVEL_PPT == 0, "an emit tile covers whole count tiles");

@@ -3,7 +3,8 @@
 // Every level is produced in three launches with no wait between blocks:
 //   count  each work item (top level: one (top node, mesh) pair per wave;
 //          lower levels: a tile of 256 parent pairs, one (parent, child)
-//          test per lane) runs its Eq. 9 tests and records how many pass
+//          test per lane, child nodes read from a run of them copied to
+//          LDS) runs its Eq. 9 tests and records how many pass
 //          (lower levels also keep the pass bits, one per child slot,
 //          packed in 32-bit words);
 //   scan   exclusive scan of the counts -> output offset of every item;
@@ -21,8 +22,8 @@
 // come first, then a top-level pass appends the (node, mesh, triangle) pairs
 // of the frames whose top is this level.  A top-level item is (frame, top
 // node, mesh of the frame); a parent's children are the range recorded with
-// it by the build (first child, count), so no frame lookup is needed below
-// the top.
+// it by the build (first child, count), so below the top a frame is looked
+// up only when a count block copies a new run of child nodes to LDS.
 #include "bounds.hpp"
 #include "traverse.hpp"
 
@@ -248,23 +249,31 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
 // Count pass with one (parent pair, child) test per lane.
 // A tile of LEVEL_TILE parent pairs is tested in NF slices of LEVEL_TILE /
 // NF parents; in a slice the NF lanes of a parent test its NF consecutive
-// children, so a wave's node loads cover 64 / NF runs of NF consecutive
-// nodes, and its ballot is directly the pass bits of its 64 / NF parents in
-// the mask layout of the count pass (NF bits per parent, parent-major).
+// children, and the wave's ballot is directly the pass bits of its 64 / NF
+// parents in the mask layout of the count pass (NF bits per parent,
+// parent-major).  A block of COUNT_THREADS takes COUNT_TPS tiles per step.
 // What the NF lanes of a parent share -- the parent node and the triangle
 // sphere -- is read once: each lane reads the pair and sphere of one of
 // the wave's 64 parents of the tile into a wave-private LDS record, and the
-// lanes of a slice read their parent's record from there.  The vector memory
-// path, which bounds this pass, then carries per test only the child's
-// 36 bytes (buffer loads on 32-bit offsets) and 3/(64 NF) of a pair read.
-// The next tile's pairs and spheres are requested before a tile is tested
-// (pairs two tiles ahead, since the sphere read depends on them).  In the
-// batched form a parent's children are the range the build recorded with it
-// (first, count); the lane that reads a parent's pair reads that record too,
-// in the same stage as the sphere, and puts it in the parent's LDS record,
-// so no lane of the slice repeats the dependent read.
-template <int NF, bool BATCH, bool PACKED>
-__global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t parent_level, uint32_t F,
+// lanes of a slice read their parent's record from there.  The next step's
+// pairs and spheres are requested before a step is tested (pairs two steps
+// ahead, since the sphere read depends on them).
+//
+// Child nodes (36 bytes a test) come from LDS where they can: the
+// descendants of one top-level node on the child level are a contiguous
+// run of F^(levels above the child level) nodes, aligned to that length
+// from the frame's first node of the level, and the pairs of a level are
+// ordered by top-level node first, so a block's consecutive steps keep
+// testing children from the same run.  When the run fits COUNT_WINDOW
+// nodes, the block copies the run holding its step's first child into LDS
+// (once per run it enters; the batched form looks the frame up only then)
+// and its waves read the children there; a group of slices with a child
+// outside the run reads the node arrays directly.  In the batched form a
+// parent's children are the range the build recorded with it (first,
+// count); the lane that reads a parent's pair reads that record too, in the
+// same stage as the sphere, and puts it in the parent's LDS record.
+template <int NF, bool BATCH, bool PACKED, bool STAGED>
+__global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t parent_level, uint32_t F,
                                                                      const float4 *__restrict__ na,
                                                                      const float4 *__restrict__ nb,
                                                                      const float *__restrict__ ns,
@@ -275,12 +284,17 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
     static_assert(LEVEL_PPT == 1 && WAVE % NF == 0, "whole parents per wave");
     constexpr uint32_t PR = LEVEL_THREADS / NF;   // parents per slice; NF slices make a tile
     constexpr uint32_t PW = WAVE / NF;            // parents of a wave per slice
+    constexpr uint32_t WPT = LEVEL_THREADS / WAVE;   // waves per tile
+    constexpr uint32_t NW = COUNT_THREADS / WAVE;    // waves per block
     constexpr uint32_t NONE = 0xFFFFFFFFu;
-    __shared__ uint32_t s_red32[2][LEVEL_THREADS / WAVE];
-    __shared__ uint64_t s_red[LEVEL_THREADS / WAVE];
-    __shared__ float4 s_sph[LEVEL_THREADS / WAVE][WAVE];      // [wave][record]
-    __shared__ uint32_t s_first[LEVEL_THREADS / WAVE][WAVE];  // first child (level-local)
-    __shared__ uint32_t s_cnt[LEVEL_THREADS / WAVE][WAVE];    // children (0: no parent)
+    constexpr uint32_t WN = STAGED ? COUNT_WINDOW : 1u;
+    __shared__ uint32_t s_red32[2][NW];
+    __shared__ uint64_t s_red[NW];
+    __shared__ float4 s_sph[NW][WAVE];      // [wave][record]
+    __shared__ uint32_t s_first[NW][WAVE];  // first child (level-local)
+    __shared__ uint32_t s_cnt[NW][WAVE];    // children (0: no parent)
+    __shared__ float4 s_wa[WN], s_wb[WN];   // the staged run of child nodes
+    __shared__ float s_ws[WN];
     const uint32_t nl = meta->n_levels;
     if ((uint32_t)parent_level > nl || parent_level < 2) return;
     const uint64_t ntiles = level_items(meta, parent_level, 0, P);
@@ -289,24 +303,39 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
     if (in.tri == nullptr || P.p[parent_level - 2].tri == nullptr) return;
     uint64_t nin = meta->pairs[parent_level - 1];
     nin = nin < in.cap ? nin : in.cap;
+    const uint64_t nsteps = (ntiles + COUNT_TPS - 1) / COUNT_TPS;
     const uint32_t nk = meta->level_cnt[parent_level - 2];
     const uint32_t offk = meta->level_off[parent_level - 2];
     const uint32_t offp = meta->level_off[parent_level - 1];
     const uint32_t np = meta->level_cnt[parent_level - 1];
     const uint32_t l = lane_id();
-    const uint32_t w = threadIdx.x / WAVE;
+    const uint32_t wb = threadIdx.x / WAVE;           // wave of the block
+    const uint32_t half = threadIdx.x / LEVEL_THREADS;   // tile of the step
+    const uint32_t tw = wb % WPT;                     // wave of the tile
     const uint32_t j = l % NF;              // child of this lane in every slice
     const uint32_t pi = l / NF;             // parent of this lane within the wave's slice
     // the parent whose pair and sphere this lane reads: slice l / PW,
     // parent l % PW of the wave's share of it
-    const uint32_t own = (l / PW) * PR + w * PW + l % PW;
+    const uint32_t own = (l / PW) * PR + tw * PW + l % PW;
     // nodes from offk + ch for ch < nk, by 32-bit byte offsets
     const uint64_t nodes = (uint64_t)offk + nk;
     const __amdgpu_buffer_rsrc_t ra = make_rsrc(na, nodes * 16u);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(nb, nodes * 16u);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(ns, nodes * 4u);
-    auto load_pair = [&](uint64_t tile, uint32_t &tri, uint32_t &par) {
-        const uint64_t q = tile * LEVEL_TILE + own;
+    // descendants of one top-level node on the child level of a hierarchy
+    // with `levels` levels: F^(levels - L + 1) (above WN: more than the
+    // window holds)
+    auto run_of = [&](uint32_t levels) {
+        uint32_t run = 1;
+        for (uint32_t e = 0; e < levels - (uint32_t)parent_level + 1 && run <= WN; ++e) run *= F;
+        return run;
+    };
+    // STAGED: the host's bound on the runs of this level fits the window
+    const bool staged = STAGED && (BATCH || run_of(nl) <= WN);
+    uint32_t wlo = NONE, wlen = 0;          // staged run (block-uniform)
+    uint32_t ulo = NONE, ulen = 0;          // batch: a frame's nodes whose runs do not fit
+    auto load_pair = [&](uint64_t step, uint32_t &tri, uint32_t &par) {
+        const uint64_t q = (step * COUNT_TPS + half) * LEVEL_TILE + own;
         tri = 0u;
         par = NONE;
         if (q < nin) pair_get<PACKED>(in, q, tri, par);
@@ -326,77 +355,159 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_count_lanes(int32_t par
         }
     };
     // two-stage prefetch: the sphere (and batch: the child range) of the
-    // next tile and the pair of the tile after it are in flight while a
-    // tile is tested
+    // next step and the pair of the step after it are in flight while a
+    // step is tested
     uint32_t first_n = 0u, cnt_n = 0u, tri_nn = 0u, par_nn = NONE;
     float4 sp_n = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (blockIdx.x < ntiles) {
+    if (blockIdx.x < nsteps) {
         uint32_t tri0, par0;
         load_pair(blockIdx.x, tri0, par0);
         sp_n = tsph[tri0 < m ? tri0 : 0u];
         children(par0, first_n, cnt_n);
-        if (blockIdx.x + gridDim.x < ntiles) load_pair(blockIdx.x + gridDim.x, tri_nn, par_nn);
+        if (blockIdx.x + gridDim.x < nsteps) load_pair(blockIdx.x + gridDim.x, tri_nn, par_nn);
     }
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x, parity ^= 1u) {
-        // this tile's records (the wave's previous reads of them are done:
+    for (uint64_t step = blockIdx.x; step < nsteps; step += gridDim.x, parity ^= 1u) {
+        const uint64_t tile = step * COUNT_TPS + half;
+        // this step's records (the wave's previous reads of them are done:
         // program order within the wave)
         __builtin_amdgcn_wave_barrier();
-        s_sph[w][l] = sp_n;
-        s_first[w][l] = first_n;
-        s_cnt[w][l] = cnt_n;
+        s_sph[wb][l] = sp_n;
+        s_first[wb][l] = first_n;
+        s_cnt[wb][l] = cnt_n;
         __builtin_amdgcn_wave_barrier();
+        if (staged) {
+            // every wave has written its records and finished its reads of
+            // the staged run (they precede the previous step's count
+            // barrier); the step's first pair is record 0 of wave 0
+            __syncthreads();
+            const uint32_t c0 = s_first[0][0];
+            if (s_cnt[0][0] != 0u && c0 < nk && c0 - wlo >= wlen && c0 - ulo >= ulen) {
+                // the frame's nodes on the child level and its levels
+                uint32_t base = 0u, cntf = nk, levels = nl;
+                if constexpr (BATCH) {
+                    const uint32_t f = frame_of_node(bd, (uint32_t)parent_level - 2, c0);
+                    base = bd.fm[f].level_base[parent_level - 2];
+                    cntf = bd.fm[f].level_cnt[parent_level - 2];
+                    levels = bd.fm[f].n_levels;
+                }
+                const uint32_t run = run_of(levels);
+                if (run <= WN && c0 >= base && c0 - base < cntf) {
+                    const uint32_t lo = base + (c0 - base) / run * run;
+                    const uint32_t len = min(run, base + cntf - lo);
+                    for (uint32_t i = threadIdx.x; i < len; i += COUNT_THREADS) {
+                        s_wa[i] = na[offk + lo + i];
+                        s_wb[i] = nb[offk + lo + i];
+                        s_ws[i] = ns[offk + lo + i];
+                    }
+                    __syncthreads();
+                    wlo = lo;
+                    wlen = len;
+                } else {
+                    ulo = base;
+                    ulen = cntf;
+                }
+            }
+        }
         sp_n = tsph[tri_nn < m ? tri_nn : 0u];
         children(par_nn, first_n, cnt_n);
-        if (tile + 2 * (uint64_t)gridDim.x < ntiles) load_pair(tile + 2 * (uint64_t)gridDim.x, tri_nn, par_nn);
+        if (step + 2 * (uint64_t)gridDim.x < nsteps) load_pair(step + 2 * (uint64_t)gridDim.x, tri_nn, par_nn);
         uint32_t c = 0;
-        // slices in groups of K: every node load of a group is issued before
-        // its first test, and the test has no branch to sink them into
-        constexpr uint32_t K = NF < 4 ? NF : 4;
+        // slices in groups of K: every node read of a group is issued before
+        // its first test, and the test has no branch to sink them into.
+        // Children outside the staged run are read from the node arrays
+        // afterwards, in a branch of their own, so the reads from LDS never
+        // wait behind memory loads.
+        constexpr uint32_t KG = 2;
+        constexpr uint32_t K = NF < KG ? NF : KG;
 #pragma unroll
         for (uint32_t r0 = 0; r0 < NF; r0 += K) {
-            float4 A[K], Bv[K];
-            float Sg[K];
-            bool ok[K];
+            bool ok[K], out[K], meets[K];
+            uint32_t ch[K];
+            bool any_out = false;
 #pragma unroll
             for (uint32_t k = 0; k < K; ++k) {
                 const uint32_t rec = (r0 + k) * PW + pi;
-                const uint32_t ch = s_first[w][rec] + j;
-                ok[k] = j < s_cnt[w][rec] && ch < nk;
-                const uint32_t g = offk + (ok[k] ? ch : 0u);
-                A[k] = buf_load4(ra, g * 16u);
-                Bv[k] = buf_load4(rb, g * 16u);
-                Sg[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
+                ch[k] = s_first[wb][rec] + j;
+                ok[k] = j < s_cnt[wb][rec] && ch[k] < nk;
+                out[k] = ok[k] && ch[k] - wlo >= wlen;
+                any_out |= out[k];
+                meets[k] = false;
+            }
+            if constexpr (STAGED) {
+                float4 A[K], Bv[K];
+                float Sg[K];
+#pragma unroll
+                for (uint32_t k = 0; k < K; ++k) {
+                    const uint32_t i = ok[k] && !out[k] ? ch[k] - wlo : 0u;
+                    A[k] = s_wa[i];
+                    Bv[k] = s_wb[i];
+                    Sg[k] = s_ws[i];
+                }
+#pragma unroll
+                for (uint32_t k = 0; k < K; ++k) {
+                    const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
+                    meets[k] = packed_meets_flat(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w);
+                }
+                // rare: a slice with children outside the run, one at a time
+                if (ballot(any_out) != 0) {
+#pragma unroll
+                    for (uint32_t k = 0; k < K; ++k) {
+                        if (ballot(out[k]) == 0) continue;
+                        const uint32_t g = offk + (out[k] ? ch[k] : 0u);
+                        const float4 Ag = buf_load4(ra, g * 16u);
+                        const float4 Bg = buf_load4(rb, g * 16u);
+                        const float Sgg = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
+                        const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
+                        const bool mg = packed_meets_flat(Ag, Bg, Sgg, mk(sp.x, sp.y, sp.z), sp.w);
+                        meets[k] = out[k] ? mg : meets[k];
+                    }
+                }
+            } else {
+                // runs longer than the window: every child from the node
+                // arrays, the group's loads issued together (out == ok)
+                float4 A[K], Bv[K];
+                float Sg[K];
+#pragma unroll
+                for (uint32_t k = 0; k < K; ++k) {
+                    const uint32_t g = offk + (ok[k] ? ch[k] : 0u);
+                    A[k] = buf_load4(ra, g * 16u);
+                    Bv[k] = buf_load4(rb, g * 16u);
+                    Sg[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
+                }
+#pragma unroll
+                for (uint32_t k = 0; k < K; ++k) {
+                    const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
+                    meets[k] = packed_meets_flat(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w);
+                }
             }
 #pragma unroll
             for (uint32_t k = 0; k < K; ++k) {
                 const uint32_t r = r0 + k;
-                const float4 sp = s_sph[w][r * PW + pi];
-                const bool meets = packed_meets_flat(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w);
                 tests += ok[k] ? 1u : 0u;
-                const uint64_t bal = ballot(ok[k] & meets);
-                if (l == 0) {
-                    const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + w * PW) * NF;   // a multiple of 64
+                const uint64_t bal = ballot(ok[k] & meets[k]);
+                if (l == 0 && tile < ntiles) {
+                    const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + tw * PW) * NF;   // a multiple of 64
                     *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal, (uint32_t)(bal >> 32));
                 }
                 c += (uint32_t)__popcll(bal);
             }
         }
-        // survivors of the tile: wave sums in alternating LDS slots (one
-        // barrier per tile)
-        if (l == 0) s_red32[parity][w] = c;
+        // survivors of each tile: wave sums in alternating LDS slots (one
+        // barrier per step)
+        if (l == 0) s_red32[parity][wb] = c;
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (threadIdx.x % LEVEL_THREADS == 0 && tile < ntiles) {
             uint32_t t = 0;
-            for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) t += s_red32[parity][ww];
+            for (uint32_t ww = 0; ww < WPT; ++ww) t += s_red32[parity][half * WPT + ww];
             S.cnt[tile] = t;
         }
     }
     tests = wave_sum(tests);
-    if (l == 0) s_red[w] = tests;
+    if (l == 0) s_red[wb] = tests;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t tt = 0;
-        for (int ww = 0; ww < LEVEL_THREADS / WAVE; ++ww) tt += s_red[ww];
+        for (uint32_t ww = 0; ww < NW; ++ww) tt += s_red[ww];
         if (tt) atomicAdd((unsigned long long *)&meta->tests[parent_level - 2], (unsigned long long)tt);
     }
 }
@@ -625,29 +736,40 @@ static uint32_t resident_blocks(K kernel, uint32_t threads)
 
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
-                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed)
+                        const batch_dev *bd, uint64_t tiles_cap, uint32_t top_levels, hipStream_t stream, bool packed)
 {
     const batch_dev b = bd ? *bd : batch_dev{};
     const uint32_t Fu = (uint32_t)merge;
     const int L = parent_level;
     int nf = 2;
     while (nf < merge) nf *= 2;
+    // descendants of a top-level node on the child level, for a hierarchy
+    // of at most top_levels levels: the staged kernel if they fit the window
+    uint64_t run = 1;
+    for (int e = 0; e < (int)top_levels - L + 1 && run <= COUNT_WINDOW; ++e) run *= Fu;
+    const bool st = run <= COUNT_WINDOW;
     prof_scope ps("k_level", stream);
-    // a persistent grid of whole rounds of resident blocks (at most one
-    // block per tile)
-#define CRSH_COUNT_ONE(NF, BT, PK)                                                                           \
+    // a persistent grid of one round of resident blocks (at most one block
+    // per step of COUNT_TPS tiles)
+#define CRSH_COUNT_ONE(NF, BT, PK, ST)                                                                       \
     {                                                                                                        \
-        const uint32_t rb = resident_blocks(k_level_count_lanes<NF, BT, PK>, LEVEL_THREADS);                 \
-        const uint64_t want = std::max<uint64_t>(tiles_cap, 1);                                              \
-        const uint32_t gl = (uint32_t)std::min<uint64_t>(want, rb ? rb : 4096);                              \
-        k_level_count_lanes<NF, BT, PK><<<gl, LEVEL_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, meta, b); \
+        const uint32_t rb = resident_blocks(k_level_count_lanes<NF, BT, PK, ST>, COUNT_THREADS);             \
+        const uint64_t want = std::max<uint64_t>((tiles_cap + COUNT_TPS - 1) / COUNT_TPS, 1);                \
+        const uint32_t gl = (uint32_t)std::min<uint64_t>(want, rb ? rb : 2048);                              \
+        k_level_count_lanes<NF, BT, PK, ST><<<gl, COUNT_THREADS, 0, stream>>>(L, Fu, na, nb, ns, tsph, m, P, S, \
+                                                                            meta, b);                       \
     }
+#define CRSH_COUNT_ST(NF, BT, PK)                                                                            \
+    if (st)                                                                                                  \
+        CRSH_COUNT_ONE(NF, BT, PK, true)                                                                     \
+    else                                                                                                     \
+        CRSH_COUNT_ONE(NF, BT, PK, false)
 #define CRSH_COUNT_NF(BT, PK)                                                                                \
     switch (nf) {                                                                                            \
-    case 2: CRSH_COUNT_ONE(2, BT, PK) break;                                                                 \
-    case 4: CRSH_COUNT_ONE(4, BT, PK) break;                                                                 \
-    case 8: CRSH_COUNT_ONE(8, BT, PK) break;                                                                 \
-    default: CRSH_COUNT_ONE(16, BT, PK) break;                                                               \
+    case 2: CRSH_COUNT_ST(2, BT, PK) break;                                                                  \
+    case 4: CRSH_COUNT_ST(4, BT, PK) break;                                                                  \
+    case 8: CRSH_COUNT_ST(8, BT, PK) break;                                                                  \
+    default: CRSH_COUNT_ST(16, BT, PK) break;                                                                \
     }
     if (bd) {
         CRSH_COUNT_NF(true, false)
@@ -657,6 +779,7 @@ void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, c
         CRSH_COUNT_NF(false, false)
     }
 #undef CRSH_COUNT_NF
+#undef CRSH_COUNT_ST
 #undef CRSH_COUNT_ONE
 }
 
@@ -806,7 +929,8 @@ static crsh_status traverse_run(const crsh_nodes *nodes, const crsh_scene *scene
     case 8: CRSH_EMIT(8, BT, PK); break;                                                                   \
     default: CRSH_EMIT(16, BT, PK); break;                                                                 \
     }
-        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles, stream, packed);
+        level_count_launch(L, merge, na, nb, ns, tsph, scene->m, P, S, meta, bd, tiles,
+                           (uint32_t)(bd ? batch_levels : levels), stream, packed);
         k_scan_items<<<scan_grid, SCAN_THREADS, 0, stream>>>(L, scene->n_mesh, P, S, meta, 0, nullptr);
         {
             prof_scope ps("k_level_emit", stream);

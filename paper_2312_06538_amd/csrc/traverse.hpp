@@ -69,6 +69,7 @@ void node_pack_launch(const crsh_nodes *nodes, crsh_meta *meta, float4 *na, floa
 // node tests added to meta)
 void level_count_launch(int32_t parent_level, int32_t merge, const float4 *na, const float4 *nb, const float *ns,
                         const float4 *tsph, uint32_t m, const pair_levels &P, const trav_scratch &S, crsh_meta *meta,
-                        const batch_dev *bd, uint64_t tiles_cap, hipStream_t stream, bool packed = false);
+                        const batch_dev *bd, uint64_t tiles_cap, uint32_t top_levels, hipStream_t stream,
+                        bool packed = false);
 
 }  // namespace crsh

@@ -188,12 +188,15 @@ def test_traverse_bit_exact(name):
 
 
 @pytest.mark.parametrize("B,F,n", [(16, 2, 4), (16, 3, 3), (16, 8, 3), (32, 16, 2), (24, 4, 4), (8, 4, 4),
-                                   (8, 8, 2)])
+                                   (8, 8, 2), (4, 4, 7), (2, 16, 4)])
 def test_traverse_shapes(B, F, n):
     """Traversal pairs, node tests and survivors of every level for merge
-    factors 2..16 and bundles on both sides of 16 rays (the level-1 count
-    runs one (parent, child) test per lane from B = 16 on, with NF = the
-    merge factor rounded up to a power of two lanes per parent)."""
+    factors 2..16 and bundles on both sides of 16 rays (one (parent, child)
+    test per lane, NF = the merge factor rounded up to a power of two lanes
+    per parent).  The count passes copy the run of child nodes below one
+    top-level node to LDS when it has at most 1024 nodes: (4, 4, 7) has runs
+    of 4^6 = 4096 nodes on level 1 (read from the node arrays) and of exactly
+    1024 on level 2; (2, 16, 4) has runs of 16^3 = 4096 on level 1."""
     base, kw = small("refl_96")
     print(f"[traverse-shape] B={B} F={F} n={n}", flush=True)
     wl = workload(base, **kw)
