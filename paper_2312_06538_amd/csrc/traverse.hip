@@ -265,10 +265,11 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
 // from the frame's first node of the level, and the pairs of a level are
 // ordered by top-level node first, so a block's consecutive steps keep
 // testing children from the same run.  When the run fits COUNT_WINDOW
-// nodes, the block copies the run holding its step's first child into LDS
-// (once per run it enters; the batched form looks the frame up only then)
-// and its waves read the children there; a group of slices with a child
-// outside the run reads the node arrays directly.  In the batched form a
+// nodes, the block copies the run holding its step's first child, and the
+// runs after it as far as the window reaches within the frame, into LDS
+// (once per window it enters; the batched form looks the frame up only
+// then) and its waves read the children there; a group of slices with a
+// child outside the window reads the node arrays directly.  In the batched form a
 // parent's children are the range the build recorded with it (first,
 // count); the lane that reads a parent's pair reads that record too, in the
 // same stage as the sphere, and puts it in the parent's LDS record.
@@ -392,8 +393,10 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
                 }
                 const uint32_t run = run_of(levels);
                 if (run <= WN && c0 >= base && c0 - base < cntf) {
+                    // as many whole runs as the window holds, from the one
+                    // holding c0 (later steps move on to the next runs)
                     const uint32_t lo = base + (c0 - base) / run * run;
-                    const uint32_t len = min(run, base + cntf - lo);
+                    const uint32_t len = min(WN / run * run, base + cntf - lo);
                     for (uint32_t i = threadIdx.x; i < len; i += COUNT_THREADS) {
                         s_wa[i] = na[offk + lo + i];
                         s_wb[i] = nb[offk + lo + i];
