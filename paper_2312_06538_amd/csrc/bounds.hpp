@@ -129,7 +129,22 @@ __device__ __forceinline__ bool packed_meets_flat(float4 A, float4 Bv, float sec
     const f3 w = cross(v, a);
     const float lhs2 = dot(w, w);
     const float rhs = fabsf(t) * Bv.w + (d + A.w) * sec;
-    return !(sec > 0.0f) | (lhs2 <= rhs * rhs);
+    return !(sec > 0.0f) || lhs2 <= rhs * rhs;
+}
+
+// packed_meets_flat over a wave: the mask of the lanes whose pair passes,
+// each condition taken as a mask of its own (a compare's result is already
+// a mask; their combination is then one scalar operation).  Called by every
+// lane of the wave.
+__device__ __forceinline__ uint64_t packed_meets_mask(float4 A, float4 Bv, float sec, f3 P, float d)
+{
+    const f3 v = P - mk(A.x, A.y, A.z);
+    const f3 a = mk(Bv.x, Bv.y, Bv.z);
+    const float t = dot(v, a);
+    const f3 w = cross(v, a);
+    const float lhs2 = dot(w, w);
+    const float rhs = fabsf(t) * Bv.w + (d + A.w) * sec;
+    return ballot(!(sec > 0.0f)) | ballot(lhs2 <= rhs * rhs);
 }
 
 

@@ -61,7 +61,9 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// wave mask of the lanes where p holds (inactive lanes: 0); lowers to the
+// compare result itself, with no per-lane select
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Raw buffer resource over `bytes` bytes at p (bytes clamped to 2^32 - 1):
 // loads through it take a 32-bit byte offset, and a load past the end

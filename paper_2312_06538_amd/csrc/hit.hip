@@ -190,19 +190,22 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
             tr.e2 = mk(b.z, b.w, c.x);
             // a padded slot's NaN t_min accepts nothing; it only must not
             // count as a test
-            if (BATCH) ok = ok && __float_as_uint(rd4.w) != PAD_SLOT;
-            tests += (uint64_t)__popcll(ballot(ok));
+            if (BATCH) ok = ok & (__float_as_uint(rd4.w) != PAD_SLOT);
+            const uint64_t okm = ballot(ok);
+            tests += (uint64_t)__popcll(okm);
             const f3 D = mk(rd4.x, rd4.y, rd4.z);
             mt_head h;
-            const bool maybe = mt_first_half(mk(ro4.x, ro4.y, ro4.z), D, tr, h) && ok;
+            const uint64_t mm = mt_first_half(mk(ro4.x, ro4.y, ro4.z), D, tr, h) & okm;
             // a wave-uniform branch: the wave runs the second half only if
-            // one of its lanes needs it
-            if (ballot(maybe) != 0) {
+            // one of its lanes needs it (every lane computes it; the masks
+            // keep the lanes that needed it)
+            if (mm != 0) {
                 float th;
-                const uint32_t st = maybe ? mt_second_half(D, rd4.w, ro4.w, tr, h, th) : 0u;
-                upass += (uint64_t)__popcll(ballot((st & MT_U) != 0u));
-                uvpass += (uint64_t)__popcll(ballot((st & MT_UV) != 0u));
-                if (st & MT_HIT) atomicMin(&keys[ro >> 4], hit_key(th, __float_as_uint(c.y)));
+                bool pu, puv, hit;
+                mt_second_half(D, rd4.w, ro4.w, tr, h, th, pu, puv, hit);
+                upass += (uint64_t)__popcll(ballot(pu) & mm);
+                uvpass += (uint64_t)__popcll(ballot(puv) & mm);
+                if ((ballot(hit) & mm) >> l & 1u) atomicMin(&keys[ro >> 4], hit_key(th, __float_as_uint(c.y)));
             }
         }
     }

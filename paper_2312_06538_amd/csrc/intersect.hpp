@@ -88,14 +88,15 @@ __device__ __forceinline__ bool moller_trumbore(f3 O, f3 D, float t_min, float t
 
 // The first half of the test, for the final-test kernel: p = D x e2,
 // det = e1 . p, T = O - v0 and a = T . p (u = a / det before rounding), and
-// whether the ray can still pass -- false exactly when moller_trumbore's
-// determinant check or its division-free decision on u rejects it.
+// the wave mask of the lanes whose ray can still pass -- clear exactly where
+// moller_trumbore's determinant check or its division-free decision on u
+// rejects it.  Called by every lane of the wave.
 struct mt_head {
     f3 p, T;
     float det, a;
 };
 
-__device__ __forceinline__ bool mt_first_half(f3 O, f3 D, const tri_t &tr, mt_head &h)
+__device__ __forceinline__ uint64_t mt_first_half(f3 O, f3 D, const tri_t &tr, mt_head &h)
 {
     h.p = cross(D, tr.e2);
     h.det = dot(tr.e1, h.p);
@@ -109,14 +110,19 @@ __device__ __forceinline__ bool mt_first_half(f3 O, f3 D, const tri_t &tr, mt_he
     // reject it (u NaN).
     const float adet = fabsf(h.det);
     const float sg = __uint_as_float(__float_as_uint(h.a) ^ (__float_as_uint(h.det) & 0x80000000u));
-    return adet >= DET_EPS && (adet > 0x1p60f || (sg > -0x1p-60f && sg <= adet * (1.0f + 0x1p-19f)));
+    // each comparison is a wave mask as it stands; they combine in scalar
+    // operations
+    return ballot(adet >= DET_EPS) &
+           (ballot(adet > 0x1p60f) | (ballot(sg > -0x1p-60f) & ballot(sg <= adet * (1.0f + 0x1p-19f))));
 }
 
 // The rest of the test for a ray that mt_first_half let through: the same
 // operations, in the same order, as moller_trumbore after its early checks.
-// Returns the checks passed (MT_U, MT_UV, MT_HIT).
-__device__ __forceinline__ uint32_t mt_second_half(f3 D, float t_min, float tmax, const tri_t &tr, const mt_head &h,
-                                                   float &tt)
+// The checks passed: pu (u in [0, 1]), puv (and v >= 0, u + v <= 1), hit
+// (and t_min < t < tmax), each implying the ones before; all comparisons are
+// made and combined without short-circuit.
+__device__ __forceinline__ void mt_second_half(f3 D, float t_min, float tmax, const tri_t &tr, const mt_head &h,
+                                               float &tt, bool &pu, bool &puv, bool &hit)
 {
     const float inv = 1.0f / h.det;
     const float u = h.a * inv;
@@ -124,10 +130,9 @@ __device__ __forceinline__ uint32_t mt_second_half(f3 D, float t_min, float tmax
     const float v = dot(D, q) * inv;
     const float t = dot(tr.e2, q) * inv;
     tt = t;
-    const bool pu = u >= 0.0f && u <= 1.0f;
-    const bool puv = pu && (v >= 0.0f && u + v <= 1.0f);
-    const bool hit = puv && (t > t_min && t < tmax);
-    return (pu ? MT_U : 0u) | (puv ? MT_UV : 0u) | (hit ? MT_HIT : 0u);
+    pu = (u >= 0.0f) & (u <= 1.0f);
+    puv = pu & (v >= 0.0f) & (u + v <= 1.0f);
+    hit = puv & (t > t_min) & (t < tmax);
 }
 
 // The same test for the final-test kernel, without early exits: every

@@ -341,7 +341,7 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
         par = NONE;
         if (q < nin) pair_get<PACKED>(in, q, tri, par);
     };
-    uint64_t tests = 0;
+    uint64_t tests = 0;                     // wave-wide
     uint32_t parity = 0;
     // a parent's children: plain, par * F + [0, F); batch, the build's
     // record (level-local first child, count)
@@ -417,62 +417,64 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
         uint32_t c = 0;
         // slices in groups of K: every node read of a group is issued before
         // its first test, and the test has no branch to sink them into.
-        // Children outside the staged run are read from the node arrays
+        // Which lanes test a child, and which of those find it outside the
+        // staged run, are wave masks (scalar registers), and so are the
+        // results; children outside the run are read from the node arrays
         // afterwards, in a branch of their own, so the reads from LDS never
         // wait behind memory loads.
         constexpr uint32_t KG = 2;
         constexpr uint32_t K = NF < KG ? NF : KG;
 #pragma unroll
         for (uint32_t r0 = 0; r0 < NF; r0 += K) {
-            bool ok[K], out[K], meets[K];
-            uint32_t ch[K];
-            bool any_out = false;
+            uint64_t okm[K], outm[K], bal[K];
+            uint32_t ch[K], idx[K];
 #pragma unroll
             for (uint32_t k = 0; k < K; ++k) {
                 const uint32_t rec = (r0 + k) * PW + pi;
                 ch[k] = s_first[wb][rec] + j;
-                ok[k] = j < s_cnt[wb][rec] && ch[k] < nk;
-                out[k] = ok[k] && ch[k] - wlo >= wlen;
-                any_out |= out[k];
-                meets[k] = false;
+                okm[k] = ballot(j < s_cnt[wb][rec]) & ballot(ch[k] < nk);
+                const uint32_t i = ch[k] - wlo;
+                outm[k] = okm[k] & ~ballot(i < wlen);
+                idx[k] = min(i, WN - 1u);       // any slot of the window for a lane that tests nothing here
             }
             if constexpr (STAGED) {
                 float4 A[K], Bv[K];
                 float Sg[K];
 #pragma unroll
                 for (uint32_t k = 0; k < K; ++k) {
-                    const uint32_t i = ok[k] && !out[k] ? ch[k] - wlo : 0u;
-                    A[k] = s_wa[i];
-                    Bv[k] = s_wb[i];
-                    Sg[k] = s_ws[i];
+                    A[k] = s_wa[idx[k]];
+                    Bv[k] = s_wb[idx[k]];
+                    Sg[k] = s_ws[idx[k]];
                 }
 #pragma unroll
                 for (uint32_t k = 0; k < K; ++k) {
                     const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
-                    meets[k] = packed_meets_flat(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w);
+                    bal[k] = packed_meets_mask(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w) & okm[k] & ~outm[k];
                 }
                 // rare: a slice with children outside the run, one at a time
-                if (ballot(any_out) != 0) {
+                uint64_t any_out = 0;
+#pragma unroll
+                for (uint32_t k = 0; k < K; ++k) any_out |= outm[k];
+                if (any_out != 0) {
 #pragma unroll
                     for (uint32_t k = 0; k < K; ++k) {
-                        if (ballot(out[k]) == 0) continue;
-                        const uint32_t g = offk + (out[k] ? ch[k] : 0u);
+                        if (outm[k] == 0) continue;
+                        const uint32_t g = offk + (((outm[k] >> l) & 1u) ? ch[k] : 0u);
                         const float4 Ag = buf_load4(ra, g * 16u);
                         const float4 Bg = buf_load4(rb, g * 16u);
                         const float Sgg = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
                         const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
-                        const bool mg = packed_meets_flat(Ag, Bg, Sgg, mk(sp.x, sp.y, sp.z), sp.w);
-                        meets[k] = out[k] ? mg : meets[k];
+                        bal[k] |= packed_meets_mask(Ag, Bg, Sgg, mk(sp.x, sp.y, sp.z), sp.w) & outm[k];
                     }
                 }
             } else {
                 // runs longer than the window: every child from the node
-                // arrays, the group's loads issued together (out == ok)
+                // arrays, the group's loads issued together (outm == okm)
                 float4 A[K], Bv[K];
                 float Sg[K];
 #pragma unroll
                 for (uint32_t k = 0; k < K; ++k) {
-                    const uint32_t g = offk + (ok[k] ? ch[k] : 0u);
+                    const uint32_t g = offk + (((okm[k] >> l) & 1u) ? ch[k] : 0u);
                     A[k] = buf_load4(ra, g * 16u);
                     Bv[k] = buf_load4(rb, g * 16u);
                     Sg[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
@@ -480,19 +482,18 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
 #pragma unroll
                 for (uint32_t k = 0; k < K; ++k) {
                     const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
-                    meets[k] = packed_meets_flat(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w);
+                    bal[k] = packed_meets_mask(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w) & okm[k];
                 }
             }
 #pragma unroll
             for (uint32_t k = 0; k < K; ++k) {
                 const uint32_t r = r0 + k;
-                tests += ok[k] ? 1u : 0u;
-                const uint64_t bal = ballot(ok[k] & meets[k]);
+                tests += (uint64_t)__popcll(okm[k]);
                 if (l == 0 && tile < ntiles) {
                     const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + tw * PW) * NF;   // a multiple of 64
-                    *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal, (uint32_t)(bal >> 32));
+                    *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal[k], (uint32_t)(bal[k] >> 32));
                 }
-                c += (uint32_t)__popcll(bal);
+                c += (uint32_t)__popcll(bal[k]);
             }
         }
         // survivors of each tile: wave sums in alternating LDS slots (one
@@ -505,8 +506,7 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
             S.cnt[tile] = t;
         }
     }
-    tests = wave_sum(tests);
-    if (l == 0) s_red[wb] = tests;
+    if (l == 0) s_red[wb] = tests;          // a wave-wide count: the same in every lane
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t tt = 0;
