@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
     const uint32_t slot = l >> log2G;        // pair of this lane within a step
     const uint32_t j = l & (G - 1);          // ray of the leaf
     const uint32_t per_wave = WAVE >> log2G;
-    const uint32_t wib = threadIdx.x / WAVE;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // scalar: so is the run arithmetic
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
     const __amdgpu_buffer_rsrc_t org_r = make_rsrc(RO, (uint64_t)ns * 16u);

@@ -310,8 +310,10 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     const uint32_t offp = meta->level_off[parent_level - 1];
     const uint32_t np = meta->level_cnt[parent_level - 1];
     const uint32_t l = lane_id();
-    const uint32_t wb = threadIdx.x / WAVE;           // wave of the block
-    const uint32_t half = threadIdx.x / LEVEL_THREADS;   // tile of the step
+    // wave indices, made scalar so that the addresses built from them are
+    // scalar arithmetic
+    const uint32_t wb = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // wave of the block
+    const uint32_t half = wb / WPT;                   // tile of the step
     const uint32_t tw = wb % WPT;                     // wave of the tile
     const uint32_t j = l % NF;              // child of this lane in every slice
     const uint32_t pi = l / NF;             // parent of this lane within the wave's slice
@@ -369,6 +371,8 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     }
     for (uint64_t step = blockIdx.x; step < nsteps; step += gridDim.x, parity ^= 1u) {
         const uint64_t tile = step * COUNT_TPS + half;
+        // this wave's slice-0 word of the tile's pass masks (scalar)
+        uint2 *const mrow = (uint2 *)S.mask + (tile * LEVEL_TILE + tw * PW) * NF / 64;
         // this step's records (the wave's previous reads of them are done:
         // program order within the wave)
         __builtin_amdgcn_wave_barrier();
@@ -489,10 +493,11 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
             for (uint32_t k = 0; k < K; ++k) {
                 const uint32_t r = r0 + k;
                 tests += (uint64_t)__popcll(okm[k]);
-                if (l == 0 && tile < ntiles) {
-                    const uint64_t bit0 = (tile * LEVEL_TILE + r * PR + tw * PW) * NF;   // a multiple of 64
-                    *(uint2 *)&S.mask[bit0 / 32] = make_uint2((uint32_t)bal[k], (uint32_t)(bal[k] >> 32));
-                }
+                // the wave's pass bits of slice r: bit (tile * LEVEL_TILE +
+                // r * PR + tw * PW) * NF of the level's masks, a multiple of 64
+                // (r * PR * NF = 64 r words' worth of 4 bits: uint2 4 r)
+                if (l == 0 && tile < ntiles)
+                    mrow[r * (PR * NF / 64)] = make_uint2((uint32_t)bal[k], (uint32_t)(bal[k] >> 32));
                 c += (uint32_t)__popcll(bal[k]);
             }
         }
