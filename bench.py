@@ -223,6 +223,9 @@ def main():
     ap.add_argument("--pairs", default="arrays", choices=["arrays", "packed"],
                     help="pair storage: two uint32 arrays, or one packed word per pair over triangle batches of "
                          "at most 2^14 triangles (crsh_traverse_packed)")
+    ap.add_argument("--last-level", default="stored", choices=["stored", "fused"],
+                    help="fused: the level-1 node tests and the final tests in crsh_leaf_hit, the level-1 pairs "
+                         "never stored (crsh_traverse_upper + crsh_leaf_hit)")
     ap.add_argument("--variant", default="crsh", choices=["crsh", "unsorted"],
                     help="unsorted: the comparison hierarchy without ray sorting or whole-mesh culling, on the "
                          "same inputs and with the same hierarchy shape")
@@ -300,11 +303,12 @@ def main():
     fr = P.DeviceFrame(wl)
     bf = P.Buffers(fr, 1 << 24, keep_levels=False)
     packed = args.pairs == "packed"
-    bf, m = P.run_with_retry(fr, bf, packed=packed)
+    fused = args.last_level == "fused"
+    bf, m = P.run_with_retry(fr, bf, packed=packed, leaf_hit=fused)
     print(f"[bench] sized: N={m.n_rays} levels={m.n_levels} pair capacity={bf.pair_capacity}",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        P.run_frame(fr, bf, packed=packed)
+        P.run_frame(fr, bf, packed=packed, leaf_hit=fused)
     torch.cuda.synchronize()
     ev = HipEvents(args.steps)
     # kernels timed on alternate steps: the two heaviest (the final tests and
@@ -312,14 +316,19 @@ def main():
     # and the sort and compaction kernels measured against HBM bandwidth (the
     # second radix pass, the emit that writes level 1)
     nl = int(m.n_levels)
-    probes = [("k_hit", 0), ("k_level", max(nl - 2, 0)), ("k_sort_pass", 1), ("k_level_emit", max(nl - 2, 0))]
+    # (fused last level: the first k_hit launch tests the level-1 pairs a
+    # top-level pass stored, none here; the second is the fused one, and no
+    # emit writes level 1)
+    probes = [("k_hit", 1 if fused else 0), ("k_level", max(nl - 2, 0)), ("k_sort_pass", 1)]
+    if not fused:
+        probes.append(("k_level_emit", max(nl - 2, 0)))
     t0 = time.perf_counter()
     for k in range(args.steps):
         a, b = ev.pair(k)
         name, occ = probes[k % len(probes)]
         if not packed:           # packed: one launch per triangle batch, no single kernel to time
             X.crsh_profile_next(name, occ, a, b)
-        P.run_frame(fr, bf, packed=packed)
+        P.run_frame(fr, bf, packed=packed, leaf_hit=fused)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     m, st = P.read_meta(bf)
@@ -382,7 +391,7 @@ def main():
         "config": {"workload": f"{args.workload}: {wl.W}x{wl.H} {ray_label(wl)}, "
                                f"{wl.scene.n_mesh} meshes, {wl.scene.m} triangles, B={wl.B} F={wl.F} n={wl.n}",
                    "rays": n, "triangles": wl.scene.m, "seed": args.seed, "variant": args.variant,
-                   "pairs": args.pairs},
+                   "pairs": args.pairs, "last_level": args.last_level},
         "tests": {"node_tests": node_tests, "final_ray_tri_tests": final, "final_u_pass": u_pass,
                   "final_uv_pass": uv_pass, "total": node_tests + final,
                   "brute_force": brute, "frac_of_brute": round((node_tests + final) / brute, 5),

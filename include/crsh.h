@@ -335,16 +335,17 @@ crsh_status crsh_closest_hit_packed(const crsh_rays *sorted, const uint32_t *sor
                                     void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Stages 4 (level 1, Eq. 9) and 5 (Sec. 3.3.8) fused, after
- * crsh_traverse_upper: the level-2 pairs pairs[1] are grouped by node; for
- * each node and triangle the node's children (leaves) are tested (Eq. 9) and
- * every passing (triangle, leaf) is tested against the leaf's rays
- * (Moller-Trumbore), with the rays and their running closest hits kept on
- * chip.  Level-1 pairs stored in pairs[0] (top level 1) are tested as in
+ * crsh_traverse_upper: every level-2 pair of pairs[1] is tested against the
+ * children (leaves) of its node (Eq. 9), the pass bits kept in the
+ * workspace, and every passing (triangle, leaf) is tested against the
+ * leaf's rays (Moller-Trumbore) straight from the level-2 pairs and those
+ * bits.  Level-1 pairs stored in pairs[0] (top level 1) are tested as in
  * crsh_closest_hit.  Results and counters equal crsh_traverse followed by
- * crsh_closest_hit: meta->tests[0], hits[0] (level-1 pairs formed) and
- * final_tests accumulate; the level-1 pairs are not stored.  `sorted`,
- * `sorted_ids`, `nodes`, bundle and merge as given to crsh_build.
- * ws: crsh_workspace_size() bytes. */
+ * crsh_closest_hit: meta->tests[0], hits[0] (level-1 pairs formed),
+ * final_tests, final_u_pass and final_uv_pass accumulate; the level-1 pairs
+ * are not stored (pairs[0] still needs storage, with a nonzero capacity:
+ * CRSH_ERR_INVALID otherwise).  `sorted`, `sorted_ids`, `nodes`, bundle and
+ * merge as given to crsh_build.  ws: crsh_workspace_size() bytes. */
 crsh_status crsh_leaf_hit(const crsh_rays *sorted, const uint32_t *sorted_ids,
                           int32_t bundle, int32_t merge, const crsh_nodes *nodes,
                           const crsh_pairs pairs[CRSH_MAX_LEVELS], const crsh_scene *scene,

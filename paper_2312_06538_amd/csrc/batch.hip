@@ -180,7 +180,8 @@ extern "C" crsh_status crsh_batch_enqueue(const crsh_batch *b, hipStream_t strea
     crsh_hits hits = b->hits;
     if (b->leaf_hit && b->levels >= 2)
         return leaf_hit_launch(&sorted, b->sids, b->bundle, b->merge, &nodes, &b->pairs[0], &b->pairs[1],
-                               &b->scene, 0.0f, &hits, b->meta, stage, stage_bytes, &bd, b->hit_block, stream);
+                               &b->scene, 0.0f, &hits, b->meta, stage, stage_bytes, &bd, b->hit_block,
+                               (uint32_t)b->levels, stream);
     return hit_launch(&sorted, b->sids, b->bundle, &b->pairs[0], &b->scene, 0.0f, &hits, b->meta, stage,
                       stage_bytes, &bd, b->hit_block, stream);
 }

@@ -291,7 +291,8 @@ crsh_status hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int3
 crsh_status leaf_hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle, int32_t merge,
                             const crsh_nodes *nodes, const crsh_pairs *level1, const crsh_pairs *level2,
                             const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta, void *ws,
-                            size_t ws_bytes, const batch_dev *bd, int32_t hit_block, hipStream_t stream);
+                            size_t ws_bytes, const batch_dev *bd, int32_t hit_block, uint32_t top_levels,
+                            hipStream_t stream);
 // pieces of the final tests shared by crsh_closest_hit and crsh_leaf_hit
 crsh_status hit_check(const crsh_rays *sorted, const uint32_t *sorted_ids, int32_t bundle, const crsh_pairs *level1,
                       const crsh_scene *scene, crsh_hits *hits, crsh_meta *meta, void *ws, int32_t hit_block,
@@ -301,6 +302,11 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
                       int32_t bundle, const crsh_scene *scene, float t_min, crsh_hits *hits, crsh_meta *meta,
                       const batch_dev *bd, int32_t hit_block, hipStream_t stream, bool packed = false,
                       uint32_t tri_base = 0);
+// final tests of the level-1 pairs given as level-2 pairs and level-1 pass
+// masks (the fused last level); rays packed by hit_pairs_launch first
+void hit_masked_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level2,
+                       const uint32_t *mask, int32_t merge, int32_t bundle, const crsh_scene *scene,
+                       crsh_hits *hits, crsh_meta *meta, const batch_dev *bd, int32_t hit_block, hipStream_t stream);
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
                       const hit_slots_ws &hs, int32_t bundle, const crsh_scene *scene, float t_min,
                       crsh_hits *hits, crsh_meta *meta, const batch_dev *bd, hipStream_t stream);

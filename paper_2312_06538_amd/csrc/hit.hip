@@ -98,6 +98,67 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
     }
 }
 
+// One step of the final tests for a wave: each lane group holds a pair --
+// its triangle (a, b, c: v0, e1, e2 packed), the triangle id, the byte offset
+// of the leaf's first ray slot and the leaf's ray count -- and lane j of the
+// group tests ray j of the leaf.  Counts go to the wave-wide totals, hits to
+// the slot keys.  Called by every lane of the wave.
+template <bool BATCH>
+__device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, const __amdgpu_buffer_rsrc_t &dir_r,
+                                         const float4 &a, const float4 &b, float tc, uint32_t tri_id,
+                                         uint32_t ray_off, uint32_t cnt, uint32_t j, uint32_t l,
+                                         unsigned long long *keys, uint64_t &tests, uint64_t &upass,
+                                         uint64_t &uvpass)
+{
+    const uint32_t ro = ray_off + j * 16u;
+    bool ok = j < cnt;
+    const float4 ro4 = buf_load4(org_r, ro);
+    const float4 rd4 = buf_load4(dir_r, ro);
+    tri_t tr;
+    tr.v0 = mk(a.x, a.y, a.z);
+    tr.e1 = mk(a.w, b.x, b.y);
+    tr.e2 = mk(b.z, b.w, tc);
+    // a padded slot's NaN t_min accepts nothing; it only must not count as a
+    // test
+    if (BATCH) ok = ok & (__float_as_uint(rd4.w) != PAD_SLOT);
+    const uint64_t okm = ballot(ok);
+    tests += (uint64_t)__popcll(okm);
+    const f3 D = mk(rd4.x, rd4.y, rd4.z);
+    mt_head h;
+    const uint64_t mm = mt_first_half(mk(ro4.x, ro4.y, ro4.z), D, tr, h) & okm;
+    // a wave-uniform branch: the wave runs the second half only if one of
+    // its lanes needs it (every lane computes it; the masks keep the lanes
+    // that needed it)
+    if (mm != 0) {
+        float th;
+        bool pu, puv, hit;
+        mt_second_half(D, rd4.w, ro4.w, tr, h, th, pu, puv, hit);
+        upass += (uint64_t)__popcll(ballot(pu) & mm);
+        uvpass += (uint64_t)__popcll(ballot(puv) & mm);
+        if ((ballot(hit) & mm) >> l & 1u) atomicMin(&keys[ro >> 4], hit_key(th, tri_id));
+    }
+}
+
+// The wave totals of a final-test kernel added to meta (s_red: [3][waves]).
+__device__ __forceinline__ void hit_counts(uint64_t (*s_red)[256 / WAVE], uint32_t wib, uint32_t l, uint64_t tests,
+                                           uint64_t upass, uint64_t uvpass, crsh_meta *meta)
+{
+    if (l == 0) {
+        s_red[0][wib] = tests;
+        s_red[1][wib] = upass;
+        s_red[2][wib] = uvpass;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint64_t tot = 0;
+        for (uint32_t i = 0; i < blockDim.x / WAVE; ++i) tot += s_red[threadIdx.x][i];
+        unsigned long long *dst = threadIdx.x == 0 ? (unsigned long long *)&meta->final_tests
+                                : threadIdx.x == 1 ? (unsigned long long *)&meta->final_u_pass
+                                                   : (unsigned long long *)&meta->final_uv_pass;
+        if (tot) atomicAdd(dst, (unsigned long long)tot);
+    }
+}
+
 // Slots in use: the plain form's sorted rays, or B per level-1 node.  PACKED:
 // the level-1 pairs are packed words in ptri (node above the low
 // CRSH_PACKED_TRI_BITS, triangle minus tri_base below; pnode unused).
@@ -141,7 +202,6 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
     const __amdgpu_buffer_rsrc_t org_r = make_rsrc(RO, (uint64_t)ns * 16u);
     const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * 16u);
     const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
-    const uint32_t jo = j * 16u;
     float4(*rec)[WAVE] = s_rec[wib];
     uint64_t tests = 0, upass = 0, uvpass = 0;   // wave-wide counts
     for (uint64_t c0 = wave * WAVE; c0 < np; c0 += nwaves * WAVE) {
@@ -179,50 +239,119 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
             const float4 a = rec[0][src];
             const float4 b = rec[1][src];
             const float4 c = rec[2][src];
-            const uint32_t cnt = __float_as_uint(c.w);
-            const uint32_t ro = __float_as_uint(c.z) + jo;
-            bool ok = j < cnt;
-            const float4 ro4 = buf_load4(org_r, ro);
-            const float4 rd4 = buf_load4(dir_r, ro);
-            tri_t tr;
-            tr.v0 = mk(a.x, a.y, a.z);
-            tr.e1 = mk(a.w, b.x, b.y);
-            tr.e2 = mk(b.z, b.w, c.x);
-            // a padded slot's NaN t_min accepts nothing; it only must not
-            // count as a test
-            if (BATCH) ok = ok & (__float_as_uint(rd4.w) != PAD_SLOT);
-            const uint64_t okm = ballot(ok);
-            tests += (uint64_t)__popcll(okm);
-            const f3 D = mk(rd4.x, rd4.y, rd4.z);
-            mt_head h;
-            const uint64_t mm = mt_first_half(mk(ro4.x, ro4.y, ro4.z), D, tr, h) & okm;
-            // a wave-uniform branch: the wave runs the second half only if
-            // one of its lanes needs it (every lane computes it; the masks
-            // keep the lanes that needed it)
-            if (mm != 0) {
-                float th;
-                bool pu, puv, hit;
-                mt_second_half(D, rd4.w, ro4.w, tr, h, th, pu, puv, hit);
-                upass += (uint64_t)__popcll(ballot(pu) & mm);
-                uvpass += (uint64_t)__popcll(ballot(puv) & mm);
-                if ((ballot(hit) & mm) >> l & 1u) atomicMin(&keys[ro >> 4], hit_key(th, __float_as_uint(c.y)));
+            hit_step<BATCH>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), __float_as_uint(c.z),
+                            __float_as_uint(c.w), j, l, keys, tests, upass, uvpass);
+        }
+    }
+    hit_counts(s_red, wib, l, tests, upass, uvpass, meta);
+}
+
+// Final tests of the level-1 pairs that the level-2 pairs and the level-1
+// pass masks describe (the fused last level: the level-1 pairs are never
+// stored).  Level-2 pair q keeps child j (leaf first(q) + j, first = node * F
+// or the build's record) when bit q * nf + j of `mask` is set (nf: F rounded
+// up to a power of two), the layout the level count writes.  A wave takes
+// runs of 64 level-2 pairs: each lane reads one pair, its pass bits and its
+// triangle into the wave's LDS records, the run's (pair, child) items are
+// listed in LDS in (pair, child) order -- the order of the level-1 pairs the
+// emit would have written -- and tested 64 / G items at a time as k_hit
+// tests pairs, up to MASKED_ITEMS items per round.
+// (240 items keep a 256-thread block under 20 KiB of LDS: eight blocks per
+// compute unit, the one round of blocks the launch assumes)
+constexpr uint32_t MASKED_ITEMS = 240;
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ RO, const float4 *__restrict__ RD,
+                                                    const float4 *__restrict__ tri,
+                                                    const uint32_t *__restrict__ ptri2,
+                                                    const uint32_t *__restrict__ pnode2, uint64_t cap2,
+                                                    const uint32_t *__restrict__ mask, uint32_t nf, uint32_t F,
+                                                    uint32_t B, uint32_t log2G, unsigned long long *keys,
+                                                    crsh_meta *meta, uint32_t slot_cap, uint32_t m, batch_dev bd)
+{
+    __shared__ uint64_t s_red[3][256 / WAVE];
+    __shared__ float4 s_rec[256 / WAVE][3][WAVE];           // [wave][record word][pair of the run]
+    __shared__ uint2 s_item[256 / WAVE][MASKED_ITEMS];     // [wave][item]: pair of the run, leaf
+    const uint32_t ns = BATCH ? batch_slots(meta, B, slot_cap) : min(meta->n_rays, slot_cap);
+    uint64_t n2 = meta->n_levels >= 2 ? meta->pairs[1] : 0;
+    n2 = n2 < cap2 ? n2 : cap2;
+    const uint32_t n1 = meta->level_cnt[0];
+    const uint32_t off2 = meta->level_off[1];
+    const uint32_t np2 = meta->level_cnt[1];
+    const uint32_t l = lane_id();
+    const uint32_t G = 1u << log2G;
+    const uint32_t slot = l >> log2G;        // item of this lane within a step
+    const uint32_t j = l & (G - 1);          // ray of the leaf
+    const uint32_t per_wave = WAVE >> log2G;
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
+    const __amdgpu_buffer_rsrc_t org_r = make_rsrc(RO, (uint64_t)ns * 16u);
+    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * 16u);
+    const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
+    const uint32_t nfm = nf >= 32 ? ~0u : (1u << nf) - 1u;
+    float4(*rec)[WAVE] = s_rec[wib];
+    uint2 *items = s_item[wib];
+    uint64_t tests = 0, upass = 0, uvpass = 0;   // wave-wide counts
+    for (uint64_t c0 = wave * WAVE; c0 < n2; c0 += nwaves * WAVE) {
+        const uint32_t cn = __builtin_amdgcn_readfirstlane((uint32_t)min(n2 - c0, (uint64_t)WAVE));
+        uint32_t my_t = 0u, bits = 0u, first = 0u;
+        if (l < cn) {
+            const uint64_t q = c0 + l;
+            my_t = ptri2[q];
+            const uint32_t node = pnode2[q];
+            const uint64_t bit = q * nf;          // nf divides 32: the bits lie in one word
+            bits = (mask[bit >> 5] >> (uint32_t)(bit & 31u)) & nfm;
+            if constexpr (BATCH) {
+                first = node < np2 ? bd.node_first[off2 + node] : 0u;
+                if (node >= np2) bits = 0u;
+            } else {
+                first = node * F;
+            }
+            if (my_t >= m) bits = 0u;
+        }
+        const uint32_t tb = bits ? my_t * 48u : 0u;
+        const float4 ta = buf_load4(tris_r, tb);
+        const float4 tbv = buf_load4(tris_r, tb + 16u);
+        const float tc = buf_load1(tris_r, tb + 32u);
+        const uint32_t cnt = (uint32_t)__popc(bits);
+        const uint32_t incl = wave_incl_scan(cnt);
+        const uint32_t excl = incl - cnt;
+        const uint32_t total = __builtin_amdgcn_readlane(incl, WAVE - 1);
+        __builtin_amdgcn_wave_barrier();          // the previous run's reads come first
+        rec[0][l] = ta;
+        rec[1][l] = tbv;
+        rec[2][l] = make_float4(tc, __uint_as_float(my_t), 0.0f, 0.0f);
+        for (uint32_t rb = 0; rb < total; rb += MASKED_ITEMS) {
+            // this round's items: the lane's (pair, child) items with index
+            // in [rb, rb + MASKED_ITEMS), in (pair, child) order
+            __builtin_amdgcn_wave_barrier();      // the previous round's reads come first
+            // an item holds the pair's lane and the leaf's ray count (bits 8
+            // and up), and the byte offset of the leaf's first ray slot (slots
+            // below 2^27: 32-bit arithmetic)
+            uint32_t bl = bits, idx = excl;
+            while (bl) {
+                const uint32_t leaf = first + (uint32_t)__builtin_ctz(bl);
+                bl &= bl - 1u;
+                const uint32_t fs = leaf * B;
+                const uint32_t rc = leaf < n1 && fs < ns ? min(B, ns - fs) : 0u;
+                if (idx - rb < MASKED_ITEMS) items[idx - rb] = make_uint2(l | (rc << 8), rc ? fs * 16u : 0u);
+                ++idx;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const uint32_t nit = min(MASKED_ITEMS, total - rb);
+            for (uint32_t k = 0; k < nit; k += per_wave) {
+                const uint32_t src = k + slot;
+                const uint2 it = items[src < nit ? src : 0u];
+                const uint32_t p = it.x & 63u;
+                const float4 a = rec[0][p];
+                const float4 b = rec[1][p];
+                const float4 c = rec[2][p];
+                hit_step<BATCH>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), it.y, src < nit ? it.x >> 8 : 0u, j,
+                                l, keys, tests, upass, uvpass);
             }
         }
     }
-    if (l == 0) {
-        s_red[0][wib] = tests;
-        s_red[1][wib] = upass;
-        s_red[2][wib] = uvpass;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        uint64_t tot = 0;
-        for (uint32_t i = 0; i < blockDim.x / WAVE; ++i) tot += s_red[threadIdx.x][i];
-        unsigned long long *dst = threadIdx.x == 0 ? (unsigned long long *)&meta->final_tests
-                                : threadIdx.x == 1 ? (unsigned long long *)&meta->final_u_pass
-                                                   : (unsigned long long *)&meta->final_uv_pass;
-        if (tot) atomicAdd(dst, (unsigned long long)tot);
-    }
+    hit_counts(s_red, wib, l, tests, upass, uvpass, meta);
 }
 
 struct hit_out {
@@ -333,6 +462,30 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
         k_hit<false, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                             level1->capacity, (uint32_t)bundle, log2G, hits->tkey,
                                                             meta, hs.slots, scene->m, 0u);
+}
+
+void hit_masked_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level2,
+                       const uint32_t *mask, int32_t merge, int32_t bundle, const crsh_scene *scene,
+                       crsh_hits *hits, crsh_meta *meta, const batch_dev *bd, int32_t hit_block, hipStream_t stream)
+{
+    (void)sorted;
+    uint32_t nf = 2;
+    while (nf < (uint32_t)merge) nf *= 2;
+    uint32_t log2G = 0;
+    while ((1u << log2G) < (uint32_t)bundle) ++log2G;
+    const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;
+    const batch_dev b = bd ? *bd : batch_dev{};
+    prof_scope ps("k_hit", stream);
+    if (bd)
+        k_hit_masked<true><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level2->tri, level2->node,
+                                                           level2->capacity, mask, nf, (uint32_t)merge,
+                                                           (uint32_t)bundle, log2G, hs.keys, meta, hs.slots,
+                                                           scene->m, b);
+    else
+        k_hit_masked<false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level2->tri, level2->node,
+                                                            level2->capacity, mask, nf, (uint32_t)merge,
+                                                            (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
+                                                            scene->m, b);
 }
 
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
