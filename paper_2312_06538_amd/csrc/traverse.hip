@@ -535,11 +535,9 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
     constexpr uint32_t TILE_OUT = TILE * NF;
     constexpr uint32_t R = PPT / LEVEL_PPT;    // count tiles per emit tile
     static_assert(PPT % LEVEL_PPT == 0, "whole count tiles");
-    constexpr uint32_t NFR = BATCH ? CRSH_MAX_FRAMES : 1u;
     __shared__ uint32_t s_scan[LEVEL_THREADS / WAVE];
     __shared__ uint32_t s_tri[TILE_OUT];
     __shared__ uint32_t s_node[TILE_OUT];
-    __shared__ uint32_t s_fbp[NFR], s_fbc[NFR];   // batch: each frame's first node on the parent / child level
     const uint32_t nl = meta->n_levels;
     if ((uint32_t)parent_level > nl) return;
     const pairs_dev in = P.p[parent_level - 1];
@@ -549,21 +547,8 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
     nin = nin < in.cap ? nin : in.cap;
     const uint64_t ctiles = (nin + LEVEL_TILE - 1) / LEVEL_TILE;
     const uint64_t ntiles = (nin + TILE - 1) / TILE;
+    const uint32_t offp = meta->level_off[parent_level - 1];
     const uint32_t np = meta->level_cnt[parent_level - 1];
-    // Batched form: a parent's first child follows from its frame's first
-    // nodes on the two levels (frames lay their levels out as the plain
-    // form does): first = child base + (parent - parent base) * F.  The
-    // bases go to LDS, and the frame of a parent is a search there instead
-    // of a dependent load of the build's record.
-    uint32_t nfr = 1;
-    if constexpr (BATCH) {
-        nfr = bd.n_frames < NFR ? bd.n_frames : NFR;
-        for (uint32_t f = threadIdx.x; f < nfr; f += LEVEL_THREADS) {
-            s_fbp[f] = bd.fm[f].level_base[parent_level - 1];
-            s_fbc[f] = bd.fm[f].level_base[parent_level - 2];
-        }
-        __syncthreads();
-    }
     // pass mask (NF bits per parent pair, PPT pairs: bits of one packed
     // word), survivor count and output offset of emit tile T
     auto tile_head = [&](uint64_t T, uint32_t &mask, uint32_t &cnt, uint64_t &off) {
@@ -600,16 +585,15 @@ __global__ __launch_bounds__(LEVEL_THREADS) void k_level_emit(int32_t parent_lev
             par[k] = 0u;
             if (live) pair_get<PACKED>(in, q0 + k, tri[k], par[k]);
         }
-        // first child of each parent: p * F, or (batched form) from its
-        // frame's bases
+        // first child of each parent: p * F, or (batched form) the build's
+        // record, requested here so that its latency overlaps the scan
         uint32_t first[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             first[k] = par[k] * F;
             if constexpr (BATCH) {
                 const bool live = ((mask >> (k * NF)) & ((1u << NF) - 1u)) != 0u && par[k] < np;
-                const uint32_t f = live ? last_at_most(nfr, par[k], [&](uint32_t g) { return s_fbp[g]; }) : 0u;
-                first[k] = live ? s_fbc[f] + (par[k] - s_fbp[f]) * F : 0u;
+                first[k] = live ? bd.node_first[offp + par[k]] : 0u;
             }
         }
         const uint64_t nt = tile + gridDim.x;
