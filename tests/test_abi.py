@@ -122,6 +122,24 @@ def test_invalid_arguments_are_rejected_on_the_host():
     h = X.Hits(1, 1, 1, 1, 1, 100)
     assert L.crsh_closest_hit(ctypes.byref(r), 1, 0, ctypes.byref(pt[0]), ctypes.byref(sc), ctypes.c_float(1e-4),
                               ctypes.byref(h), 1, 1, 1 << 30, None) == X.ERR_INVALID
+    # fused last level: level-1 storage without capacity, merge factor 1, no level-2 table, small workspace
+    lt = X.PairTable()
+    lt[0] = X.Pairs(1, 1, 0)
+    lt[1] = X.Pairs(1, 1, 10)
+    assert L.crsh_leaf_hit(ctypes.byref(r), 1, 8, 4, ctypes.byref(n), lt, ctypes.byref(sc), ctypes.c_float(1e-4),
+                           ctypes.byref(h), 1, 1, 1 << 30, None) == X.ERR_INVALID
+    assert "level-1" in X.last_error()
+    lt[0] = X.Pairs(1, 1, 10)
+    assert L.crsh_leaf_hit(ctypes.byref(r), 1, 8, 1, ctypes.byref(n), lt, ctypes.byref(sc), ctypes.c_float(1e-4),
+                           ctypes.byref(h), 1, 1, 1 << 30, None) == X.ERR_INVALID
+    assert "merge" in X.last_error()
+    assert L.crsh_leaf_hit(ctypes.byref(r), 1, 8, 4, ctypes.byref(n), lt, ctypes.byref(sc), ctypes.c_float(1e-4),
+                           ctypes.byref(h), 1, 1, 16, None) == X.ERR_INVALID
+    assert "workspace" in X.last_error()
+    lt[1] = X.Pairs(0, 0, 0)
+    assert L.crsh_leaf_hit(ctypes.byref(r), 1, 8, 4, ctypes.byref(n), lt, ctypes.byref(sc), ctypes.c_float(1e-4),
+                           ctypes.byref(h), 1, 1, 1 << 30, None) == X.ERR_INVALID
+    assert "level-2" in X.last_error()
     assert L.crsh_profile_next(None, 0, 1, 1) == X.ERR_INVALID
 
 

@@ -364,7 +364,7 @@ def test_spherical_keys_bit_exact():
     assert np.array_equal(g["hit"][0], o["hits"][0])
 
 
-LEAF_SHAPES = [(16, 4, 5), (8, 2, 3), (32, 8, 4), (5, 3, 4), (1, 16, 3), (12, 4, 2), (16, 4, 1)]
+LEAF_SHAPES = [(16, 4, 5), (8, 2, 3), (32, 8, 4), (5, 3, 4), (1, 16, 3), (12, 4, 2), (16, 4, 1), (4, 4, 7)]
 
 
 def _check_fused(g, o):
@@ -397,7 +397,8 @@ def test_leaf_hit_matches_oracle(name):
 @pytest.mark.parametrize("B,F,n", LEAF_SHAPES)
 def test_leaf_hit_shapes(B, F, n):
     """Bundles that do not fill a lane group, merge factors that do not fill
-    a power of two, single-level hierarchies (only the stored path)."""
+    a power of two, single-level hierarchies (only the stored path), and
+    level-1 runs of 4096 nodes, too long for the count's LDS copy."""
     import dataclasses
     base, kw = small("refl_96")
     wl = dataclasses.replace(workload(base, **kw), B=B, F=F, n=n)
