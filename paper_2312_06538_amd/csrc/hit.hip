@@ -99,43 +99,49 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
 }
 
 // One step of the final tests for a wave: each lane group holds a pair --
-// its triangle (a, b, c: v0, e1, e2 packed), the triangle id, the byte offset
-// of the leaf's first ray slot and the leaf's ray count -- and lane j of the
-// group tests ray j of the leaf.  Counts go to the wave-wide totals, hits to
-// the slot keys.  Called by every lane of the wave.
-template <bool BATCH>
+// its triangle (a, b, c: v0, e1, e2 packed), the triangle id and the byte
+// offset of the leaf's first ray slot -- and lane j of the group tests ray j
+// of the leaf.  `live` is the wave mask of the lanes whose test is one of the
+// pair's.  A lane outside it may still read a ray: that of a slot past the
+// leaf's rays, or a zero ray (a padded slot, or an offset past the slot
+// array's end, which reads zeros); a zero ray has a zero determinant and
+// fails the first half, so only the lanes j >= B of a group wider than the
+// bundle need the mask.  COUNT: the step counts its tests (the lanes of
+// `live`, less the padded slots of the batched form); without it the caller
+// counts them.  Hits go to the slot keys.  Called by every lane of the wave.
+template <bool BATCH, bool COUNT>
 __device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, const __amdgpu_buffer_rsrc_t &dir_r,
                                          const float4 &a, const float4 &b, float tc, uint32_t tri_id,
-                                         uint32_t ray_off, uint32_t cnt, uint32_t j, uint32_t l,
+                                         uint32_t ray_off, uint64_t live, uint32_t j,
                                          unsigned long long *keys, uint64_t &tests, uint64_t &upass,
                                          uint64_t &uvpass)
 {
     const uint32_t ro = ray_off + j * 16u;
-    bool ok = j < cnt;
     const float4 ro4 = buf_load4(org_r, ro);
     const float4 rd4 = buf_load4(dir_r, ro);
     tri_t tr;
     tr.v0 = mk(a.x, a.y, a.z);
     tr.e1 = mk(a.w, b.x, b.y);
     tr.e2 = mk(b.z, b.w, tc);
-    // a padded slot's NaN t_min accepts nothing; it only must not count as a
-    // test
-    if (BATCH) ok = ok & (__float_as_uint(rd4.w) != PAD_SLOT);
-    const uint64_t okm = ballot(ok);
-    tests += (uint64_t)__popcll(okm);
+    if constexpr (COUNT) {
+        // a padded slot's NaN t_min accepts nothing; it only must not count
+        // as a test
+        if (BATCH) live &= ballot(__float_as_uint(rd4.w) != PAD_SLOT);
+        tests += (uint64_t)__popcll(live);
+    }
     const f3 D = mk(rd4.x, rd4.y, rd4.z);
     mt_head h;
-    const uint64_t mm = mt_first_half(mk(ro4.x, ro4.y, ro4.z), D, tr, h) & okm;
+    const uint64_t mm = mt_first_half(mk(ro4.x, ro4.y, ro4.z), D, tr, h) & live;
     // a wave-uniform branch: the wave runs the second half only if one of
     // its lanes needs it (every lane computes it; the masks keep the lanes
     // that needed it)
     if (mm != 0) {
         float th;
-        bool pu, puv, hit;
+        uint64_t pu, puv, hit;
         mt_second_half(D, rd4.w, ro4.w, tr, h, th, pu, puv, hit);
-        upass += (uint64_t)__popcll(ballot(pu) & mm);
-        uvpass += (uint64_t)__popcll(ballot(puv) & mm);
-        if ((ballot(hit) & mm) >> l & 1u) atomicMin(&keys[ro >> 4], hit_key(th, tri_id));
+        upass += (uint64_t)__popcll(pu & mm);
+        uvpass += (uint64_t)__popcll(puv & mm);
+        if (__builtin_amdgcn_inverse_ballot_w64(hit & mm)) atomicMin(&keys[ro >> 4], hit_key(th, tri_id));
     }
 }
 
@@ -162,29 +168,34 @@ __device__ __forceinline__ void hit_counts(uint64_t (*s_red)[256 / WAVE], uint32
 // Slots in use: the plain form's sorted rays, or B per level-1 node.  PACKED:
 // the level-1 pairs are packed words in ptri (node above the low
 // CRSH_PACKED_TRI_BITS, triangle minus tri_base below; pnode unused).
+// leaf_cnt (batched form): the build's per-node record of the leaves, whose
+// low bits hold the leaf's ray count.
 //
 // A wave takes runs of 64 consecutive pairs before the grid stride
 // (neighbouring level-1 pairs share their triangle -- siblings of one
 // parent pair -- or their leaves, so a run finds its rays in the vector L1
 // cache).  Each lane reads one pair of the run, its triangle, and writes a
-// 64-byte record to the wave's LDS slice: the triangle (v0, e1, e2), the
-// triangle id, the byte offset of the leaf's first ray slot and the number
-// of rays of the leaf.  The run is then tested 64 / G pairs at a time, each
-// lane group reading its pair's record from LDS (the 16 lanes of a group
-// read the same address), so the vector memory path carries only the rays.
-// Rays are read with buffer loads on 32-bit byte offsets (the host bounds
-// them; a read past the end returns zeros), origins and directions from
-// their own arrays, so each of the two loads of a step covers 256
-// contiguous bytes per pair.  The test is split where most
-// of its cost lies: every lane computes the division-free first half, and
-// the wave runs the rest (the division included) only when one of its
-// lanes can still pass.
+// 48-byte record to the wave's LDS slice: the triangle (v0, e1, e2), the
+// triangle id and the byte offset of the leaf's first ray slot (past the
+// slot array for a pair out of range, so that its rays read as zeros).  The
+// run is then tested 64 / G pairs at a time, each lane group reading its
+// pair's record from LDS (the 16 lanes of a group read the same address), so
+// the vector memory path carries only the rays.  The tests are counted per
+// pair when the record is written (the leaf's rays), not per step.  Rays are
+// read with buffer loads on 32-bit byte offsets (the host bounds them; a read
+// past the end returns zeros), origins and directions from their own
+// arrays, so each of the two loads of a step covers 256 contiguous bytes per
+// pair.  The test is split where most of its cost lies: every lane computes
+// the division-free first half, and the wave runs the rest (the division
+// included) only when one of its lanes can still pass.
+constexpr uint32_t RAY_OFF_NONE = 0xFFFF0000u;   // above every slot array (2^31 bytes at most)
 template <bool BATCH, bool PACKED>
 __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, const float4 *__restrict__ RD,
                                              const float4 *__restrict__ tri,
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
                                              uint64_t cap1, uint32_t B, uint32_t log2G, unsigned long long *keys,
-                                             crsh_meta *meta, uint32_t slot_cap, uint32_t m, uint32_t tri_base)
+                                             crsh_meta *meta, uint32_t slot_cap, uint32_t m, uint32_t tri_base,
+                                             const uint32_t *__restrict__ leaf_cnt)
 {
     __shared__ uint64_t s_red[3][256 / WAVE];
     __shared__ float4 s_rec[256 / WAVE][3][WAVE];    // [wave][record word][pair of the run]
@@ -196,6 +207,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
     const uint32_t slot = l >> log2G;        // pair of this lane within a step
     const uint32_t j = l & (G - 1);          // ray of the leaf
     const uint32_t per_wave = WAVE >> log2G;
+    const uint64_t live = ballot(j < B);     // the lanes of a group that test a ray of the leaf
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);   // scalar: so is the run arithmetic
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
@@ -203,12 +215,13 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
     const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * 16u);
     const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
     float4(*rec)[WAVE] = s_rec[wib];
+    uint32_t my_tests = 0;                   // this lane's pairs: rays of their leaves
     uint64_t tests = 0, upass = 0, uvpass = 0;   // wave-wide counts
     for (uint64_t c0 = wave * WAVE; c0 < np; c0 += nwaves * WAVE) {
         const uint32_t cn = __builtin_amdgcn_readfirstlane((uint32_t)min(np - c0, (uint64_t)WAVE));
-        uint32_t my_t = 0u, my_rb = 0u, my_cnt = 0u;
+        uint32_t my_t = 0u, my_rb = RAY_OFF_NONE, leaf = 0u;
+        bool valid = false;
         if (l < cn) {
-            uint32_t leaf;
             if constexpr (PACKED) {
                 const uint32_t w = ptri[c0 + l];
                 my_t = tri_base + (w & ((1u << CRSH_PACKED_TRI_BITS) - 1u));
@@ -221,28 +234,34 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
             // of range)
             const uint64_t first = (uint64_t)leaf * B;
             if (my_t < m && first < ns) {
-                my_cnt = (uint32_t)min((uint64_t)B, ns - first);
+                valid = true;
                 my_rb = (uint32_t)first * 16u;
             }
         }
-        const uint32_t tb = my_cnt ? my_t * 48u : 0u;
+        const uint32_t tb = valid ? my_t * 48u : 0u;
         const float4 ta = buf_load4(tris_r, tb);
         const float4 tbv = buf_load4(tris_r, tb + 16u);
         const float tc = buf_load1(tris_r, tb + 32u);
+        if (valid) {
+            uint32_t cnt = min(B, ns - leaf * B);
+            if constexpr (BATCH) cnt = min(cnt, leaf_cnt[leaf] & INFO_COUNT_MASK);
+            my_tests += cnt;
+        }
         __builtin_amdgcn_wave_barrier();          // the previous run's reads come first
         rec[0][l] = ta;
         rec[1][l] = tbv;
-        rec[2][l] = make_float4(tc, __uint_as_float(my_t), __uint_as_float(my_rb), __uint_as_float(my_cnt));
+        rec[2][l] = make_float4(tc, __uint_as_float(my_t), __uint_as_float(my_rb), 0.0f);
         __builtin_amdgcn_wave_barrier();
         for (uint32_t k = 0; k < cn; k += per_wave) {
             const uint32_t src = k + slot;
             const float4 a = rec[0][src];
             const float4 b = rec[1][src];
             const float4 c = rec[2][src];
-            hit_step<BATCH>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), __float_as_uint(c.z),
-                            __float_as_uint(c.w), j, l, keys, tests, upass, uvpass);
+            hit_step<BATCH, false>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), __float_as_uint(c.z), live, j,
+                                   keys, tests, upass, uvpass);
         }
     }
+    tests = wave_sum((uint64_t)my_tests);
     hit_counts(s_red, wib, l, tests, upass, uvpass, meta);
 }
 
@@ -346,8 +365,9 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
                 const float4 a = rec[0][p];
                 const float4 b = rec[1][p];
                 const float4 c = rec[2][p];
-                hit_step<BATCH>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), it.y, src < nit ? it.x >> 8 : 0u, j,
-                                l, keys, tests, upass, uvpass);
+                const uint32_t cnt = src < nit ? it.x >> 8 : 0u;
+                hit_step<BATCH, true>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), it.y, ballot(j < cnt), j, keys,
+                                      tests, upass, uvpass);
             }
         }
     }
@@ -453,15 +473,15 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
     if (bd)
         k_hit<true, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                            level1->capacity, (uint32_t)bundle, log2G, hs.keys, meta,
-                                                           hs.slots, scene->m, 0u);
+                                                           hs.slots, scene->m, 0u, bd->node_info);
     else if (packed)
         k_hit<false, true><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, nullptr, level1->capacity,
                                                            (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
-                                                           scene->m, tri_base);
+                                                           scene->m, tri_base, nullptr);
     else
         k_hit<false, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                             level1->capacity, (uint32_t)bundle, log2G, hits->tkey,
-                                                            meta, hs.slots, scene->m, 0u);
+                                                            meta, hs.slots, scene->m, 0u, nullptr);
 }
 
 void hit_masked_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level2,

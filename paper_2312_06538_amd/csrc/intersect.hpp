@@ -118,11 +118,11 @@ __device__ __forceinline__ uint64_t mt_first_half(f3 O, f3 D, const tri_t &tr, m
 
 // The rest of the test for a ray that mt_first_half let through: the same
 // operations, in the same order, as moller_trumbore after its early checks.
-// The checks passed: pu (u in [0, 1]), puv (and v >= 0, u + v <= 1), hit
-// (and t_min < t < tmax), each implying the ones before; all comparisons are
-// made and combined without short-circuit.
+// The checks passed, as wave masks: pu (u in [0, 1]), puv (and v >= 0,
+// u + v <= 1), hit (and t_min < t < tmax), each implying the ones before; all
+// comparisons are made and combined without short-circuit.
 __device__ __forceinline__ void mt_second_half(f3 D, float t_min, float tmax, const tri_t &tr, const mt_head &h,
-                                               float &tt, bool &pu, bool &puv, bool &hit)
+                                               float &tt, uint64_t &pu, uint64_t &puv, uint64_t &hit)
 {
     const float inv = 1.0f / h.det;
     const float u = h.a * inv;
@@ -130,9 +130,9 @@ __device__ __forceinline__ void mt_second_half(f3 D, float t_min, float tmax, co
     const float v = dot(D, q) * inv;
     const float t = dot(tr.e2, q) * inv;
     tt = t;
-    pu = (u >= 0.0f) & (u <= 1.0f);
-    puv = pu & (v >= 0.0f) & (u + v <= 1.0f);
-    hit = puv & (t > t_min) & (t < tmax);
+    pu = ballot(u >= 0.0f) & ballot(u <= 1.0f);
+    puv = pu & ballot(v >= 0.0f) & ballot(u + v <= 1.0f);
+    hit = puv & ballot(t > t_min) & ballot(t < tmax);
 }
 
 // The same test for the final-test kernel, without early exits: every
