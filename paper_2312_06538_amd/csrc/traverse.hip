@@ -246,18 +246,62 @@ __global__ __launch_bounds__(256) void k_top_emit(const float4 *__restrict__ na,
 }
 
 // ----------------------------------------------------------- lower levels
+// Lane i of each quad of four lanes gets the value of lane (i / NF) * NF + r
+// of its quad (NF <= 4: the NF lanes of a group share one source lane).  r
+// is a constant once the slice loop is unrolled; the switch folds away.
+template <uint32_t NF>
+__device__ __forceinline__ uint32_t quad_pick(uint32_t v, uint32_t r)
+{
+    static_assert(NF == 2 || NF == 4, "groups within a quad");
+#define CRSH_QP(R) ((((0 / NF) * NF + (R)) & 3) | ((((1 / NF) * NF + (R)) & 3) << 2) | \
+                    ((((2 / NF) * NF + (R)) & 3) << 4) | ((((3 / NF) * NF + (R)) & 3) << 6))
+    switch (r) {
+    case 0: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CRSH_QP(0), 0xF, 0xF, true);
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CRSH_QP(1), 0xF, 0xF, true);
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CRSH_QP(2), 0xF, 0xF, true);
+    default: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CRSH_QP(3), 0xF, 0xF, true);
+    }
+#undef CRSH_QP
+}
+template <uint32_t NF>
+__device__ __forceinline__ float quad_pick(float v, uint32_t r)
+{
+    return __uint_as_float(quad_pick<NF>(__float_as_uint(v), r));
+}
+// The same through the other DPP builtin: a second, separate copy of a value
+// quad_pick already took (the compiler folds a DPP move into the one
+// instruction that uses it, and would merge two identical moves).
+template <uint32_t NF>
+__device__ __forceinline__ float quad_pick_again(float v, uint32_t r)
+{
+#define CRSH_QP(R) ((((0 / NF) * NF + (R)) & 3) | ((((1 / NF) * NF + (R)) & 3) << 2) | \
+                    ((((2 / NF) * NF + (R)) & 3) << 4) | ((((3 / NF) * NF + (R)) & 3) << 6))
+    const int x = (int)__float_as_uint(v);
+    switch (r) {
+    case 0: return __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(0, x, CRSH_QP(0), 0xF, 0xF, true));
+    case 1: return __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(0, x, CRSH_QP(1), 0xF, 0xF, true));
+    case 2: return __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(0, x, CRSH_QP(2), 0xF, 0xF, true));
+    default: return __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(0, x, CRSH_QP(3), 0xF, 0xF, true));
+    }
+#undef CRSH_QP
+}
+
 // Count pass with one (parent pair, child) test per lane.
 // A tile of LEVEL_TILE parent pairs is tested in NF slices of LEVEL_TILE /
 // NF parents; in a slice the NF lanes of a parent test its NF consecutive
 // children, and the wave's ballot is directly the pass bits of its 64 / NF
 // parents in the mask layout of the count pass (NF bits per parent,
 // parent-major).  A block of COUNT_THREADS takes COUNT_TPS tiles per step.
-// What the NF lanes of a parent share -- the parent node and the triangle
-// sphere -- is read once: each lane reads the pair and sphere of one of
-// the wave's 64 parents of the tile into a wave-private LDS record, and the
-// lanes of a slice read their parent's record from there.  The next step's
-// pairs and spheres are requested before a step is tested (pairs two steps
-// ahead, since the sphere read depends on them).
+// What the NF lanes of a parent share -- the parent's children and the
+// triangle sphere -- is read once: each lane reads the pair and sphere of
+// one of the wave's 64 parents of the tile.  For NF <= 4 that lane is one
+// of the parent's NF lanes (lane NF * p + r holds parent p of slice r), and
+// in slice r the others take the values from it within their quad of lanes
+// (a DPP broadcast, no LDS); for larger NF the lanes put them in a
+// wave-private LDS record and the lanes of a slice read their parent's
+// record from there.  The next step's pairs and spheres are requested
+// before a step is tested (pairs two steps ahead, since the sphere read
+// depends on them).
 //
 // Child nodes (36 bytes a test) come from LDS where they can: the
 // descendants of one top-level node on the child level are a contiguous
@@ -289,11 +333,14 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     constexpr uint32_t NW = COUNT_THREADS / WAVE;    // waves per block
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     constexpr uint32_t WN = STAGED ? COUNT_WINDOW : 1u;
+    constexpr bool QB = NF <= 4;             // parent values by quad broadcast
+    constexpr uint32_t NR = QB ? 1u : NW;    // wave records in LDS
     __shared__ uint32_t s_red32[2][NW];
     __shared__ uint64_t s_red[NW];
-    __shared__ float4 s_sph[NW][WAVE];      // [wave][record]
-    __shared__ uint32_t s_first[NW][WAVE];  // first child (level-local)
-    __shared__ uint32_t s_cnt[NW][WAVE];    // children (0: no parent)
+    __shared__ uint32_t s_head[2];          // the step's first pair: 16 x (first child, children)
+    __shared__ float4 s_sph[NR][WAVE];      // [wave][record]
+    __shared__ uint32_t s_first[NR][WAVE];  // 16 x first child (level-local)
+    __shared__ uint32_t s_n[NR][WAVE];      // 16 x children below nk (0: none)
     __shared__ float4 s_wa[WN], s_wb[WN];   // the staged run of child nodes
     __shared__ float s_ws[WN];
     const uint32_t nl = meta->n_levels;
@@ -316,10 +363,13 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     const uint32_t half = wb / WPT;                   // tile of the step
     const uint32_t tw = wb % WPT;                     // wave of the tile
     const uint32_t j = l % NF;              // child of this lane in every slice
+    const uint32_t j16 = j * 16u;
+    const uint32_t mlane = l == 0 ? 0u : 0x80000000u;   // mask stores: past the range but for lane 0
     const uint32_t pi = l / NF;             // parent of this lane within the wave's slice
-    // the parent whose pair and sphere this lane reads: slice l / PW,
-    // parent l % PW of the wave's share of it
-    const uint32_t own = (l / PW) * PR + tw * PW + l % PW;
+    // the parent whose pair and sphere this lane reads: quad broadcast,
+    // slice j, parent pi of the wave's share of it; else slice l / PW,
+    // parent l % PW
+    const uint32_t own = QB ? j * PR + tw * PW + pi : (l / PW) * PR + tw * PW + l % PW;
     // nodes from offk + ch for ch < nk, by 32-bit byte offsets
     const uint64_t nodes = (uint64_t)offk + nk;
     const __amdgpu_buffer_rsrc_t ra = make_rsrc(na, nodes * 16u);
@@ -336,57 +386,88 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     // STAGED: the host's bound on the runs of this level fits the window
     const bool staged = STAGED && (BATCH || run_of(nl) <= WN);
     uint32_t wlo = NONE, wlen = 0;          // staged run (block-uniform)
+    uint32_t wlo16 = 0u, wlen16 = 0u;       // the same, x 16
     uint32_t ulo = NONE, ulen = 0;          // batch: a frame's nodes whose runs do not fit
+    // the pair this lane reads for a step, by buffer loads over the tile's
+    // pairs (a step past the end reads nothing): no branch, so that the
+    // loads of every step count alike where the compiler places its waits
     auto load_pair = [&](uint64_t step, uint32_t &tri, uint32_t &par) {
-        const uint64_t q = (step * COUNT_TPS + half) * LEVEL_TILE + own;
-        tri = 0u;
-        par = NONE;
-        if (q < nin) pair_get<PACKED>(in, q, tri, par);
+        const uint64_t q0 = (step * COUNT_TPS + half) * LEVEL_TILE;
+        const uint32_t nq = (uint32_t)(q0 < nin ? min(nin - q0, (uint64_t)LEVEL_TILE) : 0u);
+        const __amdgpu_buffer_rsrc_t rt = make_rsrc(in.tri + q0, (uint64_t)nq * 4u);
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rt, own * 4u, 0, 0);
+        if constexpr (PACKED) {
+            tri = in.tri_base + (w & ((1u << CRSH_PACKED_TRI_BITS) - 1u));
+            par = own < nq ? w >> CRSH_PACKED_TRI_BITS : NONE;
+        } else {
+            const __amdgpu_buffer_rsrc_t rn = make_rsrc(in.node + q0, (uint64_t)nq * 4u);
+            tri = w;
+            par = own < nq ? __builtin_amdgcn_raw_buffer_load_b32(rn, own * 4u, 0, 0) : NONE;
+        }
     };
     uint64_t tests = 0;                     // wave-wide
     uint32_t parity = 0;
     // a parent's children: plain, par * F + [0, F); batch, the build's
-    // record (level-local first child, count)
-    auto children = [&](uint32_t par, uint32_t &first, uint32_t &cnt) {
+    // record (level-local first child, count); as 16 x (first, number below
+    // nk), byte offsets into the staged run (node indices stay below 2^28:
+    // 32-bit byte offsets into the node arrays)
+    auto children = [&](uint32_t par, uint32_t &first16, uint32_t &n16) {
+        uint32_t first, cnt;
         if constexpr (BATCH) {
             const bool ok = par < np;
             first = ok ? bd.node_first[offp + par] : 0u;
             cnt = ok ? bd.node_info[offp + par] & INFO_COUNT_MASK : 0u;
         } else {
-            first = par * F;
+            first = par != NONE ? par * F : 0u;
             cnt = par != NONE ? F : 0u;
         }
+        first16 = first < nk ? first * 16u : 0u;
+        n16 = first < nk ? (min(first + cnt, nk) - first) * 16u : 0u;
     };
     // two-stage prefetch: the sphere (and batch: the child range) of the
     // next step and the pair of the step after it are in flight while a
     // step is tested
-    uint32_t first_n = 0u, cnt_n = 0u, tri_nn = 0u, par_nn = NONE;
+    uint32_t first_n = 0u, n_n = 0u, tri_nn = 0u, par_nn = NONE;
     float4 sp_n = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (blockIdx.x < nsteps) {
         uint32_t tri0, par0;
         load_pair(blockIdx.x, tri0, par0);
         sp_n = tsph[tri0 < m ? tri0 : 0u];
-        children(par0, first_n, cnt_n);
-        if (blockIdx.x + gridDim.x < nsteps) load_pair(blockIdx.x + gridDim.x, tri_nn, par_nn);
+        children(par0, first_n, n_n);
+        load_pair(blockIdx.x + gridDim.x, tri_nn, par_nn);
     }
+    // the prologue's loads are in before the loop: the waits the compiler
+    // places in the loop then count only the loop's own memory operations
+    // (not every store of the previous step)
+    __builtin_amdgcn_s_waitcnt(0x0F70);     // vmcnt(0)
     for (uint64_t step = blockIdx.x; step < nsteps; step += gridDim.x, parity ^= 1u) {
         const uint64_t tile = step * COUNT_TPS + half;
         // this wave's slice-0 word of the tile's pass masks (scalar)
         uint2 *const mrow = (uint2 *)S.mask + (tile * LEVEL_TILE + tw * PW) * NF / 64;
-        // this step's records (the wave's previous reads of them are done:
-        // program order within the wave)
-        __builtin_amdgcn_wave_barrier();
-        s_sph[wb][l] = sp_n;
-        s_first[wb][l] = first_n;
-        s_cnt[wb][l] = cnt_n;
-        __builtin_amdgcn_wave_barrier();
+        const __amdgpu_buffer_rsrc_t mrs = make_rsrc(mrow, tile < ntiles ? (NF - 1) * (PR * NF / 64) * 8u + 8u : 0u);
+        // this step's parent values: kept in registers (quad broadcast) or
+        // put in the wave's records (the wave's previous reads of them are
+        // done: program order within the wave); the step's first pair is
+        // lane 0's of wave 0
+        const float4 sp_c = sp_n;
+        const uint32_t first_c = first_n, n_c = n_n;
+        if constexpr (!QB) {
+            __builtin_amdgcn_wave_barrier();
+            s_sph[wb][l] = sp_n;
+            s_first[wb][l] = first_n;
+            s_n[wb][l] = n_n;
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (staged && wb == 0 && l == 0) {
+            s_head[0] = first_n;
+            s_head[1] = n_n;
+        }
         if (staged) {
-            // every wave has written its records and finished its reads of
-            // the staged run (they precede the previous step's count
-            // barrier); the step's first pair is record 0 of wave 0
+            // every wave has finished its reads of the staged run (they
+            // precede the previous step's count barrier)
             __syncthreads();
-            const uint32_t c0 = s_first[0][0];
-            if (s_cnt[0][0] != 0u && c0 < nk && c0 - wlo >= wlen && c0 - ulo >= ulen) {
+            const uint32_t c0 = s_head[0] / 16u;
+            if (s_head[1] != 0u && c0 - wlo >= wlen && c0 - ulo >= ulen) {
                 // the frame's nodes on the child level and its levels
                 uint32_t base = 0u, cntf = nk, levels = nl;
                 if constexpr (BATCH) {
@@ -409,6 +490,8 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
                     __syncthreads();
                     wlo = lo;
                     wlen = len;
+                    wlo16 = lo * 16u;
+                    wlen16 = len * 16u;
                 } else {
                     ulo = base;
                     ulen = cntf;
@@ -416,8 +499,8 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
             }
         }
         sp_n = tsph[tri_nn < m ? tri_nn : 0u];
-        children(par_nn, first_n, cnt_n);
-        if (step + 2 * (uint64_t)gridDim.x < nsteps) load_pair(step + 2 * (uint64_t)gridDim.x, tri_nn, par_nn);
+        children(par_nn, first_n, n_n);
+        load_pair(step + 2 * (uint64_t)gridDim.x, tri_nn, par_nn);
         uint32_t c = 0;
         // slices in groups of K: every node read of a group is issued before
         // its first test, and the test has no branch to sink them into.
@@ -431,30 +514,57 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
 #pragma unroll
         for (uint32_t r0 = 0; r0 < NF; r0 += K) {
             uint64_t okm[K], outm[K], bal[K];
-            uint32_t ch[K], idx[K];
+            uint32_t ch16[K], idx16[K];
+            f3 pc[K];                       // the parent's triangle sphere (records)
+            float pr[K];
+            // the same by quad broadcast, taken where it is used (each copy
+            // has one use: the compiler folds it into that instruction)
+            auto sph_c = [&](uint32_t k) {
+                if constexpr (QB)
+                    return mk(quad_pick<NF>(sp_c.x, r0 + k), quad_pick<NF>(sp_c.y, r0 + k), quad_pick<NF>(sp_c.z, r0 + k));
+                else
+                    return pc[k];
+            };
+            auto sph_r = [&](uint32_t k) {
+                if constexpr (QB)
+                    return quad_pick<NF>(sp_c.w, r0 + k);
+                else
+                    return pr[k];
+            };
 #pragma unroll
             for (uint32_t k = 0; k < K; ++k) {
-                const uint32_t rec = (r0 + k) * PW + pi;
-                ch[k] = s_first[wb][rec] + j;
-                okm[k] = ballot(j < s_cnt[wb][rec]) & ballot(ch[k] < nk);
-                const uint32_t i = ch[k] - wlo;
-                outm[k] = okm[k] & ~ballot(i < wlen);
-                idx[k] = min(i, WN - 1u);       // any slot of the window for a lane that tests nothing here
+                const uint32_t r = r0 + k;
+                uint32_t f16, n16;
+                if constexpr (QB) {
+                    f16 = quad_pick<NF>(first_c, r);
+                    n16 = quad_pick<NF>(n_c, r);
+                } else {
+                    const uint32_t rec = r * PW + pi;
+                    f16 = s_first[wb][rec];
+                    n16 = s_n[wb][rec];
+                    const float4 sp = s_sph[wb][rec];
+                    pc[k] = mk(sp.x, sp.y, sp.z);
+                    pr[k] = sp.w;
+                }
+                ch16[k] = f16 + j16;
+                okm[k] = ballot(j16 < n16);
+                const uint32_t i16 = ch16[k] - wlo16;
+                outm[k] = okm[k] & ~ballot(i16 < wlen16);
+                // any slot of the window for a lane that tests nothing here
+                idx16[k] = min(i16, (WN - 1u) * 16u);
             }
             if constexpr (STAGED) {
                 float4 A[K], Bv[K];
                 float Sg[K];
 #pragma unroll
                 for (uint32_t k = 0; k < K; ++k) {
-                    A[k] = s_wa[idx[k]];
-                    Bv[k] = s_wb[idx[k]];
-                    Sg[k] = s_ws[idx[k]];
+                    A[k] = *(const float4 *)((const char *)s_wa + idx16[k]);
+                    Bv[k] = *(const float4 *)((const char *)s_wb + idx16[k]);
+                    Sg[k] = *(const float *)((const char *)s_ws + idx16[k] / 4u);
                 }
 #pragma unroll
-                for (uint32_t k = 0; k < K; ++k) {
-                    const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
-                    bal[k] = packed_meets_mask(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w) & okm[k] & ~outm[k];
-                }
+                for (uint32_t k = 0; k < K; ++k)
+                    bal[k] = packed_meets_mask(A[k], Bv[k], Sg[k], sph_c(k), sph_r(k)) & okm[k] & ~outm[k];
                 // rare: a slice with children outside the run, one at a time
                 uint64_t any_out = 0;
 #pragma unroll
@@ -463,12 +573,18 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
 #pragma unroll
                     for (uint32_t k = 0; k < K; ++k) {
                         if (outm[k] == 0) continue;
-                        const uint32_t g = offk + (((outm[k] >> l) & 1u) ? ch[k] : 0u);
+                        const uint32_t g = offk + (((outm[k] >> l) & 1u) ? ch16[k] / 16u : 0u);
                         const float4 Ag = buf_load4(ra, g * 16u);
                         const float4 Bg = buf_load4(rb, g * 16u);
                         const float Sgg = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
-                        const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
-                        bal[k] |= packed_meets_mask(Ag, Bg, Sgg, mk(sp.x, sp.y, sp.z), sp.w) & outm[k];
+                        f3 c = pc[k];
+                        float d = pr[k];
+                        if constexpr (QB) {     // copies of its own (see sph_c)
+                            c = mk(quad_pick_again<NF>(sp_c.x, r0 + k), quad_pick_again<NF>(sp_c.y, r0 + k),
+                                   quad_pick_again<NF>(sp_c.z, r0 + k));
+                            d = quad_pick_again<NF>(sp_c.w, r0 + k);
+                        }
+                        bal[k] |= packed_meets_mask(Ag, Bg, Sgg, c, d) & outm[k];
                     }
                 }
             } else {
@@ -478,16 +594,14 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
                 float Sg[K];
 #pragma unroll
                 for (uint32_t k = 0; k < K; ++k) {
-                    const uint32_t g = offk + (((okm[k] >> l) & 1u) ? ch[k] : 0u);
+                    const uint32_t g = offk + (((okm[k] >> l) & 1u) ? ch16[k] / 16u : 0u);
                     A[k] = buf_load4(ra, g * 16u);
                     Bv[k] = buf_load4(rb, g * 16u);
                     Sg[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, g * 4u, 0, 0));
                 }
 #pragma unroll
-                for (uint32_t k = 0; k < K; ++k) {
-                    const float4 sp = s_sph[wb][(r0 + k) * PW + pi];
-                    bal[k] = packed_meets_mask(A[k], Bv[k], Sg[k], mk(sp.x, sp.y, sp.z), sp.w) & okm[k];
-                }
+                for (uint32_t k = 0; k < K; ++k)
+                    bal[k] = packed_meets_mask(A[k], Bv[k], Sg[k], sph_c(k), sph_r(k)) & okm[k];
             }
 #pragma unroll
             for (uint32_t k = 0; k < K; ++k) {
@@ -495,9 +609,11 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
                 tests += (uint64_t)__popcll(okm[k]);
                 // the wave's pass bits of slice r: bit (tile * LEVEL_TILE +
                 // r * PR + tw * PW) * NF of the level's masks, a multiple of 64
-                // (r * PR * NF = 64 r words' worth of 4 bits: uint2 4 r)
-                if (l == 0 && tile < ntiles)
-                    mrow[r * (PR * NF / 64)] = make_uint2((uint32_t)bal[k], (uint32_t)(bal[k] >> 32));
+                // (r * PR * NF = 64 r words' worth of 4 bits: uint2 4 r).
+                // Every lane stores, lane 0 in range: no branch around it
+                typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+                const v2u w = {(uint32_t)bal[k], (uint32_t)(bal[k] >> 32)};
+                __builtin_amdgcn_raw_buffer_store_b64(w, mrs, mlane + r * (PR * NF / 64) * 8u, 0, 0);
                 c += (uint32_t)__popcll(bal[k]);
             }
         }
