@@ -305,7 +305,7 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
 // final tests of the level-1 pairs given as level-2 pairs and level-1 pass
 // masks (the fused last level); rays packed by hit_pairs_launch first
 void hit_masked_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level2,
-                       const uint32_t *mask, int32_t merge, int32_t bundle, const crsh_scene *scene,
+                       const uint32_t *mask, int32_t merge, int32_t bundle, const crsh_scene *scene, float t_min,
                        crsh_hits *hits, crsh_meta *meta, const batch_dev *bd, int32_t hit_block, hipStream_t stream);
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,
                       const hit_slots_ws &hs, int32_t bundle, const crsh_scene *scene, float t_min,

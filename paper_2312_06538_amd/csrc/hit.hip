@@ -57,19 +57,27 @@ __device__ __forceinline__ uint32_t batch_slots(const crsh_meta *meta, uint32_t 
     return (uint32_t)(ns < slot_cap ? ns : slot_cap);
 }
 
-// Plain form: sorted rays repacked as (origin, tmax) and (direction, t_min),
-// one float4 array each: two 16-byte loads per test instead of seven
-// scattered ones, and the 16 rays of a leaf are 256 contiguous bytes in
-// either array.
-__global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, float t_min, float4 *org,
-                           float4 *dir)
+// Plain form: sorted rays repacked as (origin, tmax), 16 bytes a slot, and
+// the direction, 12 bytes a slot (the interval start is the frame's, a
+// kernel argument): a 16-byte and a 12-byte load per test instead of seven
+// scattered ones, and the 16 rays of a leaf are 256 and 192 contiguous
+// bytes.
+__global__ void k_hit_rays(sorted_rays R, const crsh_meta *meta, uint32_t cap, float4 *org, float *dir3)
 {
     const uint32_t n = min(meta->n_rays, cap);
-    const float tm = slot_tmin(t_min);
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
         org[s] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
-        dir[s] = make_float4(R.dx[s], R.dy[s], R.dz[s], tm);
+        dir3[3 * (size_t)s + 0] = R.dx[s];
+        dir3[3 * (size_t)s + 1] = R.dy[s];
+        dir3[3 * (size_t)s + 2] = R.dz[s];
     }
+}
+
+__device__ __forceinline__ f3 buf_load3(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    typedef float v3f __attribute__((ext_vector_type(3)));
+    const v3f v = __builtin_amdgcn_raw_buffer_load_b96(r, off, 0, 0);
+    return mk(v.x, v.y, v.z);
 }
 
 // Batched form: slot p = leaf * B + j holds ray j of level-1 node `leaf`
@@ -100,8 +108,8 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
 
 // One step of the final tests for a wave: each lane group holds a pair --
 // its triangle (a, b, c: v0, e1, e2 packed), the triangle id and the byte
-// offset of the leaf's first ray slot -- and lane j of the group tests ray j
-// of the leaf.  `live` is the wave mask of the lanes whose test is one of the
+// offset of the leaf's first ray slot (and, plain form, of its first
+// 12-byte direction) -- and lane j of the group tests ray j of the leaf.  `live` is the wave mask of the lanes whose test is one of the
 // pair's.  A lane outside it may still read a ray: that of a slot past the
 // leaf's rays, or a zero ray (a padded slot, or an offset past the slot
 // array's end, which reads zeros); a zero ray has a zero determinant and
@@ -112,13 +120,22 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
 template <bool BATCH, bool COUNT>
 __device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, const __amdgpu_buffer_rsrc_t &dir_r,
                                          const float4 &a, const float4 &b, float tc, uint32_t tri_id,
-                                         uint32_t ray_off, uint64_t live, uint32_t j,
+                                         uint32_t ray_off, uint32_t dir_off, float t_min, uint64_t live, uint32_t j,
                                          unsigned long long *keys, uint64_t &tests, uint64_t &upass,
                                          uint64_t &uvpass)
 {
     const uint32_t ro = ray_off + j * 16u;
     const float4 ro4 = buf_load4(org_r, ro);
-    const float4 rd4 = buf_load4(dir_r, ro);
+    f3 D;
+    float tmin;
+    if constexpr (BATCH) {                  // (direction, t_min) slots
+        const float4 rd4 = buf_load4(dir_r, ro);
+        D = mk(rd4.x, rd4.y, rd4.z);
+        tmin = rd4.w;
+    } else {
+        D = buf_load3(dir_r, dir_off + j * 12u);
+        tmin = t_min;
+    }
     tri_t tr;
     tr.v0 = mk(a.x, a.y, a.z);
     tr.e1 = mk(a.w, b.x, b.y);
@@ -126,10 +143,9 @@ __device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, co
     if constexpr (COUNT) {
         // a padded slot's NaN t_min accepts nothing; it only must not count
         // as a test
-        if (BATCH) live &= ballot(__float_as_uint(rd4.w) != PAD_SLOT);
+        if (BATCH) live &= ballot(__float_as_uint(tmin) != PAD_SLOT);
         tests += (uint64_t)__popcll(live);
     }
-    const f3 D = mk(rd4.x, rd4.y, rd4.z);
     mt_head h;
     const uint64_t mm = mt_first_half(mk(ro4.x, ro4.y, ro4.z), D, tr, h) & live;
     // a wave-uniform branch: the wave runs the second half only if one of
@@ -138,7 +154,7 @@ __device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, co
     if (mm != 0) {
         float th;
         uint64_t pu, puv, hit;
-        mt_second_half(D, rd4.w, ro4.w, tr, h, th, pu, puv, hit);
+        mt_second_half(D, tmin, ro4.w, tr, h, th, pu, puv, hit);
         upass += (uint64_t)__popcll(pu & mm);
         uvpass += (uint64_t)__popcll(puv & mm);
         if (__builtin_amdgcn_inverse_ballot_w64(hit & mm)) atomicMin(&keys[ro >> 4], hit_key(th, tri_id));
@@ -176,16 +192,17 @@ __device__ __forceinline__ void hit_counts(uint64_t (*s_red)[256 / WAVE], uint32
 // parent pair -- or their leaves, so a run finds its rays in the vector L1
 // cache).  Each lane reads one pair of the run, its triangle, and writes a
 // 48-byte record to the wave's LDS slice: the triangle (v0, e1, e2), the
-// triangle id and the byte offset of the leaf's first ray slot (past the
-// slot array for a pair out of range, so that its rays read as zeros).  The
+// triangle id and the byte offsets of the leaf's first ray slot and, plain
+// form, of its first direction (past the arrays for a pair out of range, so
+// that its rays read as zeros).  The
 // run is then tested 64 / G pairs at a time, each lane group reading its
 // pair's record from LDS (the 16 lanes of a group read the same address), so
 // the vector memory path carries only the rays.  The tests are counted per
 // pair when the record is written (the leaf's rays), not per step.  Rays are
 // read with buffer loads on 32-bit byte offsets (the host bounds them; a read
 // past the end returns zeros), origins and directions from their own
-// arrays, so each of the two loads of a step covers 256 contiguous bytes per
-// pair.  The test is split where most of its cost lies: every lane computes
+// arrays, so each of the two loads of a step covers contiguous bytes per
+// pair (256 and, plain form, 192).  The test is split where most of its cost lies: every lane computes
 // the division-free first half, and the wave runs the rest (the division
 // included) only when one of its lanes can still pass.
 constexpr uint32_t RAY_OFF_NONE = 0xFFFF0000u;   // above every slot array (2^31 bytes at most)
@@ -195,7 +212,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
                                              uint64_t cap1, uint32_t B, uint32_t log2G, unsigned long long *keys,
                                              crsh_meta *meta, uint32_t slot_cap, uint32_t m, uint32_t tri_base,
-                                             const uint32_t *__restrict__ leaf_cnt)
+                                             const uint32_t *__restrict__ leaf_cnt, float t_min)
 {
     __shared__ uint64_t s_red[3][256 / WAVE];
     __shared__ float4 s_rec[256 / WAVE][3][WAVE];    // [wave][record word][pair of the run]
@@ -212,14 +229,14 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
     const __amdgpu_buffer_rsrc_t org_r = make_rsrc(RO, (uint64_t)ns * 16u);
-    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * 16u);
+    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * (BATCH ? 16u : 12u));
     const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
     float4(*rec)[WAVE] = s_rec[wib];
     uint32_t my_tests = 0;                   // this lane's pairs: rays of their leaves
     uint64_t tests = 0, upass = 0, uvpass = 0;   // wave-wide counts
     for (uint64_t c0 = wave * WAVE; c0 < np; c0 += nwaves * WAVE) {
         const uint32_t cn = __builtin_amdgcn_readfirstlane((uint32_t)min(np - c0, (uint64_t)WAVE));
-        uint32_t my_t = 0u, my_rb = RAY_OFF_NONE, leaf = 0u;
+        uint32_t my_t = 0u, my_rb = RAY_OFF_NONE, my_db = RAY_OFF_NONE, leaf = 0u;
         bool valid = false;
         if (l < cn) {
             if constexpr (PACKED) {
@@ -236,6 +253,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
             if (my_t < m && first < ns) {
                 valid = true;
                 my_rb = (uint32_t)first * 16u;
+                my_db = (uint32_t)first * 12u;
             }
         }
         const uint32_t tb = valid ? my_t * 48u : 0u;
@@ -250,15 +268,15 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
         __builtin_amdgcn_wave_barrier();          // the previous run's reads come first
         rec[0][l] = ta;
         rec[1][l] = tbv;
-        rec[2][l] = make_float4(tc, __uint_as_float(my_t), __uint_as_float(my_rb), 0.0f);
+        rec[2][l] = make_float4(tc, __uint_as_float(my_t), __uint_as_float(my_rb), __uint_as_float(my_db));
         __builtin_amdgcn_wave_barrier();
         for (uint32_t k = 0; k < cn; k += per_wave) {
             const uint32_t src = k + slot;
             const float4 a = rec[0][src];
             const float4 b = rec[1][src];
             const float4 c = rec[2][src];
-            hit_step<BATCH, false>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), __float_as_uint(c.z), live, j,
-                                   keys, tests, upass, uvpass);
+            hit_step<BATCH, false>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), __float_as_uint(c.z),
+                                   __float_as_uint(c.w), t_min, live, j, keys, tests, upass, uvpass);
         }
     }
     tests = wave_sum((uint64_t)my_tests);
@@ -285,7 +303,8 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
                                                     const uint32_t *__restrict__ pnode2, uint64_t cap2,
                                                     const uint32_t *__restrict__ mask, uint32_t nf, uint32_t F,
                                                     uint32_t B, uint32_t log2G, unsigned long long *keys,
-                                                    crsh_meta *meta, uint32_t slot_cap, uint32_t m, batch_dev bd)
+                                                    crsh_meta *meta, uint32_t slot_cap, uint32_t m, batch_dev bd,
+                                                    float t_min)
 {
     __shared__ uint64_t s_red[3][256 / WAVE];
     __shared__ float4 s_rec[256 / WAVE][3][WAVE];           // [wave][record word][pair of the run]
@@ -305,7 +324,7 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
     const __amdgpu_buffer_rsrc_t org_r = make_rsrc(RO, (uint64_t)ns * 16u);
-    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * 16u);
+    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * (BATCH ? 16u : 12u));
     const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
     const uint32_t nfm = nf >= 32 ? ~0u : (1u << nf) - 1u;
     float4(*rec)[WAVE] = s_rec[wib];
@@ -366,8 +385,8 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
                 const float4 b = rec[1][p];
                 const float4 c = rec[2][p];
                 const uint32_t cnt = src < nit ? it.x >> 8 : 0u;
-                hit_step<BATCH, true>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), it.y, ballot(j < cnt), j, keys,
-                                      tests, upass, uvpass);
+                hit_step<BATCH, true>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), it.y, (it.y >> 2) * 3u, t_min,
+                                      ballot(j < cnt), j, keys, tests, upass, uvpass);
             }
         }
     }
@@ -465,7 +484,7 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
         k_hit_rays_batch<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, (uint32_t)bundle, hs.slots, *bd,
                                                 hs.org, hs.dir, hs.keys);
     if (!level1->capacity) return;
-    if (!bd) k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, t_min, hs.org, hs.dir);
+    if (!bd) k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, hs.org, (float *)hs.dir);
     uint32_t log2G = 0;
     while ((1u << log2G) < (uint32_t)bundle) ++log2G;
     const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
@@ -473,19 +492,19 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
     if (bd)
         k_hit<true, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                            level1->capacity, (uint32_t)bundle, log2G, hs.keys, meta,
-                                                           hs.slots, scene->m, 0u, bd->node_info);
+                                                           hs.slots, scene->m, 0u, bd->node_info, 0.0f);
     else if (packed)
         k_hit<false, true><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, nullptr, level1->capacity,
                                                            (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
-                                                           scene->m, tri_base, nullptr);
+                                                           scene->m, tri_base, nullptr, t_min);
     else
         k_hit<false, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                             level1->capacity, (uint32_t)bundle, log2G, hits->tkey,
-                                                            meta, hs.slots, scene->m, 0u, nullptr);
+                                                            meta, hs.slots, scene->m, 0u, nullptr, t_min);
 }
 
 void hit_masked_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level2,
-                       const uint32_t *mask, int32_t merge, int32_t bundle, const crsh_scene *scene,
+                       const uint32_t *mask, int32_t merge, int32_t bundle, const crsh_scene *scene, float t_min,
                        crsh_hits *hits, crsh_meta *meta, const batch_dev *bd, int32_t hit_block, hipStream_t stream)
 {
     (void)sorted;
@@ -500,12 +519,12 @@ void hit_masked_launch(const crsh_rays *sorted, const float4 *tri, const hit_slo
         k_hit_masked<true><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level2->tri, level2->node,
                                                            level2->capacity, mask, nf, (uint32_t)merge,
                                                            (uint32_t)bundle, log2G, hs.keys, meta, hs.slots,
-                                                           scene->m, b);
+                                                           scene->m, b, 0.0f);
     else
         k_hit_masked<false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level2->tri, level2->node,
                                                             level2->capacity, mask, nf, (uint32_t)merge,
                                                             (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
-                                                            scene->m, b);
+                                                            scene->m, b, t_min);
 }
 
 void hit_final_launch(const crsh_rays *sorted, const uint32_t *sorted_ids, const float4 *tri,

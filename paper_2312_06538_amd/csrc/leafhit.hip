@@ -131,8 +131,8 @@ crsh_status leaf_hit_launch(const crsh_rays *sorted, const uint32_t *sorted_ids,
     const uint32_t gs = (uint32_t)std::max<uint64_t>(std::min<uint64_t>((lh_tiles(level2->capacity) + 255) / 256,
                                                                         1024), 1);
     k_lh_survivors<<<gs, 256, 0, stream>>>(L.S, meta, level2->capacity);
-    hit_masked_launch(sorted, L.tri, L.hs, level2, L.S.mask, merge, bundle, scene, hits, meta, bd, hit_block,
-                      stream);
+    hit_masked_launch(sorted, L.tri, L.hs, level2, L.S.mask, merge, bundle, scene, t_min, hits, meta, bd,
+                      hit_block, stream);
     hit_final_launch(sorted, sorted_ids, L.tri, L.hs, bundle, scene, t_min, hits, meta, bd, stream);
     return hip_check(hipGetLastError(), "crsh_leaf_hit launch");
 }
