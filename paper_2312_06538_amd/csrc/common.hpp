@@ -253,7 +253,7 @@ constexpr uint32_t hit_slots(uint32_t rays, bool batch)
 }
 struct hit_slots_ws {
     float4 *org;                 // per slot: origin, tmax
-    float4 *dir;                 // per slot: direction, t_min
+    float *dir;                  // per slot: direction (12 bytes)
     unsigned long long *keys;    // per slot (batched form)
     uint32_t slots;
 };
@@ -261,7 +261,7 @@ inline hit_slots_ws carve_hit_slots(void *at, uint32_t slots)
 {
     hit_slots_ws h;
     h.org = (float4 *)at;
-    h.dir = (float4 *)((char *)at + align256((size_t)slots * 16));
+    h.dir = (float *)((char *)at + align256((size_t)slots * 16));
     h.keys = (unsigned long long *)((char *)h.dir + align256((size_t)slots * 16));
     h.slots = slots;
     return h;

@@ -12,13 +12,14 @@
 //              minimum: the closest hit, ties to the lower triangle id.
 // k_hit_final  one thread per sorted ray: decode the key, recompute u, v with
 //              the same test, write the result at the ray id.
-// Ray slots: k_hit reads the rays of leaf l at slots l * B + j, j < B, of a
-// packed ray array whose second float4 carries the interval start t_min.  In
-// the plain form slot s is sorted ray s.  In the batched form a frame's rays
-// are bundled B at a time from its own first ray, so only a frame's last leaf
-// can hold fewer than B rays; its slots are padded (a marker in place of
-// t_min) and the closest-hit keys are kept by slot, so the pair loop finds a
-// ray with no per-leaf lookup.  k_hit_final maps each sorted ray back to its
+// Ray slots: k_hit reads the rays of leaf l at slots l * B + j, j < B, of two
+// packed arrays: (origin, tmax), 16 bytes a slot, and the direction, 12
+// bytes a slot; the interval start t_min is the frame's.  In the plain form
+// slot s is sorted ray s.  In the batched form a frame's rays are bundled B
+// at a time from its own first ray, so only a frame's last leaf can hold
+// fewer than B rays; its slots are padded (zeros, a marker in place of tmax)
+// and the closest-hit keys are kept by slot, so the pair loop finds a ray
+// with no per-leaf lookup.  k_hit_final maps each sorted ray back to its
 // slot through its frame's first leaf and first ray.
 #include "batch.hpp"
 #include "intersect.hpp"
@@ -45,10 +46,10 @@ struct sorted_rays {
     const float *ox, *oy, *oz, *dx, *dy, *dz, *tmax;
 };
 
-// t_min word of a padded slot (a NaN); a NaN t_min of a real ray is stored as
+// tmax word of a padded slot (a NaN); a NaN tmax of a real ray is stored as
 // the default quiet NaN, which accepts no hit either
 constexpr uint32_t PAD_SLOT = 0x7FC0DEADu;
-__device__ __forceinline__ float slot_tmin(float t_min) { return t_min != t_min ? __uint_as_float(0x7FC00000u) : t_min; }
+__device__ __forceinline__ float slot_tmax(float tmax) { return tmax != tmax ? __uint_as_float(0x7FC00000u) : tmax; }
 
 // slots of the batched form in use: B per level-1 node
 __device__ __forceinline__ uint32_t batch_slots(const crsh_meta *meta, uint32_t B, uint32_t slot_cap)
@@ -81,10 +82,10 @@ __device__ __forceinline__ f3 buf_load3(__amdgpu_buffer_rsrc_t r, uint32_t off)
 }
 
 // Batched form: slot p = leaf * B + j holds ray j of level-1 node `leaf`
-// (first ray and count as the build recorded them) with its frame's t_min,
-// or the padding marker; every slot's closest-hit key starts at all ones.
+// (first ray and count as the build recorded them), or zeros and the padding
+// marker; every slot's closest-hit key starts at all ones.
 __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t ray_cap, uint32_t B,
-                                 uint32_t slot_cap, batch_dev bd, float4 *org, float4 *dir,
+                                 uint32_t slot_cap, batch_dev bd, float4 *org, float *dir3,
                                  unsigned long long *keys)
 {
     const uint32_t n = min(meta->n_rays, ray_cap);
@@ -95,28 +96,34 @@ __global__ void k_hit_rays_batch(sorted_rays R, const crsh_meta *meta, uint32_t 
         const uint32_t info = bd.node_info[leaf];
         const uint32_t f = info >> INFO_FRAME_SHIFT;
         const uint32_t s = bd.node_first[leaf] + j;
+        float dx = 0.0f, dy = 0.0f, dz = 0.0f;
         if (j < (info & INFO_COUNT_MASK) && s < n && f < bd.n_frames) {
-            org[p] = make_float4(R.ox[s], R.oy[s], R.oz[s], R.tmax[s]);
-            dir[p] = make_float4(R.dx[s], R.dy[s], R.dz[s], slot_tmin(bd.frames[f].t_min));
+            org[p] = make_float4(R.ox[s], R.oy[s], R.oz[s], slot_tmax(R.tmax[s]));
+            dx = R.dx[s];
+            dy = R.dy[s];
+            dz = R.dz[s];
         } else {
-            org[p] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            dir[p] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(PAD_SLOT));
+            org[p] = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(PAD_SLOT));
         }
+        dir3[3 * (size_t)p + 0] = dx;
+        dir3[3 * (size_t)p + 1] = dy;
+        dir3[3 * (size_t)p + 2] = dz;
         keys[p] = ~0ull;
     }
 }
 
 // One step of the final tests for a wave: each lane group holds a pair --
-// its triangle (a, b, c: v0, e1, e2 packed), the triangle id and the byte
-// offset of the leaf's first ray slot (and, plain form, of its first
-// 12-byte direction) -- and lane j of the group tests ray j of the leaf.  `live` is the wave mask of the lanes whose test is one of the
+// its triangle (a, b, c: v0, e1, e2 packed), the triangle id, the byte
+// offsets of the leaf's first ray slot and first direction, and the interval
+// start of the pair's frame -- and lane j of the group tests ray j of the
+// leaf.  `live` is the wave mask of the lanes whose test is one of the
 // pair's.  A lane outside it may still read a ray: that of a slot past the
-// leaf's rays, or a zero ray (a padded slot, or an offset past the slot
-// array's end, which reads zeros); a zero ray has a zero determinant and
-// fails the first half, so only the lanes j >= B of a group wider than the
-// bundle need the mask.  COUNT: the step counts its tests (the lanes of
-// `live`, less the padded slots of the batched form); without it the caller
-// counts them.  Hits go to the slot keys.  Called by every lane of the wave.
+// leaf's rays, or a zero ray (a padded slot, or an offset past the arrays'
+// ends, which reads zeros); a zero ray has a zero determinant and fails the
+// first half, so only the lanes j >= B of a group wider than the bundle need
+// the mask.  COUNT: the step counts its tests (the lanes of `live`, less the
+// padded slots of the batched form); without it the caller counts them.
+// Hits go to the slot keys.  Called by every lane of the wave.
 template <bool BATCH, bool COUNT>
 __device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, const __amdgpu_buffer_rsrc_t &dir_r,
                                          const float4 &a, const float4 &b, float tc, uint32_t tri_id,
@@ -126,16 +133,7 @@ __device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, co
 {
     const uint32_t ro = ray_off + j * 16u;
     const float4 ro4 = buf_load4(org_r, ro);
-    f3 D;
-    float tmin;
-    if constexpr (BATCH) {                  // (direction, t_min) slots
-        const float4 rd4 = buf_load4(dir_r, ro);
-        D = mk(rd4.x, rd4.y, rd4.z);
-        tmin = rd4.w;
-    } else {
-        D = buf_load3(dir_r, dir_off + j * 12u);
-        tmin = t_min;
-    }
+    const f3 D = buf_load3(dir_r, dir_off + j * 12u);
     tri_t tr;
     tr.v0 = mk(a.x, a.y, a.z);
     tr.e1 = mk(a.w, b.x, b.y);
@@ -143,7 +141,7 @@ __device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, co
     if constexpr (COUNT) {
         // a padded slot's NaN t_min accepts nothing; it only must not count
         // as a test
-        if (BATCH) live &= ballot(__float_as_uint(tmin) != PAD_SLOT);
+        if (BATCH) live &= ballot(__float_as_uint(ro4.w) != PAD_SLOT);
         tests += (uint64_t)__popcll(live);
     }
     mt_head h;
@@ -154,7 +152,7 @@ __device__ __forceinline__ void hit_step(const __amdgpu_buffer_rsrc_t &org_r, co
     if (mm != 0) {
         float th;
         uint64_t pu, puv, hit;
-        mt_second_half(D, tmin, ro4.w, tr, h, th, pu, puv, hit);
+        mt_second_half(D, t_min, ro4.w, tr, h, th, pu, puv, hit);
         upass += (uint64_t)__popcll(pu & mm);
         uvpass += (uint64_t)__popcll(puv & mm);
         if (__builtin_amdgcn_inverse_ballot_w64(hit & mm)) atomicMin(&keys[ro >> 4], hit_key(th, tri_id));
@@ -184,17 +182,17 @@ __device__ __forceinline__ void hit_counts(uint64_t (*s_red)[256 / WAVE], uint32
 // Slots in use: the plain form's sorted rays, or B per level-1 node.  PACKED:
 // the level-1 pairs are packed words in ptri (node above the low
 // CRSH_PACKED_TRI_BITS, triangle minus tri_base below; pnode unused).
-// leaf_cnt (batched form): the build's per-node record of the leaves, whose
-// low bits hold the leaf's ray count.
+// Batched form: the build's per-node record of a leaf (bd.node_info) holds
+// its ray count and frame, and the frame its interval start.
 //
 // A wave takes runs of 64 consecutive pairs before the grid stride
 // (neighbouring level-1 pairs share their triangle -- siblings of one
 // parent pair -- or their leaves, so a run finds its rays in the vector L1
 // cache).  Each lane reads one pair of the run, its triangle, and writes a
-// 48-byte record to the wave's LDS slice: the triangle (v0, e1, e2), the
-// triangle id and the byte offsets of the leaf's first ray slot and, plain
-// form, of its first direction (past the arrays for a pair out of range, so
-// that its rays read as zeros).  The
+// record to the wave's LDS slice: the triangle (v0, e1, e2), the triangle
+// id, the byte offsets of the leaf's first ray slot and first direction
+// (past the arrays for a pair out of range, so that its rays read as
+// zeros) and, batched form, the interval start of the leaf's frame.  The
 // run is then tested 64 / G pairs at a time, each lane group reading its
 // pair's record from LDS (the 16 lanes of a group read the same address), so
 // the vector memory path carries only the rays.  The tests are counted per
@@ -202,20 +200,21 @@ __device__ __forceinline__ void hit_counts(uint64_t (*s_red)[256 / WAVE], uint32
 // read with buffer loads on 32-bit byte offsets (the host bounds them; a read
 // past the end returns zeros), origins and directions from their own
 // arrays, so each of the two loads of a step covers contiguous bytes per
-// pair (256 and, plain form, 192).  The test is split where most of its cost lies: every lane computes
+// pair (256 and 192).  The test is split where most of its cost lies: every lane computes
 // the division-free first half, and the wave runs the rest (the division
 // included) only when one of its lanes can still pass.
 constexpr uint32_t RAY_OFF_NONE = 0xFFFF0000u;   // above every slot array (2^31 bytes at most)
 template <bool BATCH, bool PACKED>
-__global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, const float4 *__restrict__ RD,
+__global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, const float *__restrict__ RD,
                                              const float4 *__restrict__ tri,
                                              const uint32_t *__restrict__ ptri, const uint32_t *__restrict__ pnode,
                                              uint64_t cap1, uint32_t B, uint32_t log2G, unsigned long long *keys,
                                              crsh_meta *meta, uint32_t slot_cap, uint32_t m, uint32_t tri_base,
-                                             const uint32_t *__restrict__ leaf_cnt, float t_min)
+                                             batch_dev bd, float t_min)
 {
+    constexpr uint32_t RW = BATCH ? 4 : 3;           // record words
     __shared__ uint64_t s_red[3][256 / WAVE];
-    __shared__ float4 s_rec[256 / WAVE][3][WAVE];    // [wave][record word][pair of the run]
+    __shared__ float4 s_rec[256 / WAVE][RW][WAVE];   // [wave][record word][pair of the run]
     const uint32_t ns = BATCH ? batch_slots(meta, B, slot_cap) : min(meta->n_rays, slot_cap);
     uint64_t np = meta->n_levels ? meta->pairs[0] : 0;
     np = np < cap1 ? np : cap1;
@@ -229,7 +228,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
     const __amdgpu_buffer_rsrc_t org_r = make_rsrc(RO, (uint64_t)ns * 16u);
-    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * (BATCH ? 16u : 12u));
+    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * 12u);
     const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
     float4(*rec)[WAVE] = s_rec[wib];
     uint32_t my_tests = 0;                   // this lane's pairs: rays of their leaves
@@ -260,23 +259,29 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
         const float4 ta = buf_load4(tris_r, tb);
         const float4 tbv = buf_load4(tris_r, tb + 16u);
         const float tc = buf_load1(tris_r, tb + 32u);
-        if (valid) {
-            uint32_t cnt = min(B, ns - leaf * B);
-            if constexpr (BATCH) cnt = min(cnt, leaf_cnt[leaf] & INFO_COUNT_MASK);
-            my_tests += cnt;
+        uint32_t cnt = valid ? min(B, ns - leaf * B) : 0u;
+        float my_tmin = 0.0f;
+        if constexpr (BATCH) {
+            const uint32_t info = valid ? bd.node_info[leaf] : 0u;
+            cnt = min(cnt, info & INFO_COUNT_MASK);
+            const uint32_t f = info >> INFO_FRAME_SHIFT;
+            my_tmin = cnt && f < bd.n_frames ? bd.frames[f].t_min : 0.0f;
         }
+        my_tests += cnt;
         __builtin_amdgcn_wave_barrier();          // the previous run's reads come first
         rec[0][l] = ta;
         rec[1][l] = tbv;
         rec[2][l] = make_float4(tc, __uint_as_float(my_t), __uint_as_float(my_rb), __uint_as_float(my_db));
+        if constexpr (BATCH) ((float *)rec[3])[l] = my_tmin;
         __builtin_amdgcn_wave_barrier();
         for (uint32_t k = 0; k < cn; k += per_wave) {
             const uint32_t src = k + slot;
             const float4 a = rec[0][src];
             const float4 b = rec[1][src];
             const float4 c = rec[2][src];
+            const float tm = BATCH ? ((const float *)rec[3])[src] : t_min;
             hit_step<BATCH, false>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), __float_as_uint(c.z),
-                                   __float_as_uint(c.w), t_min, live, j, keys, tests, upass, uvpass);
+                                   __float_as_uint(c.w), tm, live, j, keys, tests, upass, uvpass);
         }
     }
     tests = wave_sum((uint64_t)my_tests);
@@ -297,7 +302,7 @@ __global__ __launch_bounds__(256) void k_hit(const float4 *__restrict__ RO, cons
 // compute unit, the one round of blocks the launch assumes)
 constexpr uint32_t MASKED_ITEMS = 240;
 template <bool BATCH>
-__global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ RO, const float4 *__restrict__ RD,
+__global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ RO, const float *__restrict__ RD,
                                                     const float4 *__restrict__ tri,
                                                     const uint32_t *__restrict__ ptri2,
                                                     const uint32_t *__restrict__ pnode2, uint64_t cap2,
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
     const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + wib;
     const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
     const __amdgpu_buffer_rsrc_t org_r = make_rsrc(RO, (uint64_t)ns * 16u);
-    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * (BATCH ? 16u : 12u));
+    const __amdgpu_buffer_rsrc_t dir_r = make_rsrc(RD, (uint64_t)ns * 12u);
     const __amdgpu_buffer_rsrc_t tris_r = make_rsrc(tri, (uint64_t)m * 48u);
     const uint32_t nfm = nf >= 32 ? ~0u : (1u << nf) - 1u;
     float4(*rec)[WAVE] = s_rec[wib];
@@ -333,6 +338,7 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
     for (uint64_t c0 = wave * WAVE; c0 < n2; c0 += nwaves * WAVE) {
         const uint32_t cn = __builtin_amdgcn_readfirstlane((uint32_t)min(n2 - c0, (uint64_t)WAVE));
         uint32_t my_t = 0u, bits = 0u, first = 0u;
+        float my_tmin = t_min;                    // batched form: the pair's frame's
         if (l < cn) {
             const uint64_t q = c0 + l;
             my_t = ptri2[q];
@@ -341,6 +347,8 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
             bits = (mask[bit >> 5] >> (uint32_t)(bit & 31u)) & nfm;
             if constexpr (BATCH) {
                 first = node < np2 ? bd.node_first[off2 + node] : 0u;
+                const uint32_t f = node < np2 ? bd.node_info[off2 + node] >> INFO_FRAME_SHIFT : bd.n_frames;
+                my_tmin = f < bd.n_frames ? bd.frames[f].t_min : 0.0f;
                 if (node >= np2) bits = 0u;
             } else {
                 first = node * F;
@@ -358,7 +366,7 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
         __builtin_amdgcn_wave_barrier();          // the previous run's reads come first
         rec[0][l] = ta;
         rec[1][l] = tbv;
-        rec[2][l] = make_float4(tc, __uint_as_float(my_t), 0.0f, 0.0f);
+        rec[2][l] = make_float4(tc, __uint_as_float(my_t), my_tmin, 0.0f);
         for (uint32_t rb = 0; rb < total; rb += MASKED_ITEMS) {
             // this round's items: the lane's (pair, child) items with index
             // in [rb, rb + MASKED_ITEMS), in (pair, child) order
@@ -385,7 +393,7 @@ __global__ __launch_bounds__(256) void k_hit_masked(const float4 *__restrict__ R
                 const float4 b = rec[1][p];
                 const float4 c = rec[2][p];
                 const uint32_t cnt = src < nit ? it.x >> 8 : 0u;
-                hit_step<BATCH, true>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), it.y, (it.y >> 2) * 3u, t_min,
+                hit_step<BATCH, true>(org_r, dir_r, a, b, c.x, __float_as_uint(c.y), it.y, (it.y >> 2) * 3u, c.z,
                                       ballot(j < cnt), j, keys, tests, upass, uvpass);
             }
         }
@@ -484,7 +492,7 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
         k_hit_rays_batch<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, (uint32_t)bundle, hs.slots, *bd,
                                                 hs.org, hs.dir, hs.keys);
     if (!level1->capacity) return;
-    if (!bd) k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, hs.org, (float *)hs.dir);
+    if (!bd) k_hit_rays<<<g, 256, 0, stream>>>(S, meta, sorted->capacity, hs.org, hs.dir);
     uint32_t log2G = 0;
     while ((1u << log2G) < (uint32_t)bundle) ++log2G;
     const uint32_t grid = 2048u * 256u / (uint32_t)hit_block;   // the same number of waves
@@ -492,15 +500,15 @@ void hit_pairs_launch(const crsh_rays *sorted, const float4 *tri, const hit_slot
     if (bd)
         k_hit<true, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                            level1->capacity, (uint32_t)bundle, log2G, hs.keys, meta,
-                                                           hs.slots, scene->m, 0u, bd->node_info, 0.0f);
+                                                           hs.slots, scene->m, 0u, *bd, 0.0f);
     else if (packed)
         k_hit<false, true><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, nullptr, level1->capacity,
                                                            (uint32_t)bundle, log2G, hits->tkey, meta, hs.slots,
-                                                           scene->m, tri_base, nullptr, t_min);
+                                                           scene->m, tri_base, batch_dev{}, t_min);
     else
         k_hit<false, false><<<grid, hit_block, 0, stream>>>(hs.org, hs.dir, tri, level1->tri, level1->node,
                                                             level1->capacity, (uint32_t)bundle, log2G, hits->tkey,
-                                                            meta, hs.slots, scene->m, 0u, nullptr, t_min);
+                                                            meta, hs.slots, scene->m, 0u, batch_dev{}, t_min);
 }
 
 void hit_masked_launch(const crsh_rays *sorted, const float4 *tri, const hit_slots_ws &hs, const crsh_pairs *level2,
