@@ -356,6 +356,7 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     const uint32_t offk = meta->level_off[parent_level - 2];
     const uint32_t offp = meta->level_off[parent_level - 1];
     const uint32_t np = meta->level_cnt[parent_level - 1];
+    const uint32_t F16 = F * 16u, nk16 = nk * 16u;
     const uint32_t l = lane_id();
     // wave indices, made scalar so that the addresses built from them are
     // scalar arithmetic
@@ -393,7 +394,11 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     // loads of every step count alike where the compiler places its waits
     auto load_pair = [&](uint64_t step, uint32_t &tri, uint32_t &par) {
         const uint64_t q0 = (step * COUNT_TPS + half) * LEVEL_TILE;
-        const uint32_t nq = (uint32_t)(q0 < nin ? min(nin - q0, (uint64_t)LEVEL_TILE) : 0u);
+        // pairs of the tile: min(nin - q0, LEVEL_TILE), 0 past the end, in
+        // 32-bit scalar operations (both below 2^63)
+        const uint64_t left = nin - q0;
+        const uint32_t lhi = (uint32_t)(left >> 32), llo = (uint32_t)left;
+        const uint32_t nq = lhi == 0u ? min(llo, (uint32_t)LEVEL_TILE) : (lhi >> 31 ? 0u : (uint32_t)LEVEL_TILE);
         const __amdgpu_buffer_rsrc_t rt = make_rsrc(in.tri + q0, (uint64_t)nq * 4u);
         const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(rt, own * 4u, 0, 0);
         if constexpr (PACKED) {
@@ -412,17 +417,18 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     // nk), byte offsets into the staged run (node indices stay below 2^28:
     // 32-bit byte offsets into the node arrays)
     auto children = [&](uint32_t par, uint32_t &first16, uint32_t &n16) {
-        uint32_t first, cnt;
         if constexpr (BATCH) {
             const bool ok = par < np;
-            first = ok ? bd.node_first[offp + par] : 0u;
-            cnt = ok ? bd.node_info[offp + par] & INFO_COUNT_MASK : 0u;
+            const uint32_t first = ok ? bd.node_first[offp + par] : 0u;
+            const uint32_t cnt = ok ? bd.node_info[offp + par] & INFO_COUNT_MASK : 0u;
+            first16 = first < nk ? first * 16u : 0u;
+            n16 = first < nk ? (min(first + cnt, nk) - first) * 16u : 0u;
         } else {
-            first = par != NONE ? par * F : 0u;
-            cnt = par != NONE ? F : 0u;
+            // a parent below np has its first child below nk; F16, nk16:
+            // F and nk times 16 (scalar); first16 of no parent is never read
+            first16 = par * F16;
+            n16 = par < np ? min(F16, nk16 - first16) : 0u;
         }
-        first16 = first < nk ? first * 16u : 0u;
-        n16 = first < nk ? (min(first + cnt, nk) - first) * 16u : 0u;
     };
     // two-stage prefetch: the sphere (and batch: the child range) of the
     // next step and the pair of the step after it are in flight while a
@@ -440,7 +446,10 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
     // places in the loop then count only the loop's own memory operations
     // (not every store of the previous step)
     __builtin_amdgcn_s_waitcnt(0x0F70);     // vmcnt(0)
-    for (uint64_t step = blockIdx.x; step < nsteps; step += gridDim.x, parity ^= 1u) {
+    // a 32-bit step index (steps stay far below 2^31: 512 pairs a step), so
+    // the loop's bookkeeping is scalar arithmetic
+    const uint32_t nsteps32 = (uint32_t)min(nsteps, (uint64_t)0x7FFFFFFFu);
+    for (uint32_t step = blockIdx.x; step < nsteps32; step += gridDim.x, parity ^= 1u) {
         const uint64_t tile = step * COUNT_TPS + half;
         // this wave's slice-0 word of the tile's pass masks (scalar)
         uint2 *const mrow = (uint2 *)S.mask + (tile * LEVEL_TILE + tw * PW) * NF / 64;
@@ -500,7 +509,7 @@ __global__ __launch_bounds__(COUNT_THREADS) void k_level_count_lanes(int32_t par
         }
         sp_n = tsph[tri_nn < m ? tri_nn : 0u];
         children(par_nn, first_n, n_n);
-        load_pair(step + 2 * (uint64_t)gridDim.x, tri_nn, par_nn);
+        load_pair(step + 2u * gridDim.x, tri_nn, par_nn);
         uint32_t c = 0;
         // slices in groups of K: every node read of a group is issued before
         // its first test, and the test has no branch to sink them into.
